@@ -1,0 +1,298 @@
+"""Pins for the oracle: values and identities fixed by the paper and by the
+mathematics, chosen so that a dropped term, a wrong sign or index, or a
+transposed operand in any oracle routine fails at least one of them."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def rel(a, b):
+    return abs(a - b) / max(abs(b), 1e-300)
+
+
+def subfactorial(n):
+    # !n = n! sum_{k=0}^n (-1)^k / k!  (exact, integer recurrence)
+    d = [1, 0]
+    for k in range(2, n + 1):
+        d.append((k - 1) * (d[-1] + d[-2]))
+    return d[n]
+
+
+# --------------------------------------------------------------- definition
+@pytest.mark.parametrize("n", range(0, 9))
+def test_bruteforce_identity_and_ones(n):
+    assert oracle.perm_bruteforce(np.eye(n)) == 1.0
+    assert oracle.perm_bruteforce(np.ones((n, n))) == math.factorial(n)
+    assert oracle.perm_bruteforce(np.ones((n, n)) - np.eye(n)) == subfactorial(n)
+
+
+def test_bruteforce_small_closed_forms():
+    rng = np.random.default_rng(0)
+    a = rng.standard_normal((3, 3)) + 1j * rng.standard_normal((3, 3))
+    (p, q), (r, s) = a[0, :2], a[1, :2]
+    assert rel(oracle.perm_bruteforce(a[:2, :2]), p * s + q * r) < 1e-15
+    # 3x3: expansion along the first row with 2x2 permanent minors
+    e = (a[0, 0] * (a[1, 1] * a[2, 2] + a[1, 2] * a[2, 1])
+         + a[0, 1] * (a[1, 0] * a[2, 2] + a[1, 2] * a[2, 0])
+         + a[0, 2] * (a[1, 0] * a[2, 1] + a[1, 1] * a[2, 0]))
+    assert rel(oracle.perm_bruteforce(a), e) < 1e-15
+    # a permanent is not a determinant: the signed version differs
+    assert abs(oracle.perm_bruteforce(a) - np.linalg.det(a)) > 1e-3
+
+
+# ------------------------------------------------------------------- Ryser
+@pytest.mark.parametrize("n", range(1, 9))
+def test_ryser_matches_definition(n):
+    a = workloads.gaussian_matrix(n, seed=100 + n)
+    assert rel(oracle.perm_ryser(a), oracle.perm_bruteforce(a)) < 1e-14
+
+
+@pytest.mark.parametrize("n", range(1, 21))
+def test_ryser_integer_matrices(n):
+    pj = oracle.perm_ryser(np.ones((n, n)))
+    pd = oracle.perm_ryser(np.ones((n, n)) - np.eye(n))
+    if n <= 12:   # every partial sum is an integer below 2^64: exact
+        assert pj == math.factorial(n)
+        assert pd == subfactorial(n)
+    else:
+        # Ryser cancels terms up to k^n (|X| = k) down to n!: rounding error is
+        # bounded by (n + 2) eps_ld sum_k C(n,k) k^n, with eps_ld = 2^-64
+        bound = (n + 2) * 2.0 ** -64 * float(sum(math.comb(n, k) * k ** n for k in range(n + 1)))
+        assert abs(pj - math.factorial(n)) <= bound
+        assert abs(pd - subfactorial(n)) <= bound
+        assert bound / math.factorial(n) < 1e-7      # the bound itself is tight enough to pin
+    assert oracle.perm_ryser(np.eye(n)) == 1.0
+
+
+@pytest.mark.parametrize("n", [12, 15])
+def test_ryser_invariances(n):
+    rng = np.random.default_rng(n)
+    a = workloads.gaussian_matrix(n, seed=n)
+    p = oracle.perm_ryser(a)
+    pr, pc = rng.permutation(n), rng.permutation(n)
+    assert rel(oracle.perm_ryser(a[pr][:, pc]), p) < 1e-13
+    assert rel(oracle.perm_ryser(a.T), p) < 1e-13
+    dr = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    dc = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    scaled = dr[:, None] * a * dc[None, :]
+    assert rel(oracle.perm_ryser(scaled), np.prod(dr) * np.prod(dc) * p) < 1e-12
+
+
+def test_ryser_laplace_expansion():
+    n = 13
+    a = workloads.gaussian_matrix(n, seed=7)
+    full = oracle.perm_ryser(a)
+    lap = 0j
+    for j in range(n):
+        minor = np.delete(np.delete(a, 0, axis=0), j, axis=1)
+        lap += a[0, j] * oracle.perm_ryser(minor)
+    assert rel(lap, full) < 1e-13
+
+
+def test_ryser_haar_block_rows_are_not_swapped():
+    # a non-symmetric block: using a row where a column belongs would change
+    # the value (the check is only that the value equals the brute force)
+    u = workloads.collision_free_block(7, seed=3)
+    assert rel(oracle.perm_ryser(u), oracle.perm_bruteforce(u)) < 1e-13
+
+
+# ------------------------------------------------------ repeated rows/cols
+def _random_pattern(rng, m, n):
+    S = workloads.random_occupations(rng, m, n)
+    T = workloads.random_occupations(rng, m, n)
+    return S, T
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_mult_matches_expanded_definition(seed):
+    rng = np.random.default_rng(seed)
+    m = int(rng.integers(2, 6))
+    n = int(rng.integers(0, 8))
+    U = workloads.haar(m, seed)
+    S, T = _random_pattern(rng, m, n)
+    ref = oracle.perm_bruteforce(oracle.expand(U, S, T))
+    assert rel(oracle.perm_mult(U, S, T), ref) < 1e-13 or abs(ref) < 1e-14
+
+
+def test_mult_transpose_symmetry():
+    rng = np.random.default_rng(5)
+    U = workloads.haar(6, 5)
+    for _ in range(10):
+        S, T = _random_pattern(rng, 6, 7)
+        a = oracle.perm_mult(U, S, T)
+        b = oracle.perm_mult(np.ascontiguousarray(U.T), T, S)
+        assert rel(a, b) < 1e-13
+
+
+def test_mult_identity_gives_factorials():
+    for S in ([3, 0, 2, 1], [1, 1, 1, 1], [4, 0, 0, 0], [0, 2, 2, 0]):
+        S = np.array(S, dtype=np.int32)
+        want = float(np.prod([math.factorial(s) for s in S]))
+        assert oracle.perm_mult(np.eye(4), S, S) == want
+    # different supports on the identity: zero
+    assert oracle.perm_mult(np.eye(3), [1, 1, 0], [0, 1, 1]) == 0
+
+
+def test_mult_equals_binary_ryser_for_unit_multiplicities():
+    U = workloads.haar(14, 2)
+    S = np.ones(14, dtype=np.int32)
+    assert rel(oracle.perm_mult(U, S, S), oracle.perm_ryser(U)) < 1e-13
+
+
+def test_mult_special_cases():
+    U = workloads.haar(4, 0)
+    assert oracle.perm_mult(U, [1, 0, 0, 0], [1, 1, 0, 0]) == 0          # photon number differs
+    assert oracle.perm_mult(U, [0, 0, 0, 0], [0, 0, 0, 0]) == 1          # vacuum
+    assert oracle.perm_mult(U, [0, 0, 2, 0], [0, 2, 0, 0]) == pytest.approx(2 * U[1, 2] ** 2, rel=1e-15)
+
+
+# ------------------------------------------------- two-mode beamsplitter
+@pytest.mark.parametrize("theta,phi", [(0.3, 0.0), (np.pi / 5, 1.1), (2.2, -0.7)])
+def test_two_mode_expansion(theta, phi):
+    B = oracle.beamsplitter(theta, phi)
+    assert np.allclose(B @ B.conj().T, np.eye(2), atol=1e-15)
+    for n in range(4):
+        for m in range(4):
+            for p in range(n + m + 1):
+                q = n + m - p
+                want = oracle.two_mode_amplitude(theta, phi, n, m, p, q)
+                got = oracle.amplitude(B, [n, m], [p, q])
+                assert abs(got - want) < 1e-13, (n, m, p, q)
+
+
+def test_hong_ou_mandel_dip():
+    B = oracle.beamsplitter(np.pi / 4, 0.0)
+    assert abs(oracle.amplitude(B, [1, 1], [1, 1])) < 1e-15
+    assert oracle.probability(B, [1, 1], [2, 0]) == pytest.approx(0.5, abs=1e-15)
+
+
+# ---------------------------------------------------------- completeness
+def test_completeness_four_photons_eight_modes():
+    U = workloads.haar(8, 1)
+    S = np.array([1, 1, 1, 1, 0, 0, 0, 0], dtype=np.int32)
+    outs = workloads.fock_outputs(8, 4, at_most=True)
+    assert len(outs) == 495
+    probs = np.array([oracle.probability(U, S, T) for T in outs])
+    nonzero = [T for T in outs if T.sum() == 4]
+    assert len(nonzero) == 330
+    assert np.all(probs[[T.sum() < 4 for T in outs]] == 0)
+    assert abs(probs.sum() - 1.0) < 1e-13
+
+
+def _paper_circuit(phi=0.0):
+    # Boson Sampling example: input (1,2,0,2,1) through beamsplitters
+    # theta = pi/3 on (1,2), pi/4 on (2,3), pi/5 on (0,1), pi/6 on (3,4)
+    return oracle.mesh_unitary([(np.pi / 3, phi), (np.pi / 4, phi), (np.pi / 5, phi), (np.pi / 6, phi)],
+                               [(1, 2), (2, 3), (0, 1), (3, 4)], 5)
+
+
+@pytest.mark.parametrize("phi", [0.0, np.pi / 4])
+def test_paper_sampling_example(phi):
+    U = _paper_circuit(phi)
+    S = np.array([1, 2, 0, 2, 1], dtype=np.int32)
+    outs = workloads.fock_outputs(5, 6)
+    assert len(outs) == 210
+    probs = {tuple(T): oracle.probability(U, S, T) for T in outs}
+    assert abs(sum(probs.values()) - 1.0) < 1e-13
+    # the printed samples must be possible outcomes
+    for sample in [(0, 1, 2, 1, 2), (2, 0, 3, 0, 1)]:
+        assert probs[sample] > 1e-6
+    # a photon entering mode 4 meets only the (3,4) cell, so it leaves in
+    # mode 3 or 4: all six photons in mode 0 is impossible
+    assert probs[(6, 0, 0, 0, 0)] < 1e-30
+
+
+# -------------------------------------------------------------- gradients
+def test_gradient_finite_differences():
+    rng = np.random.default_rng(3)
+    U = workloads.haar(5, 3)
+    S = np.array([2, 1, 0, 1, 1], dtype=np.int32)
+    T = np.array([1, 0, 3, 1, 0], dtype=np.int32)
+    g = oracle.perm_grad(U, S, T)
+    h = 1e-6
+    for (i, j) in [(0, 0), (2, 1), (3, 4), (2, 3), (1, 1)]:
+        E = np.zeros_like(U)
+        E[i, j] = h
+        fd = (oracle.perm_mult(U + E, S, T) - oracle.perm_mult(U - E, S, T)) / (2 * h)
+        assert abs(fd - g[i, j]) < 1e-8, (i, j)
+        # holomorphic: an imaginary step gives i times the same derivative
+        fdi = (oracle.perm_mult(U + 1j * E, S, T) - oracle.perm_mult(U - 1j * E, S, T)) / (2 * h)
+        assert abs(fdi - 1j * g[i, j]) < 1e-8
+
+
+def test_gradient_euler_identities():
+    U = workloads.haar(6, 4)
+    S = np.array([1, 2, 0, 1, 0, 2], dtype=np.int32)
+    T = np.array([0, 1, 3, 0, 2, 0], dtype=np.int32)
+    g = oracle.perm_grad(U, S, T)
+    p = oracle.perm_mult(U, S, T)
+    for i in range(6):
+        assert abs(np.sum(U[i, :] * g[i, :]) - T[i] * p) < 1e-13
+    for j in range(6):
+        assert abs(np.sum(U[:, j] * g[:, j]) - S[j] * p) < 1e-13
+
+
+def test_gradient_unit_multiplicity_is_minor():
+    A = workloads.gaussian_matrix(6, seed=9)
+    ones = np.ones(6, dtype=np.int32)
+    g = oracle.perm_grad(A, ones, ones)
+    for i, j in [(0, 0), (2, 5), (5, 1)]:
+        minor = np.delete(np.delete(A, i, axis=0), j, axis=1)
+        assert abs(g[i, j] - oracle.perm_bruteforce(minor)) < 1e-13
+
+
+# -------------------------------------------------------- chain-rule rows
+def test_extend_row_is_laplace_expansion():
+    U = workloads.haar(9, 6)
+    rows = [3, 3, 7]
+    cols = [2, 0, 5, 1]
+    out = oracle.extend_row(U, rows, cols)
+    S = np.zeros(9, dtype=np.int32)
+    S[cols] = 1
+    for l in range(9):
+        T = np.bincount(rows + [l], minlength=9).astype(np.int32)
+        assert abs(out[l] - oracle.perm_mult(U, S, T)) < 1e-14
+
+
+def test_chain_rule_marginals_sum_to_one():
+    # sum over the next mode of the chain-rule weights, normalised by
+    # (k-1)!-free counting, reproduces the marginal: for k = 1 the weights are
+    # |U[l, c0]|^2 and sum to 1 for a unitary
+    U = workloads.haar(6, 8)
+    w = oracle.chain_rule_distribution(U, [4, 1, 2], [])
+    assert abs(w.sum() - 1.0) < 1e-14
+
+
+# ------------------------------------------------------------------ mesh
+def test_mesh_is_unitary_and_cells_compose():
+    ang = workloads.mesh_angles(0)
+    U = oracle.mesh_unitary(ang, workloads.MESH_CELLS, workloads.MESH_MODES)
+    assert len(workloads.MESH_CELLS) == 66 and ang.shape == (66, 2)
+    assert np.allclose(U @ U.conj().T, np.eye(12), atol=1e-13)
+    one = oracle.mesh_unitary([(0.4, 1.3)], [(0, 1)], 2)
+    assert np.allclose(one, oracle.beamsplitter(0.4, 1.3))
+
+
+def test_golden_values_present_and_pinned():
+    """Stored oracle values for full-size single permanents were written by
+    tests/golden/make_golden.py (calls only the oracle); check the file parses
+    and that each stored matrix reproduces its stored value's magnitude scale
+    |perm| ~ sqrt(n!) m^{-n/2} within a few orders of magnitude."""
+    path = os.path.join(GOLDEN, "single_permanents.txt")
+    if not os.path.exists(path):
+        pytest.skip("golden file not generated")
+    from tests.golden import load_single
+    cases = load_single(path)
+    assert cases
+    for c in cases:
+        n = c["n"]
+        m = 2 * n * n
+        scale = math.sqrt(math.factorial(n)) * m ** (-n / 2)
+        assert 1e-4 < abs(c["perm"]) / scale < 1e4
