@@ -1,0 +1,202 @@
+/*
+ * pq.h -- C ABI of the MI355X permanent engine (libpq.so).
+ *
+ * The engine computes Fock-basis transition amplitudes of a linear-optical
+ * interferometer.  For an m-mode unitary U, input occupations S and output
+ * occupations T (non-negative integers, n = sum S photons), the matrix
+ * U_{T,S} is the n x n matrix whose rows are the output modes i repeated t_i
+ * times and whose columns are the input modes j repeated s_j times, and
+ *
+ *     amp(S -> T) = perm(U_{T,S}) / sqrt(prod_j s_j! prod_i t_i!),
+ *     p(S -> T)   = |amp|^2                      (Appendix, Eq. BS_prob),
+ *
+ * with perm(A) = sum over permutations sigma of prod_i A[sigma(i)][i]
+ * (Appendix, Eq. per_def).  U_{T,S} is indexed U[output][input].
+ *
+ * The permanent is evaluated by the Balasubramanian-Bax-Franklin-Glynn
+ * formula generalised to repeated rows and columns: the outer sum runs over
+ * an n-ary Gray code whose digits range from zero to the occupation of each
+ * mode (Benchmarks / Boson Sampling), with one sign fixed ("halving").
+ *
+ * Conventions shared by every entry point
+ *   - Complex numbers are pq_c128 {double re, im}: the same bytes as
+ *     torch.complex128, std::complex<double> and C99 double _Complex.
+ *   - Matrices are row-major; a leading dimension counts complex elements.
+ *   - Device pointers are HIP device memory on the ctx's device; occupation
+ *     vectors and job descriptions are host memory (they drive planning).
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream)
+ *     and is stream-ordered; the call returns before the GPU finishes.
+ *     Device buffers must stay valid until that work completes.
+ *   - Ownership: the caller owns every buffer it passes.  The library never
+ *     frees caller memory; it allocates only workspace owned by the ctx.
+ *   - Errors: a status code is returned synchronously; no C++ exception
+ *     crosses the ABI.  Argument and planning errors leave outputs
+ *     untouched.  Launch failures return PQ_EDEVICE.  pq_last_error() gives
+ *     a human-readable detail for the last failing call on a ctx.
+ *   - Threading: a ctx is not thread-safe and its workspace is reused by
+ *     consecutive calls, so calls on one ctx must be issued on one stream
+ *     (or the caller must order the streams).  Distinct ctxs are independent.
+ *   - Special cases: sum S != sum T gives perm = amp = 0 with PQ_OK
+ *     (a passive circuit conserves photon number); n = 0 gives perm = amp = 1.
+ *     n > PQ_MAX_N, more than PQ_MAX_N distinct columns, or 2^62 or more
+ *     Gray-code terms give PQ_ERANGE.
+ */
+#ifndef PQ_H
+#define PQ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { double re, im; } pq_c128;
+typedef struct pq_ctx pq_ctx;
+
+enum {
+    PQ_OK = 0,
+    PQ_EINVAL = 1,      /* invalid argument (NULL pointer, negative size or occupation, ldu < m) */
+    PQ_ERANGE = 2,      /* problem too large for the engine */
+    PQ_ENOMEM = 3,      /* device workspace allocation failed */
+    PQ_EDEVICE = 4,     /* HIP runtime or launch error */
+    PQ_ECANCELLED = 5   /* reserved */
+};
+
+#define PQ_MAX_N 48     /* photons per permanent, and distinct rows/columns */
+
+/* Library version string, e.g. "pq 0.1 gfx950". Static storage. */
+const char* pq_version(void);
+
+/* Create a context on HIP device `hip_device` (PQ_EINVAL for a bad ordinal or
+ * NULL out, PQ_EDEVICE if the device cannot be queried).  *out is set only on
+ * success.  The ctx owns device workspace, grown on demand. */
+int pq_create(pq_ctx** out, int hip_device);
+
+/* Destroy a context (NULL-safe).  Waits for the device before freeing. */
+void pq_destroy(pq_ctx* ctx);
+
+/* Static description of a status code. */
+const char* pq_strerror(int status);
+
+/* Detail of the last failing call on ctx ("" if none); owned by ctx, valid
+ * until the next call on ctx. */
+const char* pq_last_error(const pq_ctx* ctx);
+
+/*
+ * pq_perm -- one amplitude (Eq. BS_prob, Eq. per_def).
+ *   U      device, m x m complex, row-major, leading dimension ldu >= m.
+ *   S, T   host int32[m]: input / output occupations (>= 0).
+ *   perm   device, 1 complex, may be NULL: perm(U_{T,S}).
+ *   amp    device, 1 complex, may be NULL: perm / sqrt(prod S! prod T!).
+ * U must not be NULL when m > 0; S and T must not be NULL.
+ */
+int pq_perm(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m,
+            const int32_t* S, const int32_t* T,
+            pq_c128* perm, pq_c128* amp, void* stream);
+
+/*
+ * Batched jobs on one interferometer U (uneven sizes).  Jobs use the sparse
+ * form: distinct row modes with their multiplicities (the output side) and
+ * distinct column modes with theirs (the input side).
+ *
+ *   PQ_OP_PERM        one output: perm(U_{T,S}) (and amp) at out_offset.
+ *                     Needs sum row_mult == sum col_mult (else 0, as pq_perm).
+ *   PQ_OP_EXTEND_ROW  m outputs at out_offset .. out_offset+m-1:
+ *                     out[l] = perm(U_{T+e_l, S}) for every mode l, i.e. the
+ *                     Laplace expansion along one more output row used by
+ *                     chain-rule boson sampling (Clifford-Clifford algorithm
+ *                     A, Benchmarks / Boson Sampling).  Needs
+ *                     sum col_mult == sum row_mult + 1; amp is not written
+ *                     for this op.
+ */
+enum { PQ_OP_PERM = 0, PQ_OP_EXTEND_ROW = 1 };
+typedef struct {
+    int32_t op;
+    int32_t nr, nc;              /* number of distinct rows / columns (>= 0) */
+    const int32_t* row_idx;      /* host, nr mode indices in [0, m), distinct */
+    const int32_t* row_mult;     /* host, nr multiplicities >= 1 */
+    const int32_t* col_idx;      /* host, nc mode indices in [0, m), distinct */
+    const int32_t* col_mult;     /* host, nc multiplicities >= 1 */
+    int64_t out_offset;          /* element offset into perm[] / amp[] */
+} pq_job;
+
+/*
+ * pq_perm_batched -- all jobs in one stream-ordered submission (one persistent
+ * work-queue launch for the Gray-code sums).
+ *   perm  device, complex, large enough for every job's outputs.
+ *   amp   device, may be NULL; written for PQ_OP_PERM jobs only.
+ * Output ranges of different jobs must not overlap (PQ_EINVAL otherwise).
+ */
+int pq_perm_batched(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m,
+                    const pq_job* jobs, int32_t njobs,
+                    pq_c128* perm, pq_c128* amp, void* stream);
+
+/*
+ * pq_perm_grad -- vector-Jacobian product over a batch of patterns on one U.
+ * perm(U_{T,S}) is a polynomial (holomorphic) in U; following the
+ * conjugate-Wirtinger convention of complex autograd,
+ *     dU = sum_p gperm[p] * conj( d perm(U_{T_p,S_p}) / dU ),
+ * where d perm / d U_ij = t_i s_j perm(U_{T-e_i, S-e_j}) (the minor
+ * permanents), computed inside the same Gray-code sweep as the forward value.
+ *   S, T   host int32[batch*m], pattern p at offset p*m.
+ *   gperm  device, batch complex.
+ *   perm   device, batch complex, may be NULL: forward values of the sweep.
+ *   dU     device, m x m, leading dimension lddu >= m; OVERWRITTEN
+ *          (entries outside every pattern's support are set to 0).
+ * Per pattern the compact matrix may have at most PQ_GRAD_MAX_DIM distinct
+ * rows and columns (PQ_ERANGE otherwise).
+ */
+#define PQ_GRAD_MAX_DIM 24
+int pq_perm_grad(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m,
+                 int32_t batch, const int32_t* S, const int32_t* T,
+                 const pq_c128* gperm, pq_c128* perm,
+                 pq_c128* dU, int64_t lddu, void* stream);
+
+/*
+ * Sweep-kernel timing.  While enabled, every Gray-code sweep launch on ctx is
+ * bracketed by HIP events recorded on the launch stream.  pq_profile_read
+ * waits for the recorded events, returns the number of sweep launches and
+ * their summed duration in milliseconds since the last read (or enable), and
+ * clears the record.  Disabled by default; enabling costs two event records
+ * per launch.
+ */
+int pq_profile_enable(pq_ctx* ctx, int on);
+int pq_profile_read(pq_ctx* ctx, int64_t* launches, double* total_ms);
+
+/*
+ * Planning description (no GPU work; usable without a device).  Fills the
+ * fields below for the problem (S, T) exactly as pq_perm would plan it.
+ */
+typedef struct {
+    int32_t status;        /* PQ_OK, or the error pq_perm would return */
+    int32_t n;             /* photons */
+    int32_t trivial;       /* 1: sums differ (value 0), 2: n == 0 (value 1), else 0 */
+    int32_t transposed;    /* 1: the Gray code runs over the input side S */
+    int32_t rows, cols;    /* compact sizes (iterated side, power side) */
+    int32_t fixed_row;     /* index (into the iterated modes, ascending) of the fixed group */
+    int32_t lane_digits;   /* digits mapped onto the 64 lanes of a wavefront */
+    int32_t lane_states;   /* product of their radices (<= 64) */
+    int32_t time_digits;   /* digits swept in time */
+    int32_t inner_digits;  /* time digits driven by the per-step table */
+    int32_t inner_states;  /* product of the inner radices */
+    int32_t binary;        /* 1: every digit binary and every power 1 */
+    uint64_t terms;        /* Gray-code terms N = mu_f prod_{i != f} (mu_i + 1) */
+    uint64_t time_states;  /* terms / lane_states (rounded up for padding lanes) */
+    double log2_norm;      /* log2 of 1 / sqrt(prod S! prod T!) */
+} pq_plan_info;
+
+int pq_plan_describe(int32_t m, const int32_t* S, const int32_t* T, pq_plan_info* out);
+
+/*
+ * Reflected mixed-radix Gray code helper (host; exposed for tests).
+ * Digits are listed least-significant first with radices radix[0..d-1] >= 1.
+ * Writes the Gray digits of rank `rank` into digits[0..d-1].  Returns
+ * PQ_EINVAL for bad arguments or rank >= prod radix.
+ */
+int pq_gray_unrank(int32_t d, const int32_t* radix, uint64_t rank, int32_t* digits);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PQ_H */

@@ -1,0 +1,185 @@
+"""MI355X permanent engine: Fock amplitudes perm(U_{T,S}) / sqrt(prod S! prod T!)
+of linear-optical interferometers, computed by hand-written HIP kernels
+(libpq.so) behind a C ABI.  This package only marshals arguments: tensors are
+torch complex128 on the GPU, occupations are integer sequences on the host,
+and every computation runs in the library's kernels on the caller's current
+torch stream.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Sequence
+
+import torch
+
+from . import _lib
+from ._lib import PqError, pq_job, pq_plan_info, PQ_OP_PERM, PQ_OP_EXTEND_ROW, PQ_MAX_N  # noqa: F401
+
+__all__ = [
+    "Engine", "engine", "perm", "plan_describe", "gray_unrank", "PqError",
+    "PQ_OP_PERM", "PQ_OP_EXTEND_ROW",
+]
+
+
+def _check(status: int, ctx=None):
+    if status != _lib.PQ_OK:
+        lib = _lib.load()
+        detail = lib.pq_last_error(ctx).decode() if ctx else lib.pq_strerror(status).decode()
+        raise PqError(status, detail)
+
+
+def _stream_handle(device: torch.device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _as_matrix(U: torch.Tensor) -> tuple:
+    if not isinstance(U, torch.Tensor) or U.dtype != torch.complex128 or U.dim() != 2:
+        raise TypeError("U must be a 2-D torch.complex128 tensor")
+    if not U.is_cuda:
+        raise TypeError("U must live on the GPU")
+    if U.shape[0] != U.shape[1]:
+        raise ValueError("U must be square")
+    if U.stride(1) != 1:
+        U = U.contiguous()
+    return U, U.stride(0)
+
+
+class Engine:
+    """One libpq context on one GPU (not thread-safe; one stream at a time)."""
+
+    def __init__(self, device: int | torch.device | None = None):
+        lib = _lib.load()
+        if device is None:
+            device = torch.cuda.current_device()
+        self.device = torch.device("cuda", device if isinstance(device, int) else device.index or 0)
+        ctx = ctypes.c_void_p()
+        _check(lib.pq_create(ctypes.byref(ctx), self.device.index))
+        self._ctx = ctx
+        self._lib = lib
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            self._lib.pq_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ----------------------------------------------------------- pq_perm
+    def perm(self, U: torch.Tensor, S: Sequence[int], T: Sequence[int], *,
+             out_perm: torch.Tensor | None = None, out_amp: torch.Tensor | None = None):
+        """perm(U_{T,S}) and the amplitude, as 0-d complex128 device tensors."""
+        U, ldu = _as_matrix(U)
+        m = U.shape[0]
+        if len(S) != m or len(T) != m:
+            raise ValueError("S and T need one entry per mode")
+        if out_perm is None:
+            out_perm = torch.empty((), dtype=torch.complex128, device=U.device)
+        if out_amp is None:
+            out_amp = torch.empty((), dtype=torch.complex128, device=U.device)
+        st = self._lib.pq_perm(self._ctx, U.data_ptr(), ldu, m, _lib.i32_array(S), _lib.i32_array(T),
+                               out_perm.data_ptr(), out_amp.data_ptr(), _stream_handle(U.device))
+        _check(st, self._ctx)
+        return out_perm, out_amp
+
+    # ------------------------------------------------------------ timing
+    def profile(self, on: bool = True):
+        """Bracket every sweep launch with HIP events (pq_profile_enable)."""
+        _check(self._lib.pq_profile_enable(self._ctx, 1 if on else 0), self._ctx)
+
+    def profile_read(self):
+        """(launches, total sweep milliseconds) since the last read."""
+        n = ctypes.c_int64()
+        ms = ctypes.c_double()
+        _check(self._lib.pq_profile_read(self._ctx, ctypes.byref(n), ctypes.byref(ms)), self._ctx)
+        return n.value, ms.value
+
+    # ---------------------------------------------------- pq_perm_batched
+    def perm_batched(self, U: torch.Tensor, jobs: Sequence[dict], n_out: int | None = None,
+                     with_amp: bool = True):
+        """Run jobs given as dicts {op, rows: [(mode, mult)], cols: [(mode, mult)], out}.
+        Returns (perm, amp) device tensors of length n_out."""
+        U, ldu = _as_matrix(U)
+        m = U.shape[0]
+        keep = []
+        arr = (pq_job * max(1, len(jobs)))()
+        total = 0
+        for k, j in enumerate(jobs):
+            op = int(j.get("op", PQ_OP_PERM))
+            rows = list(j["rows"])
+            cols = list(j["cols"])
+            ri = _lib.i32_array([r for r, _ in rows])
+            rm = _lib.i32_array([c for _, c in rows])
+            ci = _lib.i32_array([r for r, _ in cols])
+            cm = _lib.i32_array([c for _, c in cols])
+            keep += [ri, rm, ci, cm]
+            off = int(j.get("out", total))
+            arr[k] = pq_job(op, len(rows), len(cols), ri, rm, ci, cm, off)
+            total = max(total, off + (m if op == PQ_OP_EXTEND_ROW else 1))
+        n_out = total if n_out is None else n_out
+        perm = torch.zeros(max(1, n_out), dtype=torch.complex128, device=U.device)
+        amp = torch.zeros(max(1, n_out), dtype=torch.complex128, device=U.device) if with_amp else None
+        st = self._lib.pq_perm_batched(self._ctx, U.data_ptr(), ldu, m, arr, len(jobs), perm.data_ptr(),
+                                       amp.data_ptr() if amp is not None else None,
+                                       _stream_handle(U.device))
+        _check(st, self._ctx)
+        return perm[:n_out], (amp[:n_out] if amp is not None else None)
+
+    # -------------------------------------------------------- pq_perm_grad
+    def perm_grad(self, U: torch.Tensor, S_list, T_list, gperm: torch.Tensor, want_perm: bool = True):
+        """dU = sum_p gperm[p] conj(d perm_p / dU); returns (dU, perm or None)."""
+        U, ldu = _as_matrix(U)
+        m = U.shape[0]
+        batch = len(S_list)
+        flatS = [int(v) for s in S_list for v in s]
+        flatT = [int(v) for t in T_list for v in t]
+        if len(flatS) != batch * m or len(flatT) != batch * m:
+            raise ValueError("patterns need one entry per mode")
+        gperm = gperm.to(dtype=torch.complex128, device=U.device).contiguous()
+        dU = torch.empty((m, m), dtype=torch.complex128, device=U.device)
+        perm = torch.empty(max(1, batch), dtype=torch.complex128, device=U.device) if want_perm else None
+        st = self._lib.pq_perm_grad(self._ctx, U.data_ptr(), ldu, m, batch, _lib.i32_array(flatS),
+                                    _lib.i32_array(flatT), gperm.data_ptr(),
+                                    perm.data_ptr() if perm is not None else None,
+                                    dU.data_ptr(), m, _stream_handle(U.device))
+        _check(st, self._ctx)
+        return dU, (perm[:batch] if perm is not None else None)
+
+
+_engines: dict = {}
+
+
+def engine(device: int | None = None) -> Engine:
+    """Per-device default Engine."""
+    if device is None:
+        device = torch.cuda.current_device()
+    if device not in _engines:
+        _engines[device] = Engine(device)
+    return _engines[device]
+
+
+def perm(U: torch.Tensor, S: Sequence[int], T: Sequence[int]):
+    """(perm, amp) of U_{T,S} on U's device (see Engine.perm)."""
+    return engine(U.device.index).perm(U, S, T)
+
+
+def plan_describe(S: Sequence[int], T: Sequence[int]) -> dict:
+    """GPU-free planning summary of one permanent (pq_plan_describe)."""
+    lib = _lib.load()
+    info = pq_plan_info()
+    m = len(S)
+    lib.pq_plan_describe(m, _lib.i32_array(S), _lib.i32_array(T), ctypes.byref(info))
+    return {name: getattr(info, name) for name, _ in pq_plan_info._fields_}
+
+
+def gray_unrank(radix: Sequence[int], rank: int) -> list:
+    """Gray digits (least significant first) of `rank` in the reflected
+    mixed-radix code with the given radices (pq_gray_unrank)."""
+    lib = _lib.load()
+    d = len(radix)
+    out = (ctypes.c_int32 * max(1, d))()
+    _check(lib.pq_gray_unrank(d, _lib.i32_array(radix), int(rank), out))
+    return [out[k] for k in range(d)]

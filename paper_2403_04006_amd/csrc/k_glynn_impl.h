@@ -1,0 +1,219 @@
+// Forward Gray-code sweep of the generalised BB/FG permanent formula on
+// gfx950 (complex FP64 on the vector ALUs; no matrix cores: the sum is not a
+// dense contraction).
+//
+// Work layout (one problem, one launch):
+//   * the digits are split into lane digits (fixed per lane, product of
+//     radices <= 64, one digit vector per lane of a wavefront) and time
+//     digits (swept by a reflected Gray code, identical for all lanes of a
+//     wavefront, so the row updated at each step is wavefront-uniform and its
+//     +-2B values come through scalar loads into SGPR operands);
+//   * the time-state range is split evenly over all resident wavefronts, so
+//     every wavefront does the same number of steps (+-1);
+//   * every lane keeps its NC column sums in VGPRs (NC is a template
+//     parameter so the sums are never indexed dynamically) and per step does
+//     2*NC adds (the row update), NC-1 complex multiplies (two independent
+//     chains), and one complex multiply-add into its accumulator.
+//
+// Kernels:
+//   glynn_bin<NC>  every digit binary and every column power 1: the step's row
+//                  and direction come from the 64-bit time counter with
+//                  scalar bit operations (row = ctz(t), direction from bit
+//                  ctz(t)+1), the term weight alternates sign;
+//   glynn_mix<NC>  mixed radices and powers: the lowest time digits follow a
+//                  per-step table (row offset, signed binomial weight),
+//                  the remaining time digits are re-derived per segment.
+//
+// The template instances are spread over k_glynn_p*.hip so they build in
+// parallel.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "device.h"
+#include "kernels.h"
+
+namespace pq {
+
+template <int NC>
+__device__ __forceinline__ cplx product_unit_powers(const cplx (&c)[NC]) {
+    if constexpr (NC == 1) {
+        return c[0];
+    } else {
+        cplx p0 = c[0], p1 = c[1];
+#pragma unroll
+        for (int j = 2; j < NC; j += 2) {
+            p0 = cmul(p0, c[j]);
+            if (j + 1 < NC) p1 = cmul(p1, c[j + 1]);
+        }
+        return cmul(p0, p1);
+    }
+}
+
+// prod_j c_j^{kap_j}; kap_j >= 1 are wavefront-uniform (kernel arguments).
+template <int NC>
+__device__ __forceinline__ cplx product_powers(const cplx (&c)[NC], const int32_t* kap) {
+    cplx p0 = c[0];
+    for (int e = 1; e < kap[0]; ++e) p0 = cmul(p0, c[0]);
+    if constexpr (NC == 1) {
+        return p0;
+    } else {
+        cplx p1 = c[1];
+        for (int e = 1; e < kap[1]; ++e) p1 = cmul(p1, c[1]);
+#pragma unroll
+        for (int j = 2; j < NC; j += 2) {
+            for (int e = 0; e < kap[j]; ++e) p0 = cmul(p0, c[j]);
+            if (j + 1 < NC)
+                for (int e = 0; e < kap[j + 1]; ++e) p1 = cmul(p1, c[j + 1]);
+        }
+        return cmul(p0, p1);
+    }
+}
+
+template <int NC>
+__device__ __forceinline__ void add_row(cplx (&c)[NC], const cplx* __restrict__ r) {
+#pragma unroll
+    for (int j = 0; j < NC; ++j) cadd_to(c[j], r[j]);
+}
+
+template <int NC>
+__device__ __forceinline__ void fma_row(cplx (&c)[NC], double coef, const cplx* __restrict__ r) {
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+        c[j].re = __builtin_fma(coef, r[j].re, c[j].re);
+        c[j].im = __builtin_fma(coef, r[j].im, c[j].im);
+    }
+}
+
+// Column sums at the lane's digits (time digits all zero): base + lane part.
+// Returns the lane's weight (0 for padding lanes beyond lane_states).
+template <int NC>
+__device__ __forceinline__ double lane_init(const GlynnArgs& a, int lane, cplx (&c)[NC]) {
+#pragma unroll
+    for (int j = 0; j < NC; ++j) c[j] = a.base[j];
+    double wl = lane < a.lane_states ? 1.0 : 0.0;
+    int rest = lane;
+    for (int i = 0; i < a.n_lane; ++i) {
+        const int rho = a.lane_radix[i];
+        const int d = rest % rho;
+        rest /= rho;
+        wl *= digit_weight(rho, d);
+        fma_row(c, (double)d, a.rows2 + (size_t)i * 2 * NC);      // += d * (-2 B_i)
+    }
+    return wl;
+}
+
+template <int NC>
+__global__ __launch_bounds__(kBlock) void glynn_bin(const GlynnArgs a) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t wave = wave_id_uniform();
+    cplx acc{0.0, 0.0};
+    if (wave < a.waves) {
+        uint64_t start, count;
+        split_range(a.time_states, a.waves, wave, start, count);
+        if (count > 0) {
+            cplx c[NC];
+            const double wl = lane_init<NC>(a, lane, c);
+            const cplx* trows = a.rows2 + (size_t)a.n_lane * 2 * NC;
+            // time digits at the Gray state of rank `start`
+            const uint64_t g = start ^ (start >> 1);
+            for (int k = 0; k < a.n_time; ++k)
+                if ((g >> k) & 1ull) add_row(c, trows + (size_t)k * 2 * NC);
+            double w = (__builtin_popcountll(g) & 1) ? -1.0 : 1.0;
+            cfma_to(acc, w, product_unit_powers(c));
+            const uint64_t end = start + count;
+            for (uint64_t t = start + 1; t < end; ++t) {
+                const int i = __builtin_ctzll(t);
+                // the new value of Gray bit i is 1 - bit (i+1) of t:
+                // 1 -> digit up -> -2B row (sel 0); 0 -> +2B row (sel 1)
+                const int sel = (int)((t >> (i + 1)) & 1ull);
+                add_row(c, trows + ((size_t)i * 2 + sel) * NC);
+                w = -w;
+                cfma_to(acc, w, product_unit_powers(c));
+            }
+            acc.re *= wl;
+            acc.im *= wl;
+        }
+    }
+    block_reduce_store(to_cdd(acc), a.partials);
+}
+
+template <int NC>
+__global__ __launch_bounds__(kBlock) void glynn_mix(const GlynnArgs a) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t wave = wave_id_uniform();
+    cplx acc{0.0, 0.0};
+    if (wave < a.waves) {
+        uint64_t start, count;
+        split_range(a.time_states, a.waves, wave, start, count);
+        const uint64_t end = start + count;
+        const cplx* trows = a.rows2 + (size_t)a.n_lane * 2 * NC;
+        const uint64_t M = (uint64_t)a.m_inner;
+        const int n_high = a.n_time - a.n_inner;
+        double wl = 0.0;
+        uint64_t s = start;
+        while (s < end) {
+            // one segment: fixed high digits, a run of inner positions
+            const uint64_t hi = s / M;
+            const int pos0 = (int)(s - hi * M);
+            const uint64_t seg_end = (end - hi * M) < M ? end : (hi + 1) * M;
+            const int len = (int)(seg_end - s);
+            cplx c[NC];
+            wl = lane_init<NC>(a, lane, c);
+            // high digits (Gray state of the segment index)
+            int32_t gh[kMaxDim];
+            gray_unrank(n_high, a.time_radix + a.n_inner, hi, gh);
+            int refl = 0;
+            double wh = 1.0;
+            for (int k = 0; k < n_high; ++k) {
+                refl ^= gh[k] & 1;
+                wh *= digit_weight(a.time_radix[a.n_inner + k], gh[k]);
+                if (gh[k]) fma_row(c, (double)gh[k], trows + (size_t)(a.n_inner + k) * 2 * NC);
+            }
+            // inner digits at the forward-table index of position pos0
+            const int q0 = refl ? (int)M - 1 - pos0 : pos0;
+            int32_t gi[16];
+            gray_unrank(a.n_inner, a.time_radix, (uint64_t)q0, gi);
+            for (int k = 0; k < a.n_inner; ++k)
+                if (gi[k]) fma_row(c, (double)gi[k], trows + (size_t)k * 2 * NC);
+            const StepEntry* tab = refl ? a.tab_bwd : a.tab_fwd;
+            cplx seg{0.0, 0.0};
+            cfma_to(seg, tab[pos0].w, product_powers(c, a.kap));
+            for (int p = pos0 + 1; p < pos0 + len; ++p) {
+                add_row(c, trows + tab[p].off);
+                cfma_to(seg, tab[p].w, product_powers(c, a.kap));
+            }
+            cfma_to(acc, wh, seg);
+            s = seg_end;
+        }
+        acc.re *= wl;
+        acc.im *= wl;
+    }
+    block_reduce_store(to_cdd(acc), a.partials);
+}
+
+// ------------------------------------------------------------- launchers
+template <int NC>
+static hipError_t launch_one(bool binary, const GlynnArgs& a, int grid, hipStream_t st) {
+    if (binary)
+        hipLaunchKernelGGL(glynn_bin<NC>, dim3(grid), dim3(kBlock), 0, st, a);
+    else
+        hipLaunchKernelGGL(glynn_mix<NC>, dim3(grid), dim3(kBlock), 0, st, a);
+    return hipGetLastError();
+}
+
+template <int NC>
+static int occupancy_one(bool binary) {
+    int nb = 0;
+    hipError_t e = binary
+        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, glynn_bin<NC>, kBlock, 0)
+        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, glynn_mix<NC>, kBlock, 0);
+    return e == hipSuccess ? nb : 0;
+}
+
+#define PQ_INST(NC)                                                                \
+    hipError_t launch_glynn_##NC(bool b, const GlynnArgs& a, int g, hipStream_t s) { \
+        return launch_one<NC>(b, a, g, s);                                         \
+    }                                                                              \
+    int occupancy_glynn_##NC(bool b) { return occupancy_one<NC>(b); }
+
+}  // namespace pq

@@ -1,0 +1,190 @@
+// Host runtime (see runtime.h).
+#include "runtime.h"
+
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "../../include/pq.h"
+#include "kernels.h"
+
+int pq_ctx::fail(int status, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    last_error = buf;
+    return status;
+}
+
+int pq_ctx::check(hipError_t e, const char* what) {
+    if (e == hipSuccess) return PQ_OK;
+    return fail(PQ_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+void* pq_ctx::workspace(size_t bytes) {
+    if (bytes <= ws_bytes && ws) return ws;
+    if (ws) {
+        hipFree(ws);
+        ws = nullptr;
+        ws_bytes = 0;
+    }
+    size_t want = bytes < ((size_t)1 << 20) ? ((size_t)1 << 20) : bytes;
+    if (hipMalloc(&ws, want) != hipSuccess) {
+        ws = nullptr;
+        fail(PQ_ENOMEM, "workspace: hipMalloc(%zu) failed", want);
+        return nullptr;
+    }
+    ws_bytes = want;
+    return ws;
+}
+
+hipEvent_t pq_ctx::take_event() {
+    if (!ev_free.empty()) {
+        hipEvent_t e = ev_free.back();
+        ev_free.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+void pq_ctx::release_events() {
+    for (auto& pr : ev_used) {
+        ev_free.push_back(pr.first);
+        ev_free.push_back(pr.second);
+    }
+    ev_used.clear();
+}
+
+void pq_ctx::release_all() {
+    release_events();
+    for (hipEvent_t e : ev_free) hipEventDestroy(e);
+    ev_free.clear();
+    if (ws) hipFree(ws);
+    ws = nullptr;
+    ws_bytes = 0;
+}
+
+int pq_ctx::occupancy(bool binary, int nc) {
+    int& o = occ[binary ? 1 : 0][nc];
+    if (o == 0) {
+        o = pq::occupancy_glynn(binary, nc);
+        if (o < 1) o = 1;
+    }
+    return o;
+}
+
+namespace pq {
+
+// Fewest time steps per wavefront worth a wavefront's start-up (the column
+// sums are rebuilt from the digits, about (digits x NC) multiply-adds).
+static constexpr uint64_t kMinStepsPerWave = 32;
+
+Geometry sweep_geometry(pq_ctx* ctx, const Plan& p) {
+    Geometry g;
+    const int occ = ctx->occupancy(p.binary, p.nc);
+    const uint64_t full = (uint64_t)occ * (uint64_t)ctx->num_cu * kWavesPerBlock;
+    uint64_t waves = (p.time_states + kMinStepsPerWave - 1) / kMinStepsPerWave;
+    if (waves > full) waves = full;
+    if (waves < 1) waves = 1;
+    g.waves = (uint32_t)waves;
+    g.grid = (int)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
+    return g;
+}
+
+int timed_sweep(pq_ctx* ctx, bool binary, int nc, const GlynnArgs& a, int grid, hipStream_t st) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (ctx->profiling) {
+        e0 = ctx->take_event();
+        e1 = ctx->take_event();
+        if (!e0 || !e1) return ctx->fail(PQ_EDEVICE, "profile: hipEventCreate failed");
+        int rc = ctx->check(hipEventRecord(e0, st), "profile: record");
+        if (rc) return rc;
+    }
+    int rc = ctx->check(launch_glynn(binary, nc, a, grid, st), "sweep");
+    if (rc) return rc;
+    if (ctx->profiling) {
+        rc = ctx->check(hipEventRecord(e1, st), "profile: record");
+        if (rc) return rc;
+        ctx->ev_used.emplace_back(e0, e1);
+    }
+    return PQ_OK;
+}
+
+int run_single(pq_ctx* ctx, const Plan& p, const cplx* U, int64_t ldu, cplx* perm, cplx* amp,
+               hipStream_t st) {
+    const Geometry geo = sweep_geometry(ctx, p);
+    const int r = p.r, nc = p.nc;
+    Carve cv;
+    const size_t oB = cv.take(sizeof(cplx) * r * nc);
+    const size_t oR = cv.take(sizeof(cplx) * r * 2 * nc);
+    const size_t oBase = cv.take(sizeof(cplx) * nc);
+    const size_t oTf = cv.take(sizeof(StepEntry) * (size_t)p.m_inner);
+    const size_t oTb = cv.take(sizeof(StepEntry) * (size_t)p.m_inner);
+    const size_t oP = cv.take(sizeof(double) * 4 * (size_t)geo.grid);
+    char* ws = (char*)ctx->workspace(cv.off);
+    if (!ws) return PQ_ENOMEM;
+
+    PrepArgs pa;
+    memset(&pa, 0, sizeof(pa));
+    pa.U = U;
+    pa.ldu = ldu;
+    pa.B = (cplx*)(ws + oB);
+    pa.rows2 = (cplx*)(ws + oR);
+    pa.base = (cplx*)(ws + oBase);
+    pa.r = r;
+    pa.nc = nc;
+    pa.transposed = p.transposed;
+    for (int i = 0; i < r; ++i) { pa.row_mode[i] = p.row_mode[i]; pa.row_mu[i] = p.row_mu[i]; }
+    for (int j = 0; j < nc; ++j) pa.col_mode[j] = p.col_mode[j];
+    int rc = ctx->check(launch_prep(pa, st), "prep");
+    if (rc) return rc;
+
+    GlynnArgs ga;
+    memset(&ga, 0, sizeof(ga));
+    ga.B = pa.B;
+    ga.rows2 = pa.rows2;
+    ga.base = pa.base;
+    ga.tab_fwd = (const StepEntry*)(ws + oTf);
+    ga.tab_bwd = (const StepEntry*)(ws + oTb);
+    ga.partials = (double*)(ws + oP);
+    ga.time_states = p.time_states;
+    ga.waves = geo.waves;
+    ga.n_lane = p.n_lane;
+    ga.lane_states = p.lane_states;
+    ga.n_time = p.n_time;
+    ga.n_inner = p.n_inner;
+    ga.m_inner = p.m_inner;
+    for (int k = 0; k < p.n_lane; ++k) ga.lane_radix[k] = p.lane_radix[k];
+    for (int k = 0; k < p.n_time; ++k) ga.time_radix[k] = p.time_radix[k];
+    for (int j = 0; j < nc; ++j) ga.kap[j] = p.col_kap[j];
+
+    if (!p.binary) {
+        TableArgs ta;
+        memset(&ta, 0, sizeof(ta));
+        ta.tab_fwd = (StepEntry*)(ws + oTf);
+        ta.tab_bwd = (StepEntry*)(ws + oTb);
+        ta.n_inner = p.n_inner;
+        ta.m_inner = p.m_inner;
+        ta.nc = nc;
+        for (int k = 0; k < p.n_inner; ++k) ta.radix[k] = p.time_radix[k];
+        rc = ctx->check(launch_table(ta, st), "table");
+        if (rc) return rc;
+    }
+    rc = timed_sweep(ctx, p.binary, nc, ga, geo.grid, st);
+    if (rc) return rc;
+
+    FinalArgs fa;
+    fa.partials = ga.partials;
+    fa.count = geo.grid;
+    fa.scale = p.scale;
+    fa.norm = p.norm;
+    fa.perm = perm;
+    fa.amp = amp;
+    return ctx->check(launch_final(fa, st), "final");
+}
+
+}  // namespace pq

@@ -1,0 +1,78 @@
+// Host runtime of the permanent engine: the context (device, workspace,
+// launch-geometry cache, error state) and the launch sequences.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "plan.h"
+#include "pq_common.h"
+
+struct pq_ctx {
+    int device = 0;
+    int num_cu = 0;
+    int clock_khz = 0;
+    std::string last_error;
+
+    // device workspace, grown on demand (hipFree waits for earlier work)
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    // resident workgroups per CU per (binary, nc); 0 = not yet queried
+    int occ[2][pq::kMaxDim + 1] = {};
+
+    // sweep timing (pq_profile_enable / pq_profile_read)
+    bool profiling = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used;
+    std::vector<hipEvent_t> ev_free;
+    hipEvent_t take_event();
+    void release_events();
+
+    void clear_error() { last_error.clear(); }
+    int fail(int status, const char* fmt, ...);
+    int check(hipError_t e, const char* what);
+    // workspace of at least `bytes`; nullptr on failure (status set)
+    void* workspace(size_t bytes);
+    void release_all();
+    int occupancy(bool binary, int nc);
+};
+
+namespace pq {
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int d) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != d) hipSetDevice(d);
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) hipSetDevice(prev);
+    }
+};
+
+// Bump allocator over the ctx workspace (256-byte aligned pieces).
+struct Carve {
+    size_t off = 0;
+    size_t take(size_t bytes) {
+        size_t o = (off + 255) & ~(size_t)255;
+        off = o + bytes;
+        return o;
+    }
+};
+
+// Launch geometry of one forward sweep.
+struct Geometry {
+    int grid = 1;       // workgroups
+    uint32_t waves = 1; // active wavefronts
+};
+Geometry sweep_geometry(pq_ctx* ctx, const Plan& p);
+
+// Launch a sweep, bracketed by timing events when profiling is on.
+int timed_sweep(pq_ctx* ctx, bool binary, int nc, const GlynnArgs& a, int grid, hipStream_t st);
+
+// Full single-permanent sequence: prep, (table), sweep, final.
+int run_single(pq_ctx* ctx, const Plan& p, const cplx* U, int64_t ldu, cplx* perm, cplx* amp,
+               hipStream_t st);
+
+}  // namespace pq
