@@ -33,7 +33,7 @@ def main():
             f.write(f"case {n} {seed}\n")
             f.write(f"perm {float(re)!r} {float(im)!r}\n")
             for r in range(n):
-                f.write(" ".join(f"{x.real!r} {x.imag!r}" for x in A[r]) + "\n")
+                f.write(" ".join(f"{float(x.real)!r} {float(x.imag)!r}" for x in A[r]) + "\n")
             f.flush()
     os.replace(out + ".tmp", out)
 
