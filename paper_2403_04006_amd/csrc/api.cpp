@@ -52,6 +52,7 @@ void pq_destroy(pq_ctx* ctx) {
     hipGetDevice(&prev);
     hipSetDevice(ctx->device);
     hipDeviceSynchronize();
+    pq_release_batch_cache(ctx);
     ctx->release_all();
     if (prev >= 0) hipSetDevice(prev);
     delete ctx;

@@ -1,0 +1,246 @@
+// Persistent work-queue kernels of the batched entry point (see batch.h).
+//
+// One kernel per class <OP, NC, BIN, UNIT>: NC is the padded column count
+// (columns beyond a job's own have column sum 1 and zero update rows, so they
+// drop out of every product), BIN selects the binary time-digit walk (row and
+// direction from the 64-bit counter) over the table-driven mixed-radix walk,
+// UNIT the plain products of unit column powers over products with powers.
+//
+//   OP = kOpPerm:    per term  acc += w * prod_j c_j^{kap_j}.
+//   OP = kOpExtend:  per term  acc_j += w * d/dc_j prod_l c_l^{kap_l} for every
+//                    column j (prefix products, then a backward sweep with a
+//                    running suffix product), giving kap_j perm(U_{T, S - e_j});
+//                    the finishing wavefront forms out[l] = sum_j U[l, C_j] L_j
+//                    for every mode l (Laplace expansion along the new row).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "batch.h"
+#include "device.h"
+#include "sweep_common.h"
+
+namespace pq {
+
+// ------------------------------------------------------------ term bodies
+template <int NC, bool UNIT>
+struct PermBody {
+    cplx acc{0.0, 0.0};
+    const int8_t* kap;
+    __device__ __forceinline__ void term(const cplx (&c)[NC], double w) {
+        if constexpr (UNIT) cfma_to(acc, w, product_unit_powers(c));
+        else cfma_to(acc, w, product_powers(c, kap));
+    }
+};
+
+template <int NC, bool UNIT>
+struct ExtendBody {
+    cplx acc[NC];
+    const int8_t* kap;
+    __device__ __forceinline__ ExtendBody() {
+#pragma unroll
+        for (int j = 0; j < NC; ++j) acc[j] = cplx{0.0, 0.0};
+    }
+    __device__ __forceinline__ void term(const cplx (&c)[NC], double w) {
+        if constexpr (UNIT) {
+            // G_j = prod_{l != j} c_l
+            if constexpr (NC == 1) {
+                acc[0].re += w;
+            } else {
+                cplx pre[NC];
+                pre[1] = c[0];
+#pragma unroll
+                for (int j = 2; j < NC; ++j) pre[j] = cmul(pre[j - 1], c[j - 1]);
+                cfma_to(acc[NC - 1], w, pre[NC - 1]);
+                cplx s = c[NC - 1];
+#pragma unroll
+                for (int j = NC - 2; j >= 1; --j) {
+                    cfma_to(acc[j], w, cmul(pre[j], s));
+                    s = cmul(s, c[j]);
+                }
+                cfma_to(acc[0], w, s);
+            }
+        } else {
+            // y_l = c_l^{kap_l}; G_j = kap_j c_j^{kap_j - 1} prod_{l != j} y_l
+            cplx pre[NC];
+            cplx y = c[0];
+            for (int e = 1; e < kap[0]; ++e) y = cmul(y, c[0]);
+            pre[0] = cplx{1.0, 0.0};
+            if constexpr (NC > 1) pre[1] = y;
+#pragma unroll
+            for (int j = 2; j < NC; ++j) {
+                cplx yj = c[j - 1];
+                for (int e = 1; e < kap[j - 1]; ++e) yj = cmul(yj, c[j - 1]);
+                pre[j] = cmul(pre[j - 1], yj);
+            }
+            cplx s{1.0, 0.0};
+#pragma unroll
+            for (int j = NC - 1; j >= 0; --j) {
+                const int k = kap[j];
+                cplx d{(double)k, 0.0};                 // k c_j^{k-1}
+                for (int e = 1; e < k; ++e) d = cmul(d, c[j]);
+                cfma_to(acc[j], w, cmul(cmul(pre[j], s), d));
+                if (j > 0) {
+                    cplx yj = c[j];
+                    for (int e = 1; e < k; ++e) yj = cmul(yj, c[j]);
+                    s = cmul(s, yj);
+                }
+            }
+        }
+    }
+};
+
+// --------------------------------------------------------------- sweeping
+// Sweep time states [start, start+count) of job J for this lane; returns the
+// lane weight (0 for padding lanes).
+template <int NC, bool BIN, class Body>
+__device__ __forceinline__ double sweep_chunk(const BJob& J, const cplx* __restrict__ mat,
+                                              const StepEntry* __restrict__ tabs, int lane,
+                                              uint64_t start, uint64_t count, Body& body) {
+    const cplx* rows2 = mat + (size_t)J.r * NC;
+    const cplx* base = rows2 + (size_t)J.r * 2 * NC;
+    const cplx* trows = rows2 + (size_t)J.n_lane * 2 * NC;
+    cplx c[NC];
+    double wl = lane_init<NC>(base, rows2, J.n_lane, J.lane_states, J.lane_radix, lane, c);
+    if constexpr (BIN) {
+        const uint64_t g = start ^ (start >> 1);
+        for (int k = 0; k < J.n_time; ++k)
+            if ((g >> k) & 1ull) add_row(c, trows + (size_t)k * 2 * NC);
+        double w = (__builtin_popcountll(g) & 1) ? -1.0 : 1.0;
+        body.term(c, w);
+        const uint64_t end = start + count;
+        for (uint64_t t = start + 1; t < end; ++t) {
+            const int i = __builtin_ctzll(t);
+            const int sel = (int)((t >> (i + 1)) & 1ull);
+            add_row(c, trows + ((size_t)i * 2 + sel) * NC);
+            w = -w;
+            body.term(c, w);
+        }
+    } else {
+        const uint64_t M = (uint64_t)J.m_inner;
+        const int n_high = J.n_time - J.n_inner;
+        const StepEntry* tf = tabs + (size_t)J.tab * 2 * kMaxInner;
+        const StepEntry* tb = tf + kMaxInner;
+        const uint64_t end = start + count;
+        uint64_t s = start;
+        bool first = true;
+        while (s < end) {
+            const uint64_t hi = s / M;
+            const int pos0 = (int)(s - hi * M);
+            const uint64_t seg_end = (end - hi * M) < M ? end : (hi + 1) * M;
+            const int len = (int)(seg_end - s);
+            if (!first) wl = lane_init<NC>(base, rows2, J.n_lane, J.lane_states, J.lane_radix, lane, c);
+            first = false;
+            int32_t radix_hi[kMaxDim];
+            for (int k = 0; k < n_high; ++k) radix_hi[k] = J.time_radix[J.n_inner + k];
+            int32_t gh[kMaxDim];
+            gray_unrank(n_high, radix_hi, hi, gh);
+            int refl = 0;
+            double wh = 1.0;
+            for (int k = 0; k < n_high; ++k) {
+                refl ^= gh[k] & 1;
+                wh *= digit_weight(radix_hi[k], gh[k]);
+                if (gh[k]) fma_row(c, (double)gh[k], trows + (size_t)(J.n_inner + k) * 2 * NC);
+            }
+            const int q0 = refl ? (int)M - 1 - pos0 : pos0;
+            int32_t radix_in[16], gi[16];
+            for (int k = 0; k < J.n_inner; ++k) radix_in[k] = J.time_radix[k];
+            gray_unrank(J.n_inner, radix_in, (uint64_t)q0, gi);
+            for (int k = 0; k < J.n_inner; ++k)
+                if (gi[k]) fma_row(c, (double)gi[k], trows + (size_t)k * 2 * NC);
+            const StepEntry* tab = refl ? tb : tf;
+            body.term(c, wh * tab[pos0].w);
+            for (int p = pos0 + 1; p < pos0 + len; ++p) {
+                add_row(c, trows + tab[p].off);
+                body.term(c, wh * tab[p].w);
+            }
+            s = seg_end;
+        }
+    }
+    return wl;
+}
+
+__device__ __forceinline__ unsigned wave_atomic_add(unsigned* p, unsigned v) {
+    unsigned r = 0;
+    if ((threadIdx.x & 63) == 0) r = atomicAdd(p, v);
+    return (unsigned)__builtin_amdgcn_readfirstlane((int)r);
+}
+
+__device__ __forceinline__ cdd load_cdd(const double* p) { return cdd{{p[0], p[1]}, {p[2], p[3]}}; }
+__device__ __forceinline__ void store_cdd(double* p, cdd v) {
+    p[0] = v.re.hi; p[1] = v.re.lo; p[2] = v.im.hi; p[3] = v.im.lo;
+}
+
+template <int OP, int NC, bool BIN, bool UNIT>
+__global__ __launch_bounds__(kBlock) void batch_kernel(const BatchArgs a) {
+    const int lane = threadIdx.x & 63;
+    __shared__ cplx sL[kWavesPerBlock][NC];
+    cplx* L = sL[threadIdx.x >> 6];
+    while (true) {
+        const unsigned ci = wave_atomic_add(a.counter, 1u);
+        if (ci >= (unsigned)a.nchunks) break;
+        const BChunk ch = a.chunks[ci];
+        const BJob& J = a.jobs[ch.job];
+        const cplx* mat = a.mat + J.mat_off;
+        double* slot = a.partials + (size_t)ch.slot * a.slot_doubles;
+        if constexpr (OP == kOpPerm) {
+            PermBody<NC, UNIT> body;
+            body.kap = J.kap;
+            const double wl = sweep_chunk<NC, BIN>(J, mat, a.tabs, lane, ch.start, ch.count, body);
+            cdd v = wave_reduce(to_cdd(cplx{body.acc.re * wl, body.acc.im * wl}));
+            if (lane == 0) store_cdd(slot, v);
+        } else {
+            ExtendBody<NC, UNIT> body;
+            body.kap = J.kap;
+            const double wl = sweep_chunk<NC, BIN>(J, mat, a.tabs, lane, ch.start, ch.count, body);
+#pragma unroll
+            for (int j = 0; j < NC; ++j) {
+                if (j < J.nc) {
+                    cdd v = wave_reduce(to_cdd(cplx{body.acc[j].re * wl, body.acc[j].im * wl}));
+                    if (lane == 0) store_cdd(slot + 4 * j, v);
+                }
+            }
+        }
+        // publish the slot, then take a ticket; the last chunk of the job
+        // finalises it
+        __threadfence();
+        const unsigned t = wave_atomic_add(a.tickets + ch.job, 1u);
+        if (t + 1 != (unsigned)J.nchunks) continue;
+        __threadfence();
+        const double* js = a.partials + (size_t)J.slot_base * a.slot_doubles;
+        if constexpr (OP == kOpPerm) {
+            if (lane == 0) {
+                cdd s = load_cdd(js);
+                for (int k = 1; k < J.nchunks; ++k) s = cdd_add(s, load_cdd(js + (size_t)k * a.slot_doubles));
+                const double re = (s.re.hi + s.re.lo) * J.scale;
+                const double im = (s.im.hi + s.im.lo) * J.scale;
+                a.perm[J.out_offset] = cplx{re, im};
+                if (a.amp) a.amp[J.out_offset] = cplx{re * J.norm, im * J.norm};
+            }
+        } else {
+            for (int j = lane; j < J.nc; j += 64) {
+                cdd s = load_cdd(js + 4 * j);
+                for (int k = 1; k < J.nchunks; ++k) s = cdd_add(s, load_cdd(js + (size_t)k * a.slot_doubles + 4 * j));
+                L[j] = cplx{(s.re.hi + s.re.lo) * J.scale, (s.im.hi + s.im.lo) * J.scale};
+            }
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            const int32_t* cmode = a.idx + J.idx_off + 2 * J.r;
+            for (int l = lane; l < J.m_out; l += 64) {
+                const cplx* Ul = a.U + (size_t)l * (size_t)a.ldu;
+                double re = 0.0, im = 0.0;
+                for (int j = 0; j < J.nc; ++j) {
+                    const cplx u = Ul[cmode[j]];
+                    const cplx v = L[j];
+                    re = __builtin_fma(u.re, v.re, re);
+                    re = __builtin_fma(-u.im, v.im, re);
+                    im = __builtin_fma(u.re, v.im, im);
+                    im = __builtin_fma(u.im, v.re, im);
+                }
+                a.perm[J.out_offset + l] = cplx{re, im};
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+}
+
+}  // namespace pq

@@ -31,76 +31,9 @@
 
 #include "device.h"
 #include "kernels.h"
+#include "sweep_common.h"
 
 namespace pq {
-
-template <int NC>
-__device__ __forceinline__ cplx product_unit_powers(const cplx (&c)[NC]) {
-    if constexpr (NC == 1) {
-        return c[0];
-    } else {
-        cplx p0 = c[0], p1 = c[1];
-#pragma unroll
-        for (int j = 2; j < NC; j += 2) {
-            p0 = cmul(p0, c[j]);
-            if (j + 1 < NC) p1 = cmul(p1, c[j + 1]);
-        }
-        return cmul(p0, p1);
-    }
-}
-
-// prod_j c_j^{kap_j}; kap_j >= 1 are wavefront-uniform (kernel arguments).
-template <int NC>
-__device__ __forceinline__ cplx product_powers(const cplx (&c)[NC], const int32_t* kap) {
-    cplx p0 = c[0];
-    for (int e = 1; e < kap[0]; ++e) p0 = cmul(p0, c[0]);
-    if constexpr (NC == 1) {
-        return p0;
-    } else {
-        cplx p1 = c[1];
-        for (int e = 1; e < kap[1]; ++e) p1 = cmul(p1, c[1]);
-#pragma unroll
-        for (int j = 2; j < NC; j += 2) {
-            for (int e = 0; e < kap[j]; ++e) p0 = cmul(p0, c[j]);
-            if (j + 1 < NC)
-                for (int e = 0; e < kap[j + 1]; ++e) p1 = cmul(p1, c[j + 1]);
-        }
-        return cmul(p0, p1);
-    }
-}
-
-template <int NC>
-__device__ __forceinline__ void add_row(cplx (&c)[NC], const cplx* __restrict__ r) {
-#pragma unroll
-    for (int j = 0; j < NC; ++j) cadd_to(c[j], r[j]);
-}
-
-template <int NC>
-__device__ __forceinline__ void fma_row(cplx (&c)[NC], double coef, const cplx* __restrict__ r) {
-#pragma unroll
-    for (int j = 0; j < NC; ++j) {
-        c[j].re = __builtin_fma(coef, r[j].re, c[j].re);
-        c[j].im = __builtin_fma(coef, r[j].im, c[j].im);
-    }
-}
-
-// Column sums at the lane's digits (time digits all zero): base + lane part.
-// Returns the lane's weight (0 for padding lanes beyond lane_states).
-template <int NC>
-__device__ __forceinline__ double lane_init(const GlynnArgs& a, int lane, cplx (&c)[NC]) {
-#pragma unroll
-    for (int j = 0; j < NC; ++j) c[j] = a.base[j];
-    double wl = lane < a.lane_states ? 1.0 : 0.0;
-    int rest = lane;
-    for (int i = 0; i < a.n_lane; ++i) {
-        const int rho = a.lane_radix[i];
-        const int d = rest % rho;
-        rest /= rho;
-        wl *= digit_weight(rho, d);
-        fma_row(c, (double)d, a.rows2 + (size_t)i * 2 * NC);      // += d * (-2 B_i)
-    }
-    return wl;
-}
 
 template <int NC>
 __global__ __launch_bounds__(kBlock) void glynn_bin(const GlynnArgs a) {

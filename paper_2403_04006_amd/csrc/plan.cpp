@@ -55,7 +55,7 @@ static void choose_lane_digits(int nfree, const int* radix, int* chosen, int& nc
         if (reach[best] >> i & 1ull) chosen[nchosen++] = i;
 }
 
-void plan_sparse(const Side& rows, const Side& cols, bool allow_transpose, Plan& p) {
+void plan_sparse(const Side& rows, const Side& cols, bool allow_transpose, Plan& p, bool extend) {
     p = Plan();
     int nr = 0, nc_ = 0;
     for (int i = 0; i < rows.count; ++i) nr += rows.mult[i];
@@ -66,9 +66,14 @@ void plan_sparse(const Side& rows, const Side& cols, bool allow_transpose, Plan&
     for (int j = 0; j < cols.count; ++j) lg += lgamma((double)cols.mult[j] + 1.0);
     p.log2_norm = -0.5 * lg / log(2.0);
     p.norm = exp2(p.log2_norm);
-    if (nr != nc_) { p.trivial = 1; p.n = nc_; return; }
+    if (extend) {
+        allow_transpose = false;
+        if (nc_ != nr + 1) { p.status = PQ_EINVAL; return; }
+    } else {
+        if (nr != nc_) { p.trivial = 1; p.n = nc_; return; }
+        if (nr == 0) { p.trivial = 2; return; }
+    }
     p.n = nr;
-    if (p.n == 0) { p.trivial = 2; return; }
     if (p.n > PQ_MAX_N || rows.count > kMaxDim || cols.count > kMaxDim) { p.status = PQ_ERANGE; return; }
 
     uint64_t t_rows = 0, t_cols = 0;
@@ -85,7 +90,7 @@ void plan_sparse(const Side& rows, const Side& cols, bool allow_transpose, Plan&
     p.r = it.count;
     p.nc = pw.count;
     for (int j = 0; j < pw.count; ++j) { p.col_mode[j] = pw.mode[j]; p.col_kap[j] = pw.mult[j]; }
-    p.scale = ldexp(1.0, -(p.n - 1));
+    p.scale = p.n > 0 ? ldexp(1.0, -(p.n - 1)) : 1.0;
 
     // radices in ascending-mode order
     int radix[kMaxDim];

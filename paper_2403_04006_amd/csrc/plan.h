@@ -41,8 +41,11 @@ struct Side {
 };
 
 // Plan from the sparse form (rows = output side, cols = input side).
-// `allow_transpose` = false keeps the rows as the iterated side.
-void plan_sparse(const Side& rows, const Side& cols, bool allow_transpose, Plan& p);
+// `allow_transpose` = false keeps the rows as the iterated side.  `extend`
+// plans the row sweep of a Laplace expansion along one more row: the column
+// side then holds one photon more than the row side, the rows are always the
+// iterated side, and n is the row count (zero rows is allowed).
+void plan_sparse(const Side& rows, const Side& cols, bool allow_transpose, Plan& p, bool extend = false);
 
 // Plan from dense occupation vectors of length m (validates them).
 void plan_dense(int m, const int32_t* S, const int32_t* T, Plan& p);

@@ -19,6 +19,8 @@ struct pq_ctx {
     // device workspace, grown on demand (hipFree waits for earlier work)
     void* ws = nullptr;
     size_t ws_bytes = 0;
+    // cached batch plans, device buffers and graphs (batched.cpp)
+    void* batch_cache = nullptr;
     // resident workgroups per CU per (binary, nc); 0 = not yet queried
     int occ[2][pq::kMaxDim + 1] = {};
 
@@ -37,6 +39,8 @@ struct pq_ctx {
     void release_all();
     int occupancy(bool binary, int nc);
 };
+
+void pq_release_batch_cache(pq_ctx* ctx);
 
 namespace pq {
 

@@ -1,0 +1,265 @@
+"""Parity of the batched work-queue path (pq_perm_batched) against the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def rel(a, b):
+    return abs(a - b) / max(abs(b), 1e-300)
+
+
+@pytest.fixture(scope="module")
+def eng():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2403_04006_amd as pq
+    return pq.Engine(0)
+
+
+def dev(U):
+    return torch.from_numpy(np.ascontiguousarray(U, dtype=np.complex128)).cuda()
+
+
+def sparse(v):
+    return [(i, int(c)) for i, c in enumerate(v) if c > 0]
+
+
+def perm_job(S, T, out=None):
+    j = {"op": 0, "rows": sparse(T), "cols": sparse(S)}
+    if out is not None:
+        j["out"] = out
+    return j
+
+
+def test_completeness_batch_495(eng):
+    U = workloads.haar(8, 1)
+    S = [1, 1, 1, 1, 0, 0, 0, 0]
+    outs = workloads.fock_outputs(8, 4, at_most=True)
+    jobs = [perm_job(S, T) for T in outs]
+    perm, amp = eng.perm_batched(dev(U), jobs)
+    amp = amp.cpu().numpy()
+    perm = perm.cpu().numpy()
+    assert abs(np.sum(np.abs(amp) ** 2) - 1.0) < 1e-12
+    for k, T in enumerate(outs):
+        ref = oracle.amplitude(U, S, T)
+        assert abs(amp[k] - ref) < 1e-13
+        if T.sum() < 4:
+            assert perm[k] == 0 and amp[k] == 0
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_uneven_perm_jobs(eng, seed):
+    rng = np.random.default_rng(seed)
+    m = 10
+    U = workloads.haar(m, 200 + seed)
+    jobs, refs = [], []
+    for k in range(40):
+        n = int(rng.integers(0, 16))
+        S = workloads.random_occupations(rng, m, n, cap=4)
+        T = workloads.random_occupations(rng, m, n, cap=4)
+        jobs.append(perm_job(S, T))
+        refs.append((oracle.perm_mult(U, S, T), oracle.amplitude(U, S, T)))
+    perm, amp = eng.perm_batched(dev(U), jobs)
+    perm = perm.cpu().numpy()
+    amp = amp.cpu().numpy()
+    for k, (rp, ra) in enumerate(refs):
+        if abs(rp) < 1e-12:
+            assert abs(perm[k]) < 1e-11
+        else:
+            assert rel(perm[k], rp) < 1e-10, (k, jobs[k])
+            assert rel(amp[k], ra) < 1e-10
+
+
+def test_unit_multiplicity_jobs_all_classes(eng):
+    # one collision-free job per padded column class, sizes 1..24
+    m = 2 * 24 * 24
+    U = workloads.haar(m, 9)
+    jobs, refs = [], []
+    for n in list(range(1, 25)):
+        cols = list(range(n))
+        rows = list(range(24, 24 + n))
+        S = np.zeros(m, np.int32)
+        T = np.zeros(m, np.int32)
+        S[cols] = 1
+        T[rows] = 1
+        jobs.append(perm_job(S, T))
+        refs.append(oracle.perm_ryser(U[np.ix_(rows, cols)]))
+    perm, _ = eng.perm_batched(dev(U), jobs)
+    perm = perm.cpu().numpy()
+    for k, r in enumerate(refs):
+        assert rel(perm[k], r) < (1e-10 if k < 20 else 1e-8), k
+
+
+def extend_job(rows, cols, out):
+    rc = np.bincount(rows, minlength=max(rows, default=0) + 1) if rows else []
+    cc = np.bincount(cols)
+    return {"op": 1, "rows": sparse(rc), "cols": sparse(cc), "out": out}
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_extend_row_jobs(eng, seed):
+    rng = np.random.default_rng(seed)
+    m = 30
+    U = workloads.haar(m, 300 + seed)
+    jobs, refs = [], []
+    off = 0
+    for k in range(1, 13):
+        cols = list(rng.choice(m, size=k, replace=False))
+        rows = list(rng.integers(0, m, size=k - 1))     # may repeat (collisions)
+        jobs.append(extend_job(rows, cols, off))
+        refs.append(oracle.extend_row(U, rows, cols))
+        off += m
+    perm, amp = eng.perm_batched(dev(U), jobs, n_out=off)
+    out = perm.cpu().numpy()
+    for k, r in enumerate(refs):
+        got = out[k * m:(k + 1) * m]
+        scale = np.max(np.abs(r))
+        assert np.max(np.abs(got - r)) < 1e-10 * scale, k
+
+
+def test_extend_row_with_repeated_input_columns(eng):
+    U = workloads.haar(7, 4)
+    rows = [1, 1, 5, 2]
+    # input columns with multiplicities: mode 0 twice, mode 3 once, mode 6 twice
+    S = np.array([2, 0, 0, 1, 0, 0, 2], np.int32)
+    T = np.bincount(rows, minlength=7).astype(np.int32)
+    job = {"op": 1, "rows": sparse(T), "cols": sparse(S), "out": 0}
+    perm, _ = eng.perm_batched(dev(U), [job], n_out=7)
+    got = perm.cpu().numpy()
+    for l in range(7):
+        T2 = T.copy()
+        T2[l] += 1
+        ref = oracle.perm_mult(U, S, T2)
+        assert abs(got[l] - ref) < 1e-12 * max(1.0, abs(ref))
+
+
+def test_batched_matches_single_calls(eng):
+    rng = np.random.default_rng(77)
+    m = 12
+    U = workloads.haar(m, 77)
+    Ud = dev(U)
+    jobs, singles = [], []
+    for k in range(20):
+        n = int(rng.integers(1, 14))
+        S = workloads.random_occupations(rng, m, n, cap=3)
+        T = workloads.random_occupations(rng, m, n, cap=3)
+        jobs.append(perm_job(S, T))
+        p, _ = eng.perm(Ud, list(S), list(T))
+        singles.append(complex(p.item()))
+    perm, _ = eng.perm_batched(Ud, jobs)
+    perm = perm.cpu().numpy()
+    for k in range(20):
+        if abs(singles[k]) > 1e-12:
+            assert rel(perm[k], singles[k]) < 1e-12
+
+
+def test_graph_replay_follows_input_and_is_deterministic(eng):
+    # the same description and pointers replay a captured graph; eager work
+    # and a changed U between replays must be reflected in every replay
+    m = 9
+    U1 = workloads.haar(m, 5)
+    U2 = workloads.haar(m, 6)
+    Ud = dev(U1)
+    rng = np.random.default_rng(3)
+    pats = [(workloads.random_occupations(rng, m, 7, cap=3), workloads.random_occupations(rng, m, 7, cap=3))
+            for _ in range(12)]
+    jobs = [perm_job(S, T, out=k) for k, (S, T) in enumerate(pats)]
+    out = torch.zeros(12, dtype=torch.complex128, device="cuda")
+    import paper_2403_04006_amd as pq
+    import ctypes
+    lib = pq._lib.load()
+    keep = []
+    arr = (pq.pq_job * len(jobs))()
+    for k, j in enumerate(jobs):
+        ri = pq._lib.i32_array([r for r, _ in j["rows"]]); rm = pq._lib.i32_array([c for _, c in j["rows"]])
+        ci = pq._lib.i32_array([r for r, _ in j["cols"]]); cm = pq._lib.i32_array([c for _, c in j["cols"]])
+        keep += [ri, rm, ci, cm]
+        arr[k] = pq.pq_job(0, len(j["rows"]), len(j["cols"]), ri, rm, ci, cm, k)
+    stream = torch.cuda.current_stream().cuda_stream
+    results = []
+    for rep in range(4):
+        src = U1 if rep % 2 == 0 else U2
+        Ud.copy_(torch.from_numpy(src))
+        _ = (Ud * 2).sum()                     # unrelated eager work between replays
+        st = lib.pq_perm_batched(eng._ctx, Ud.data_ptr(), m, m, arr, len(jobs), out.data_ptr(), None, stream)
+        assert st == 0
+        torch.cuda.synchronize()
+        got = out.cpu().numpy().copy()
+        for k, (S, T) in enumerate(pats):
+            ref = oracle.perm_mult(src, S, T)
+            assert abs(got[k] - ref) < 1e-12 * max(1.0, abs(ref))
+        results.append(got)
+    assert np.array_equal(results[0], results[2]) and np.array_equal(results[1], results[3])
+
+
+def test_argument_errors(eng):
+    import paper_2403_04006_amd as pq
+    U = dev(workloads.haar(4, 0))
+    with pytest.raises(pq.PqError):      # overlapping outputs
+        eng.perm_batched(U, [perm_job([1, 0, 0, 0], [1, 0, 0, 0], out=0),
+                             perm_job([0, 1, 0, 0], [0, 1, 0, 0], out=0)])
+    with pytest.raises(pq.PqError):      # mode out of range
+        eng.perm_batched(U, [{"op": 0, "rows": [(7, 1)], "cols": [(0, 1)]}])
+    with pytest.raises(pq.PqError):      # EXTEND_ROW photon count
+        eng.perm_batched(U, [{"op": 1, "rows": [(1, 1)], "cols": [(0, 1)], "out": 0}])
+    with pytest.raises(pq.PqError):      # repeated mode index
+        eng.perm_batched(U, [{"op": 0, "rows": [(1, 1), (1, 1)], "cols": [(0, 2)]}])
+
+
+def _c3_patterns_sorted():
+    pats = workloads.repeated_patterns(count=256, seed=1)
+    cost = []
+    for S, T in pats:
+        cs = int(np.prod(S[S > 0] + 1))
+        ct = int(np.prod(T[T > 0] + 1))
+        cost.append(min(cs, ct))
+    order = np.argsort(cost)
+    return pats, order, cost
+
+
+def test_repeated_40_photons_full_size(eng):
+    # the 256-pattern workload: all patterns in one batch; the two cheapest
+    # patterns against the oracle, and every pattern against single calls on
+    # a sample
+    pats, order, cost = _c3_patterns_sorted()
+    U = workloads.haar(20, 0)
+    Ud = dev(U)
+    jobs = [perm_job(S, T) for S, T in pats]
+    perm, amp = eng.perm_batched(Ud, jobs)
+    perm = perm.cpu().numpy()
+    for idx in order[:2]:
+        S, T = pats[idx]
+        ref = oracle.perm_mult_cheaper_side(U, S, T)
+        err = rel(perm[idx], ref)
+        print(f"C3 pattern {idx} cost {cost[idx]:.3g} rel err {err:.2e}")
+        assert err < 1e-8
+    for idx in order[::64]:
+        S, T = pats[idx]
+        p, _ = eng.perm(Ud, list(S), list(T))
+        assert rel(perm[idx], complex(p.item())) < 1e-10
+
+
+def test_sampling_shaped_extend_jobs_full_size(eng):
+    # 20 photons in 400 modes: sample the k = 20 step of three samples
+    U = workloads.haar(400, 0)
+    cols, rows = workloads.sampling_jobs(samples=3, seed=0)
+    jobs, refs = [], []
+    for s in range(3):
+        c = [int(x) for x in cols[s]]
+        r = [int(x) for x in rows[s]]
+        jobs.append(extend_job(r, c, s * 400))
+        refs.append(oracle.extend_row(U, r, c))
+    perm, _ = eng.perm_batched(dev(U), jobs, n_out=1200)
+    out = perm.cpu().numpy()
+    for s in range(3):
+        got = out[s * 400:(s + 1) * 400]
+        scale = np.max(np.abs(refs[s]))
+        err = np.max(np.abs(got - refs[s])) / scale
+        print(f"extend k=20 sample {s}: max rel err {err:.2e}")
+        assert err < 1e-10
