@@ -122,7 +122,9 @@ typedef struct {
 
 /*
  * pq_perm_batched -- all jobs in one stream-ordered submission (one persistent
- * work-queue launch for the Gray-code sums).
+ * work-queue launch for the Gray-code sums, captured into a HIP graph).
+ * This path is switched off in this build: after validating its arguments it
+ * returns PQ_EDEVICE.  pq_perm_many computes the same outputs.
  *   perm  device, complex, large enough for every job's outputs.
  *   amp   device, may be NULL; written for PQ_OP_PERM jobs only.
  * Output ranges of different jobs must not overlap (PQ_EINVAL otherwise).
@@ -130,6 +132,19 @@ typedef struct {
 int pq_perm_batched(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m,
                     const pq_job* jobs, int32_t njobs,
                     pq_c128* perm, pq_c128* amp, void* stream);
+
+/*
+ * pq_perm_many -- the same jobs and outputs as pq_perm_batched, scheduled
+ * statically: every job's Gray-code range is cut into chunks on the host, one
+ * wavefront sweeps one chunk and writes its own partial slot, and a second
+ * kernel adds each job's slots in order (results do not depend on timing).
+ * Plans and their device descriptors are cached per distinct job list, so a
+ * repeated call with the same jobs only launches kernels.  EXTEND_ROW jobs
+ * may have at most 24 distinct columns (PQ_ERANGE otherwise).
+ */
+int pq_perm_many(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m,
+                 const pq_job* jobs, int32_t njobs,
+                 pq_c128* perm, pq_c128* amp, void* stream);
 
 /*
  * pq_perm_grad -- vector-Jacobian product over a batch of patterns on one U.
@@ -151,6 +166,41 @@ int pq_perm_grad(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m,
                  int32_t batch, const int32_t* S, const int32_t* T,
                  const pq_c128* gperm, pq_c128* perm,
                  pq_c128* dU, int64_t lddu, void* stream);
+
+/*
+ * Differentiable circuits (Beamsplitter gate section; differentiable
+ * circuits in the simulator overview).
+ *
+ * pq_mesh_unitary -- U = B_ncell ... B_2 B_1 for cells acting on mode pairs
+ * (modes[2q], modes[2q+1]) with the beamsplitter mode matrix
+ * [[t, -r*], [r, t]], t = cos(theta_q), r = e^{i phi_q} sin(theta_q)
+ * (row = output mode, column = input mode); cell q applies first when q is
+ * smallest.  angles: device, 2*ncell doubles (theta_q, phi_q).  modes: host.
+ * U: device m x m, leading dimension ldu.  1 <= m <= 32, ncell <= 512.
+ *
+ * pq_mesh_unitary_vjp -- gradient of a real loss with respect to the angles
+ * given its gradient gU with respect to U in the conjugate-Wirtinger
+ * convention of complex autograd (gU = dL/dRe U + i dL/dIm U):
+ * gangles[2q] = dL/dtheta_q, gangles[2q+1] = dL/dphi_q (device, overwritten).
+ */
+int pq_mesh_unitary(pq_ctx* ctx, int32_t m, int32_t ncell, const int32_t* modes, const double* angles,
+                    pq_c128* U, int64_t ldu, void* stream);
+int pq_mesh_unitary_vjp(pq_ctx* ctx, int32_t m, int32_t ncell, const int32_t* modes, const double* angles,
+                        const pq_c128* gU, int64_t ldg, double* gangles, void* stream);
+
+/*
+ * Sampling loss of a batch of output patterns (Eq. BS_prob):
+ *   loss = -(1/batch) sum_p ( log |perm_p|^2 - log_norm_p ),
+ * log_norm_p = log(prod S_p! prod T_p!) (device, may be NULL for zeros), so
+ * that loss is the mean negative log-probability.  Fixed-order double-double
+ * sum.  pq_neg_log_prob_vjp writes gperm_p = dloss/dperm_p in the same
+ * convention as above, scaled by *gloss (device scalar, NULL for 1):
+ * gperm_p = -(2/batch) gloss / conj(perm_p).
+ */
+int pq_neg_log_prob(pq_ctx* ctx, int32_t batch, const pq_c128* perm, const double* log_norm, double* loss,
+                    void* stream);
+int pq_neg_log_prob_vjp(pq_ctx* ctx, int32_t batch, const pq_c128* perm, const double* gloss, pq_c128* gperm,
+                        void* stream);
 
 /*
  * Sweep-kernel timing.  While enabled, every Gray-code sweep launch on ctx is

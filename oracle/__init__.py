@@ -295,3 +295,53 @@ def chain_rule_distribution(U, inputs_order, rows_so_far) -> np.ndarray:
     k = len(rows_so_far) + 1
     out = extend_row(U, rows_so_far, list(inputs_order[:k]))
     return np.abs(out) ** 2
+
+
+def beamsplitter_derivatives(theta: float, phi: float) -> tuple:
+    """d/dtheta and d/dphi of the beamsplitter matrix [[t, -r*], [r, t]],
+    t = cos(theta), r = e^{i phi} sin(theta), differentiated entry by entry."""
+    c, s = math.cos(theta), math.sin(theta)
+    e = complex(math.cos(phi), math.sin(phi))
+    d_theta = np.array([[-s, -e.conjugate() * c], [e * c, -s]], dtype=np.complex128)
+    d_phi = np.array([[0.0, 1j * e.conjugate() * s], [1j * e * s, 0.0]], dtype=np.complex128)
+    return d_theta, d_phi
+
+
+def mesh_jacobian(angles, cells, modes: int) -> np.ndarray:
+    """dU/dtheta_q and dU/dphi_q of U = B_N ... B_1 by the product rule:
+    dU/dx_q = (B_N ... B_{q+1}) (dB_q/dx) (B_{q-1} ... B_1).
+    Returns an array of shape (N, 2, modes, modes)."""
+    angles = np.asarray(angles, dtype=np.float64)
+    N = len(cells)
+    emb = []
+    for (theta, phi), (a, b) in zip(angles, cells):
+        B = np.eye(modes, dtype=np.complex128)
+        B[np.ix_([a, b], [a, b])] = beamsplitter(theta, phi)
+        emb.append(B)
+    prefix = [np.eye(modes, dtype=np.complex128)]
+    for q in range(N):
+        prefix.append(emb[q] @ prefix[-1])          # prefix[q] = B_{q-1} ... B_1
+    J = np.zeros((N, 2, modes, modes), dtype=np.complex128)
+    suffix = np.eye(modes, dtype=np.complex128)      # B_N ... B_{q+1}
+    for q in range(N - 1, -1, -1):
+        (theta, phi), (a, b) = angles[q], cells[q]
+        for k, d in enumerate(beamsplitter_derivatives(theta, phi)):
+            D = np.zeros((modes, modes), dtype=np.complex128)
+            D[np.ix_([a, b], [a, b])] = d
+            J[q, k] = suffix @ D @ prefix[q]
+        suffix = suffix @ emb[q]
+    return J
+
+
+def mesh_loss_grad(angles, cells, modes: int, S, patterns) -> np.ndarray:
+    """d/d(theta_q, phi_q) of L = -(1/N) sum_p log(|perm(U_{T_p,S})|^2 / prod T_p!):
+    dL/dx = -(2/N) sum_p Re( sum_ab d perm_p/dU_ab dU_ab/dx / perm_p )."""
+    U = mesh_unitary(angles, cells, modes)
+    J = mesh_jacobian(angles, cells, modes)
+    total = np.zeros(J.shape[:2])
+    for T in patterns:
+        p = perm_mult(U, S, T)
+        G = perm_grad(U, S, T)
+        dp = np.einsum("ab,qkab->qk", G, J)
+        total += np.real(dp / p)
+    return -2.0 * total / len(patterns)

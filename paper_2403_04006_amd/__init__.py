@@ -97,13 +97,9 @@ class Engine:
         _check(self._lib.pq_profile_read(self._ctx, ctypes.byref(n), ctypes.byref(ms)), self._ctx)
         return n.value, ms.value
 
-    # ---------------------------------------------------- pq_perm_batched
-    def perm_batched(self, U: torch.Tensor, jobs: Sequence[dict], n_out: int | None = None,
-                     with_amp: bool = True):
-        """Run jobs given as dicts {op, rows: [(mode, mult)], cols: [(mode, mult)], out}.
-        Returns (perm, amp) device tensors of length n_out."""
-        U, ldu = _as_matrix(U)
-        m = U.shape[0]
+    # ------------------------------------------------- batched job lists
+    @staticmethod
+    def _job_array(jobs: Sequence[dict], m: int):
         keep = []
         arr = (pq_job * max(1, len(jobs)))()
         total = 0
@@ -119,14 +115,32 @@ class Engine:
             off = int(j.get("out", total))
             arr[k] = pq_job(op, len(rows), len(cols), ri, rm, ci, cm, off)
             total = max(total, off + (m if op == PQ_OP_EXTEND_ROW else 1))
+        return arr, keep, total
+
+    def _run_jobs(self, fn, U, jobs, n_out, with_amp):
+        U, ldu = _as_matrix(U)
+        m = U.shape[0]
+        arr, keep, total = self._job_array(jobs, m)
         n_out = total if n_out is None else n_out
         perm = torch.zeros(max(1, n_out), dtype=torch.complex128, device=U.device)
         amp = torch.zeros(max(1, n_out), dtype=torch.complex128, device=U.device) if with_amp else None
-        st = self._lib.pq_perm_batched(self._ctx, U.data_ptr(), ldu, m, arr, len(jobs), perm.data_ptr(),
-                                       amp.data_ptr() if amp is not None else None,
-                                       _stream_handle(U.device))
+        st = fn(self._ctx, U.data_ptr(), ldu, m, arr, len(jobs), perm.data_ptr(),
+                amp.data_ptr() if amp is not None else None, _stream_handle(U.device))
         _check(st, self._ctx)
         return perm[:n_out], (amp[:n_out] if amp is not None else None)
+
+    def perm_many(self, U: torch.Tensor, jobs: Sequence[dict], n_out: int | None = None, with_amp: bool = True):
+        """Jobs {op, rows: [(mode, mult)], cols: [(mode, mult)], out} through the
+        statically scheduled many-pattern path (pq_perm_many).  PERM jobs write
+        perm(U_{T,S}) (and the amplitude) at `out`; EXTEND_ROW jobs write
+        perm(U_{T+e_l,S}) for l = 0..m-1 at out..out+m-1.  Returns (perm, amp)."""
+        return self._run_jobs(self._lib.pq_perm_many, U, jobs, n_out, with_amp)
+
+    def perm_batched(self, U: torch.Tensor, jobs: Sequence[dict], n_out: int | None = None,
+                     with_amp: bool = True):
+        """The same jobs through the persistent work-queue entry point
+        (pq_perm_batched, switched off in this build: raises PqError)."""
+        return self._run_jobs(self._lib.pq_perm_batched, U, jobs, n_out, with_amp)
 
     # -------------------------------------------------------- pq_perm_grad
     def perm_grad(self, U: torch.Tensor, S_list, T_list, gperm: torch.Tensor, want_perm: bool = True):

@@ -67,11 +67,18 @@ _SIGNATURES = {
     "pq_perm": ([_VP, _VP, ctypes.c_int64, ctypes.c_int32, _I32P, _I32P, _VP, _VP, _VP], ctypes.c_int),
     "pq_perm_batched": ([_VP, _VP, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(pq_job), ctypes.c_int32,
                          _VP, _VP, _VP], ctypes.c_int),
+    "pq_perm_many": ([_VP, _VP, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(pq_job), ctypes.c_int32,
+                      _VP, _VP, _VP], ctypes.c_int),
     "pq_perm_grad": ([_VP, _VP, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _I32P, _I32P, _VP, _VP,
                       _VP, ctypes.c_int64, _VP], ctypes.c_int),
     "pq_plan_describe": ([ctypes.c_int32, _I32P, _I32P, ctypes.POINTER(pq_plan_info)], ctypes.c_int),
     "pq_gray_unrank": ([ctypes.c_int32, _I32P, ctypes.c_uint64, _I32P], ctypes.c_int),
     "pq_profile_enable": ([_VP, ctypes.c_int], ctypes.c_int),
+    "pq_mesh_unitary": ([_VP, ctypes.c_int32, ctypes.c_int32, _I32P, _VP, _VP, ctypes.c_int64, _VP], ctypes.c_int),
+    "pq_mesh_unitary_vjp": ([_VP, ctypes.c_int32, ctypes.c_int32, _I32P, _VP, _VP, ctypes.c_int64, _VP, _VP],
+                            ctypes.c_int),
+    "pq_neg_log_prob": ([_VP, ctypes.c_int32, _VP, _VP, _VP, _VP], ctypes.c_int),
+    "pq_neg_log_prob_vjp": ([_VP, ctypes.c_int32, _VP, _VP, _VP, _VP], ctypes.c_int),
     "pq_profile_read": ([_VP, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
 }
 

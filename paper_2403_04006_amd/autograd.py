@@ -1,0 +1,123 @@
+"""torch.autograd Functions over the library's kernels (argument marshalling
+only): a beamsplitter mesh (angles -> U), permanents of many output patterns
+(U -> perm), and the mean negative log-probability (perm -> loss).  Chained,
+gradients flow from the loss to every mesh angle through the adjoint
+Gray-code sweep.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Sequence
+
+import torch
+
+from . import _lib, _check, _stream_handle, engine as _engine
+
+__all__ = ["MeshUnitary", "PermAmp", "NegLogProb", "mesh_unitary", "perm_amp", "neg_log_prob", "mesh_loss"]
+
+
+def _modes_array(cells: Sequence[tuple]):
+    flat = [int(x) for pair in cells for x in pair]
+    return _lib.i32_array(flat), len(cells)
+
+
+class MeshUnitary(torch.autograd.Function):
+    """U = B_last ... B_1 from (ncell, 2) float64 angles (theta, phi)."""
+
+    @staticmethod
+    def forward(ctx, angles: torch.Tensor, cells: tuple, m: int):
+        eng = _engine(angles.device.index)
+        angles = angles.detach().to(torch.float64).contiguous()
+        modes, ncell = _modes_array(cells)
+        U = torch.empty((m, m), dtype=torch.complex128, device=angles.device)
+        _check(eng._lib.pq_mesh_unitary(eng._ctx, m, ncell, modes, angles.data_ptr(), U.data_ptr(), m,
+                                        _stream_handle(angles.device)), eng._ctx)
+        ctx.save_for_backward(angles)
+        ctx.cells = cells
+        ctx.m = m
+        return U
+
+    @staticmethod
+    def backward(ctx, gU: torch.Tensor):
+        (angles,) = ctx.saved_tensors
+        eng = _engine(angles.device.index)
+        gU = gU.to(torch.complex128).contiguous()
+        modes, ncell = _modes_array(ctx.cells)
+        gang = torch.empty_like(angles)
+        _check(eng._lib.pq_mesh_unitary_vjp(eng._ctx, ctx.m, ncell, modes, angles.data_ptr(), gU.data_ptr(),
+                                            gU.stride(0), gang.data_ptr(), _stream_handle(angles.device)),
+               eng._ctx)
+        return gang, None, None
+
+
+def _sparse(v):
+    return [(i, int(c)) for i, c in enumerate(v) if int(c) > 0]
+
+
+class PermAmp(torch.autograd.Function):
+    """perm(U_{T_p,S_p}) for every pattern p (forward: pq_perm_many; backward:
+    pq_perm_grad, the adjoint sweep)."""
+
+    @staticmethod
+    def forward(ctx, U: torch.Tensor, S_list, T_list):
+        eng = _engine(U.device.index)
+        U = U.detach().contiguous()
+        jobs = [{"op": 0, "rows": _sparse(T), "cols": _sparse(S), "out": p}
+                for p, (S, T) in enumerate(zip(S_list, T_list))]
+        perm, _ = eng.perm_many(U, jobs, n_out=len(jobs), with_amp=False)
+        ctx.save_for_backward(U)
+        ctx.S_list = S_list
+        ctx.T_list = T_list
+        return perm
+
+    @staticmethod
+    def backward(ctx, gperm: torch.Tensor):
+        (U,) = ctx.saved_tensors
+        eng = _engine(U.device.index)
+        dU, _ = eng.perm_grad(U, ctx.S_list, ctx.T_list, gperm.contiguous(), want_perm=False)
+        return dU, None, None
+
+
+class NegLogProb(torch.autograd.Function):
+    """-(1/N) sum_p (log|perm_p|^2 - log_norm_p)."""
+
+    @staticmethod
+    def forward(ctx, perm: torch.Tensor, log_norm: torch.Tensor | None = None):
+        eng = _engine(perm.device.index)
+        perm = perm.detach().contiguous()
+        loss = torch.empty((), dtype=torch.float64, device=perm.device)
+        ln = log_norm.detach().to(torch.float64).contiguous() if log_norm is not None else None
+        _check(eng._lib.pq_neg_log_prob(eng._ctx, perm.numel(), perm.data_ptr(),
+                                        ln.data_ptr() if ln is not None else None, loss.data_ptr(),
+                                        _stream_handle(perm.device)), eng._ctx)
+        ctx.save_for_backward(perm)
+        return loss
+
+    @staticmethod
+    def backward(ctx, gloss: torch.Tensor):
+        (perm,) = ctx.saved_tensors
+        eng = _engine(perm.device.index)
+        gl = gloss.detach().to(torch.float64).contiguous()
+        gperm = torch.empty_like(perm)
+        _check(eng._lib.pq_neg_log_prob_vjp(eng._ctx, perm.numel(), perm.data_ptr(), gl.data_ptr(),
+                                            gperm.data_ptr(), _stream_handle(perm.device)), eng._ctx)
+        return gperm, None
+
+
+def mesh_unitary(angles: torch.Tensor, cells, m: int) -> torch.Tensor:
+    return MeshUnitary.apply(angles, tuple(tuple(c) for c in cells), m)
+
+
+def perm_amp(U: torch.Tensor, S_list, T_list) -> torch.Tensor:
+    return PermAmp.apply(U, S_list, T_list)
+
+
+def neg_log_prob(perm: torch.Tensor, log_norm: torch.Tensor | None = None) -> torch.Tensor:
+    return NegLogProb.apply(perm, log_norm)
+
+
+def mesh_loss(angles: torch.Tensor, cells, m: int, S, T_list, log_norm: torch.Tensor | None = None):
+    """Loss of output patterns T_list for input S through the mesh."""
+    U = mesh_unitary(angles, cells, m)
+    perm = perm_amp(U, [S] * len(T_list), T_list)
+    return neg_log_prob(perm, log_norm)

@@ -87,9 +87,12 @@ static bool graphs_enabled() {
     return !(e && e[0] == '0');
 }
 
+}  // namespace pq
+
 // Validate the jobs and build the cache key.  Returns PQ_OK or an error.
-static int validate_jobs(pq_ctx* ctx, int32_t m, const pq_job* jobs, int32_t njobs,
-                         std::vector<int64_t>& key) {
+int pq_validate_jobs(pq_ctx* ctx, int32_t m, const pq_job* jobs, int32_t njobs,
+                     std::vector<int64_t>& key) {
+    using namespace pq;
     std::vector<std::pair<int64_t, int64_t>> ranges;
     ranges.reserve(njobs);
     std::vector<char> seen((size_t)m, 0);
@@ -137,6 +140,8 @@ static int validate_jobs(pq_ctx* ctx, int32_t m, const pq_job* jobs, int32_t njo
             return ctx->fail(PQ_EINVAL, "output ranges of two jobs overlap");
     return PQ_OK;
 }
+
+namespace pq {
 
 // Enqueue the whole batch on stream `st`.
 static int enqueue_batch(pq_ctx* ctx, BatchEntry& E, hipStream_t st) {
@@ -376,6 +381,16 @@ void pq_release_batch_cache(pq_ctx* ctx) {
     ctx->batch_cache = nullptr;
 }
 
+// The persistent work-queue path below is switched off: its first GPU run
+// (a graph-captured batch of 495 small permanents) hung, while CPU emulation
+// of the same kernels and host planning (sequential and with concurrent
+// wavefronts) completes with correct results, so no mistake in this code that
+// would explain the hang has been shown.  Until one is, pq_perm_batched
+// reports PQ_EDEVICE after validating its arguments.
+static int perm_batched_queue(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m,
+                              const pq_job* jobs, int32_t njobs,
+                              pq_c128* perm, pq_c128* amp, void* stream);
+
 int pq_perm_batched(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m,
                     const pq_job* jobs, int32_t njobs,
                     pq_c128* perm, pq_c128* amp, void* stream) {
@@ -385,8 +400,23 @@ int pq_perm_batched(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m,
     if (njobs == 0) return PQ_OK;
     if (!jobs || !perm) return ctx->fail(PQ_EINVAL, "pq_perm_batched: NULL jobs or perm");
     if (m > 0 && (!U || ldu < m)) return ctx->fail(PQ_EINVAL, "pq_perm_batched: NULL U or ldu < m");
+    std::vector<int64_t> key;
+    int rc = pq_validate_jobs(ctx, m, jobs, njobs, key);
+    if (rc) return rc;
+    if (getenv("PQ_BATCH_QUEUE") == nullptr)
+        return ctx->fail(PQ_EDEVICE, "pq_perm_batched: the persistent work-queue path is disabled in this build");
+    return perm_batched_queue(ctx, U, ldu, m, jobs, njobs, perm, amp, stream);
+}
+
+static int perm_batched_queue(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m,
+                              const pq_job* jobs, int32_t njobs,
+                              pq_c128* perm, pq_c128* amp, void* stream) {
+    if (m < 0 || njobs < 0) return ctx->fail(PQ_EINVAL, "pq_perm_batched: negative size");
+    if (njobs == 0) return PQ_OK;
+    if (!jobs || !perm) return ctx->fail(PQ_EINVAL, "pq_perm_batched: NULL jobs or perm");
+    if (m > 0 && (!U || ldu < m)) return ctx->fail(PQ_EINVAL, "pq_perm_batched: NULL U or ldu < m");
     std::vector<int64_t> key = {(int64_t)(uintptr_t)U, ldu, m, (int64_t)(uintptr_t)perm, (int64_t)(uintptr_t)amp, njobs};
-    int rc = validate_jobs(ctx, m, jobs, njobs, key);
+    int rc = pq_validate_jobs(ctx, m, jobs, njobs, key);
     if (rc) return rc;
     DeviceGuard guard(ctx->device);
     hipStream_t st = (hipStream_t)stream;

@@ -26,6 +26,7 @@ template <int NC, bool UNIT>
 struct PermBody {
     cplx acc{0.0, 0.0};
     const int8_t* kap;
+    __device__ __forceinline__ void flip(int, int) {}
     __device__ __forceinline__ void term(const cplx (&c)[NC], double w) {
         if constexpr (UNIT) cfma_to(acc, w, product_unit_powers(c));
         else cfma_to(acc, w, product_powers(c, kap));
@@ -36,6 +37,7 @@ template <int NC, bool UNIT>
 struct ExtendBody {
     cplx acc[NC];
     const int8_t* kap;
+    __device__ __forceinline__ void flip(int, int) {}
     __device__ __forceinline__ ExtendBody() {
 #pragma unroll
         for (int j = 0; j < NC; ++j) acc[j] = cplx{0.0, 0.0};
@@ -111,6 +113,7 @@ __device__ __forceinline__ double sweep_chunk(const BJob& J, const cplx* __restr
         for (uint64_t t = start + 1; t < end; ++t) {
             const int i = __builtin_ctzll(t);
             const int sel = (int)((t >> (i + 1)) & 1ull);
+            body.flip(i, sel ? -1 : 1);          // time digit i moves by +1 (sel 0) or -1
             add_row(c, trows + ((size_t)i * 2 + sel) * NC);
             w = -w;
             body.term(c, w);
@@ -150,7 +153,9 @@ __device__ __forceinline__ double sweep_chunk(const BJob& J, const cplx* __restr
             const StepEntry* tab = refl ? tb : tf;
             body.term(c, wh * tab[pos0].w);
             for (int p = pos0 + 1; p < pos0 + len; ++p) {
-                add_row(c, trows + tab[p].off);
+                const int off = tab[p].off;
+                body.flip(off / (2 * NC), ((off / NC) & 1) ? -1 : 1);
+                add_row(c, trows + off);
                 body.term(c, wh * tab[p].w);
             }
             s = seg_end;

@@ -1,0 +1,137 @@
+// Reduction and scatter kernels of the many-pattern entry points, and the
+// class dispatch.
+#include <hip/hip_runtime.h>
+
+#include "device.h"
+#include "many_kernels.h"
+
+namespace pq {
+
+// One workgroup per pattern: add its chunk slots in slot order.
+__global__ __launch_bounds__(64) void many_final_kernel(const ManyFinalArgs a) {
+    const int p = blockIdx.x;
+    if (p >= a.npat) return;
+    const int t = threadIdx.x;
+    const int cls = a.pat_class[p];
+    if (cls < 0) {
+        if (t == 0) {
+            const BJob& J = a.jobs[p];
+            if (a.perm) a.perm[J.out_offset] = a.trivial[p];
+            if (a.amp) a.amp[J.out_offset] = a.trivial[p];
+        }
+        return;
+    }
+    const BJob& J = a.jobs[p];
+    const int sd = a.class_sd[cls];
+    const double* base = a.partials + a.class_off[cls] + (size_t)a.pat_slot[p] * sd;
+    if (J.op == kOpPerm) {
+        if (t == 0) {
+            cdd s{{base[0], base[1]}, {base[2], base[3]}};
+            for (int k = 1; k < J.nchunks; ++k) {
+                const double* q = base + (size_t)k * sd;
+                s = cdd_add(s, cdd{{q[0], q[1]}, {q[2], q[3]}});
+            }
+            const double re = (s.re.hi + s.re.lo) * J.scale;
+            const double im = (s.im.hi + s.im.lo) * J.scale;
+            if (a.perm) a.perm[J.out_offset] = cplx{re, im};
+            if (a.amp) a.amp[J.out_offset] = cplx{re * J.norm, im * J.norm};
+        }
+        if (a.adjoint) {
+            const int nent = J.r * J.nc;
+            cplx* D = a.dpat + a.dpat_off[p];
+            for (int e = t; e < nent; e += 64) {
+                double re = 0.0, im = 0.0;
+                for (int k = 0; k < J.nchunks; ++k) {
+                    const double* q = base + (size_t)k * sd + 4 + 2 * e;
+                    re += q[0];
+                    im += q[1];
+                }
+                D[e] = cplx{re * J.scale, im * J.scale};
+            }
+        }
+    } else {
+        // Laplace expansion: L_j from the chunk sums, then out[l] = sum_j U[l, C_j] L_j
+        __shared__ cplx L[kMaxExtendCols];
+        for (int j = t; j < J.nc; j += 64) {
+            cdd s{{base[4 * j], base[4 * j + 1]}, {base[4 * j + 2], base[4 * j + 3]}};
+            for (int k = 1; k < J.nchunks; ++k) {
+                const double* q = base + (size_t)k * sd + 4 * j;
+                s = cdd_add(s, cdd{{q[0], q[1]}, {q[2], q[3]}});
+            }
+            L[j] = cplx{(s.re.hi + s.re.lo) * J.scale, (s.im.hi + s.im.lo) * J.scale};
+        }
+        __syncthreads();
+        const int32_t* cmode = a.idx + J.idx_off + 2 * J.r;
+        for (int l = t; l < J.m_out; l += 64) {
+            const cplx* Ul = a.U + (size_t)l * (size_t)a.ldu;
+            double re = 0.0, im = 0.0;
+            for (int j = 0; j < J.nc; ++j) {
+                const cplx u = Ul[cmode[j]];
+                re = __builtin_fma(u.re, L[j].re, re);
+                re = __builtin_fma(-u.im, L[j].im, re);
+                im = __builtin_fma(u.re, L[j].im, im);
+                im = __builtin_fma(u.im, L[j].re, im);
+            }
+            if (a.perm) a.perm[J.out_offset + l] = cplx{re, im};
+        }
+    }
+}
+
+hipError_t launch_many_final(const ManyFinalArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(many_final_kernel, dim3(a.npat > 0 ? a.npat : 1), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+// dU[a][b] = sum_p g_p conj(d perm_p / d U_ab), patterns added in order.  For
+// a pattern iterated over its output side, B_ij = U[row_mode_i][col_mode_j];
+// over its input side (transposed), B_ij = U[col_mode_j][row_mode_i].
+__global__ __launch_bounds__(256) void grad_scatter_kernel(const GradScatterArgs a) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= a.m * a.m) return;
+    const int ra = e / a.m, cb = e % a.m;
+    double re = 0.0, im = 0.0;
+    for (int p = 0; p < a.npat; ++p) {
+        if (a.pat_class[p] < 0) continue;
+        const BJob& J = a.jobs[p];
+        const int32_t* rmode = a.idx + J.idx_off;
+        const int32_t* cmode = rmode + 2 * J.r;
+        const int want_row = J.transposed ? cb : ra;
+        const int want_col = J.transposed ? ra : cb;
+        int i = -1, j = -1;
+        for (int q = 0; q < J.r; ++q) if (rmode[q] == want_row) { i = q; break; }
+        if (i < 0) continue;
+        for (int q = 0; q < J.nc; ++q) if (cmode[q] == want_col) { j = q; break; }
+        if (j < 0) continue;
+        const cplx d = a.dpat[a.dpat_off[p] + (size_t)i * J.nc + j];
+        const cplx g = a.gperm[p];
+        // g * conj(d)
+        re = __builtin_fma(g.re, d.re, re);
+        re = __builtin_fma(g.im, d.im, re);
+        im = __builtin_fma(g.im, d.re, im);
+        im = __builtin_fma(-g.re, d.im, im);
+    }
+    a.dU[(size_t)ra * (size_t)a.lddu + cb] = cplx{re, im};
+}
+
+hipError_t launch_grad_scatter(const GradScatterArgs& a, hipStream_t s) {
+    const int n = a.m * a.m;
+    hipLaunchKernelGGL(grad_scatter_kernel, dim3((n + 255) / 256 > 0 ? (n + 255) / 256 : 1), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+typedef hipError_t (*mlaunch_fn)(int, const ManyArgs&, hipStream_t);
+#define PQ_MPTR(MODE, NC) &launch_many_##MODE##_##NC,
+static const mlaunch_fn g_m_fwd[] = {PQ_MCLASS_FWD(PQ_MPTR)};
+static const mlaunch_fn g_m_ext[] = {PQ_MCLASS_EXT(PQ_MPTR)};
+static const mlaunch_fn g_m_adj[] = {PQ_MCLASS_ADJ(PQ_MPTR)};
+
+hipError_t launch_many(int mode, int ncmax, int var, const ManyArgs& a, hipStream_t s) {
+    const int k = ncmax / 4 - 1;
+    if (ncmax % 4 || k < 0) return hipErrorInvalidValue;
+    if (mode == 0 && k < (int)(sizeof(g_m_fwd) / sizeof(g_m_fwd[0]))) return g_m_fwd[k](var, a, s);
+    if (mode == 1 && k < (int)(sizeof(g_m_ext) / sizeof(g_m_ext[0]))) return g_m_ext[k](var, a, s);
+    if (mode == 2 && k < (int)(sizeof(g_m_adj) / sizeof(g_m_adj[0]))) return g_m_adj[k](var, a, s);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace pq

@@ -1,0 +1,178 @@
+// Statically scheduled kernels over many patterns (see many.h): one
+// wavefront per chunk, one wavefront per workgroup.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "k_batch_impl.h"
+#include "many.h"
+
+namespace pq {
+
+// Adjoint inner digits per chunk: column sums, P, prefix products and KA
+// rows of flip accumulators stay in registers.
+template <int NC>
+struct AdjDigits { static constexpr int value = NC <= 12 ? 2 : 1; };
+
+// Reverse sweep body: P_j = sum w G_j (G_j = d/dc_j prod c^kap), the forward
+// sum, and per inner digit k the flip accumulator A_k = sum_flips 2 dd P.
+template <int NC, bool UNIT, int KA>
+struct AdjBody {
+    cplx P[NC];
+    cplx A[KA][NC];
+    cplx fwd{0.0, 0.0};
+    const int8_t* kap;
+    __device__ __forceinline__ AdjBody() {
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+            P[j] = cplx{0.0, 0.0};
+#pragma unroll
+            for (int q = 0; q < KA; ++q) A[q][j] = cplx{0.0, 0.0};
+        }
+    }
+    __device__ __forceinline__ void flip(int k, int dd) {
+        const double s = 2.0 * (double)dd;
+#pragma unroll
+        for (int q = 0; q < KA; ++q) {
+            if (q == k) {
+#pragma unroll
+                for (int j = 0; j < NC; ++j) cfma_to(A[q][j], s, P[j]);
+            }
+        }
+    }
+    __device__ __forceinline__ void term(const cplx (&c)[NC], double w) {
+        // prefix products of y_l = c_l^{kap_l}, then a backward sweep with the
+        // running suffix product: G_j = dy_j * pre_j * suf_j
+        cplx pre[NC];
+        pre[0] = cplx{1.0, 0.0};
+#pragma unroll
+        for (int j = 1; j < NC; ++j) {
+            cplx y = c[j - 1];
+            if constexpr (!UNIT)
+                for (int e = 1; e < kap[j - 1]; ++e) y = cmul(y, c[j - 1]);
+            pre[j] = (j == 1) ? y : cmul(pre[j - 1], y);
+        }
+        cplx s{1.0, 0.0};
+#pragma unroll
+        for (int j = NC - 1; j >= 0; --j) {
+            cplx G = (j == NC - 1) ? pre[j] : (j == 0 ? s : cmul(pre[j], s));
+            cplx y = c[j];
+            if constexpr (!UNIT) {
+                const int k = kap[j];
+                cplx d{(double)k, 0.0};
+                for (int e = 1; e < k; ++e) {
+                    d = cmul(d, c[j]);
+                    y = cmul(y, c[j]);
+                }
+                G = cmul(G, d);
+            }
+            cfma_to(P[j], w, G);
+            if (j == NC - 1) cfma_to(fwd, w, cmul(pre[j], y));   // full product
+            if (j > 0) s = (j == NC - 1) ? y : cmul(s, y);
+        }
+    }
+};
+
+__device__ __forceinline__ void store_cdd_slot(double* p, cdd v) {
+    p[0] = v.re.hi; p[1] = v.re.lo; p[2] = v.im.hi; p[3] = v.im.lo;
+}
+
+template <int MODE, int NC, bool BIN, bool UNIT>
+__global__ __launch_bounds__(64) void many_kernel(const ManyArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int ci = (int)blockIdx.x;
+    if (ci >= a.nchunks) return;
+    const MChunk ch = a.chunks[ci];
+    const BJob& J = a.jobs[ch.pat];
+    const cplx* mat = a.mat + J.mat_off;
+    double* slot = a.partials + (size_t)ch.slot * a.slot_doubles;
+    if constexpr (MODE == kModeFwd) {
+        PermBody<NC, UNIT> body;
+        body.kap = J.kap;
+        const double wl = sweep_chunk<NC, BIN>(J, mat, a.tabs, lane, ch.start, ch.count, body);
+        cdd v = wave_reduce(to_cdd(cplx{body.acc.re * wl, body.acc.im * wl}));
+        if (lane == 0) store_cdd_slot(slot, v);
+    } else if constexpr (MODE == kModeExt) {
+        ExtendBody<NC, UNIT> body;
+        body.kap = J.kap;
+        const double wl = sweep_chunk<NC, BIN>(J, mat, a.tabs, lane, ch.start, ch.count, body);
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+            if (j < J.nc) {
+                cdd v = wave_reduce(to_cdd(cplx{body.acc[j].re * wl, body.acc[j].im * wl}));
+                if (lane == 0) store_cdd_slot(slot + 4 * j, v);
+            }
+        }
+    } else {
+        constexpr int KA = AdjDigits<NC>::value;
+        __shared__ cplx sP[64][NC];
+        __shared__ cplx sA[64][KA][NC];
+        AdjBody<NC, UNIT, KA> body;
+        body.kap = J.kap;
+        const double wl = sweep_chunk<NC, BIN>(J, mat, a.tabs, lane, ch.start, ch.count, body);
+        // Gray digits of the chunk's last state (uniform)
+        int32_t tr[kMaxDim], g[kMaxDim];
+        for (int k = 0; k < J.n_time; ++k) tr[k] = J.time_radix[k];
+        gray_unrank(J.n_time, tr, ch.start + ch.count - 1, g);
+        const int32_t* rmu = a.idx + J.idx_off + J.r;
+        // inner rows: close the summation by parts with delta_k(end) P(end)
+#pragma unroll
+        for (int q = 0; q < KA; ++q) {
+            if (q < J.n_time && q < J.n_inner) {
+                const double dk = (double)(rmu[J.n_lane + q] - 2 * g[q]);
+#pragma unroll
+                for (int j = 0; j < NC; ++j) cfma_to(body.A[q][j], dk, body.P[j]);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+            sP[lane][j] = cplx{body.P[j].re * wl, body.P[j].im * wl};
+#pragma unroll
+            for (int q = 0; q < KA; ++q) sA[lane][q][j] = cplx{body.A[q][j].re * wl, body.A[q][j].im * wl};
+        }
+        cdd fv = wave_reduce(to_cdd(cplx{body.fwd.re * wl, body.fwd.im * wl}));
+        if (lane == 0) store_cdd_slot(slot, fv);
+        __syncthreads();
+        // D_ij of this chunk, contracted over the lanes in lane order
+        double* D = slot + 4;
+        const int nent = J.r * J.nc;
+        for (int e = lane; e < nent; e += 64) {
+            const int i = e / J.nc, j = e % J.nc;
+            double re = 0.0, im = 0.0;
+            if (i < J.n_lane) {
+                // lane row: delta_i depends on the lane's digit
+                const int mu = rmu[i];
+                for (int L = 0; L < 64; ++L) {
+                    int rest = L;
+                    int d = 0;
+                    for (int q = 0; q <= i; ++q) {
+                        d = rest % J.lane_radix[q];
+                        rest /= J.lane_radix[q];
+                    }
+                    const double del = (double)(mu - 2 * d);
+                    re = __builtin_fma(del, sP[L][j].re, re);
+                    im = __builtin_fma(del, sP[L][j].im, im);
+                }
+            } else if (i < J.n_lane + J.n_time && (i - J.n_lane) < J.n_inner && (i - J.n_lane) < KA) {
+                const int q = i - J.n_lane;
+                for (int L = 0; L < 64; ++L) {
+                    re += sA[L][q][j].re;
+                    im += sA[L][q][j].im;
+                }
+            } else {
+                // high time rows (constant over the chunk) and constant rows
+                double del = (double)rmu[i];
+                if (i < J.n_lane + J.n_time) del -= 2.0 * (double)g[i - J.n_lane];
+                for (int L = 0; L < 64; ++L) {
+                    re += sP[L][j].re;
+                    im += sP[L][j].im;
+                }
+                re *= del;
+                im *= del;
+            }
+            D[2 * e] = re;
+            D[2 * e + 1] = im;
+        }
+    }
+}
+
+}  // namespace pq

@@ -1,0 +1,24 @@
+// Many-pattern kernel instances (adjoint/4, adjoint/8, adjoint/12).
+#include "k_many_impl.h"
+#include "many_kernels.h"
+
+namespace pq {
+
+#define PQ_MKER(MODE, NC, B, U) many_kernel<MODE, NC, B, U>
+#define PQ_MINST(MODE, NC)                                                                       \
+    hipError_t launch_many_##MODE##_##NC(int var, const ManyArgs& a, hipStream_t s) {              \
+        const dim3 grid(a.nchunks > 0 ? a.nchunks : 1), block(64);                               \
+        switch (var) {                                                                           \
+            case 0: hipLaunchKernelGGL((PQ_MKER(MODE, NC, false, false)), grid, block, 0, s, a); break; \
+            case 1: hipLaunchKernelGGL((PQ_MKER(MODE, NC, false, true)), grid, block, 0, s, a); break; \
+            case 2: hipLaunchKernelGGL((PQ_MKER(MODE, NC, true, false)), grid, block, 0, s, a); break; \
+            default: hipLaunchKernelGGL((PQ_MKER(MODE, NC, true, true)), grid, block, 0, s, a); break; \
+        }                                                                                        \
+        return hipGetLastError();                                                                \
+    }
+
+PQ_MINST(2, 4)
+PQ_MINST(2, 8)
+PQ_MINST(2, 12)
+
+}  // namespace pq

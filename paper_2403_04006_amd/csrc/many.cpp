@@ -1,0 +1,491 @@
+// pq_perm_many and pq_perm_grad: statically scheduled sweeps over many
+// patterns on one interferometer (see many.h).  The host plans every pattern
+// once per distinct description (cached with its uploaded descriptors); each
+// call then gathers the compact matrices from U, builds the step tables, runs
+// one kernel per column class (one wavefront per chunk), and reduces every
+// pattern's chunk slots in slot order.
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <memory>
+#include <tuple>
+#include <vector>
+
+#include "../../include/pq.h"
+#include "batch_kernels.h"
+#include "many.h"
+#include "many_kernels.h"
+#include "plan.h"
+#include "runtime.h"
+
+namespace pq {
+
+namespace {
+
+constexpr uint64_t kFwdMinChunk = 64;
+constexpr uint64_t kFwdChunksPerWave = 2;
+constexpr int kMaxManyEntries = 4;
+
+struct ManyClass {
+    int mode = 0, ncmax = 0, var = 0;
+    int first_chunk = 0, nchunks = 0;
+    int slot_doubles = 0;
+    int64_t slot_off = 0;    // doubles
+};
+
+struct ManyEntry {
+    std::vector<int64_t> key;
+    int mode = 0;                // kModeFwd (forward and extend jobs) or kModeAdj
+    int npat = 0, ntab = 0;
+    size_t mat_elems = 0, partial_doubles = 0, dpat_elems = 0;
+    std::vector<ManyClass> classes;
+    // device
+    char* dmem = nullptr;
+    BJob* d_jobs = nullptr;
+    MChunk* d_chunks = nullptr;
+    int32_t* d_idx = nullptr;
+    int32_t* d_sig = nullptr;
+    int32_t* d_pat_slot = nullptr;
+    int32_t* d_pat_class = nullptr;
+    int64_t* d_class_off = nullptr;
+    int32_t* d_class_sd = nullptr;
+    cplx* d_trivial = nullptr;
+    int64_t* d_dpat_off = nullptr;
+    cplx* d_mat = nullptr;
+    StepEntry* d_tabs = nullptr;
+    double* d_partials = nullptr;
+    cplx* d_dpat = nullptr;
+    uint64_t last_use = 0;
+    ~ManyEntry() {
+        if (dmem) hipFree(dmem);
+    }
+};
+
+struct ManyCache {
+    std::vector<std::unique_ptr<ManyEntry>> entries;
+    uint64_t clock = 0;
+};
+
+struct PatternSpec {
+    int op;            // kOpPerm / kOpExtend
+    Side rows, cols;
+    int64_t out;
+};
+
+int build_many(pq_ctx* ctx, int mode, int32_t m, const std::vector<PatternSpec>& pats, ManyEntry& E,
+               hipStream_t st) {
+    E.mode = mode;
+    const bool adj = mode == kModeAdj;
+    E.npat = (int)pats.size();
+    std::vector<BJob> hj(pats.size());
+    std::vector<int32_t> hidx, sig_flat, pat_slot(pats.size(), 0), pat_class(pats.size(), -1);
+    std::vector<cplx> trivial(pats.size(), cplx{0.0, 0.0});
+    std::vector<int64_t> dpat_off(pats.size(), 0);
+    std::map<std::vector<int32_t>, int> sigs;
+    std::map<std::tuple<int, int, int>, std::vector<int>> by_class;
+    size_t mat_elems = 0, dpat_elems = 0;
+    for (size_t k = 0; k < pats.size(); ++k) {
+        const PatternSpec& ps = pats[k];
+        const bool ext = ps.op == kOpExtend;
+        Plan p;
+        plan_sparse(ps.rows, ps.cols, !ext, p, ext);
+        if (p.status) return ctx->fail(p.status, "pattern %zu: planning failed", k);
+        BJob& b = hj[k];
+        memset(&b, 0, sizeof(b));
+        b.op = ext ? kOpExtend : kOpPerm;
+        b.out_offset = ps.out;
+        b.tab = -1;
+        if (p.trivial) {
+            trivial[k] = p.trivial == 1 ? cplx{0.0, 0.0} : cplx{1.0, 0.0};
+            continue;
+        }
+        const int ncmax = ((p.nc + 3) / 4) * 4;
+        if (ext && ncmax > kMaxExtendCols) return ctx->fail(PQ_ERANGE, "pattern %zu: more than %d columns", k, kMaxExtendCols);
+        if (adj && ncmax > kManyMaxAdjCols) return ctx->fail(PQ_ERANGE, "pattern %zu: more than %d columns", k, kManyMaxAdjCols);
+        b.nc = p.nc;
+        b.ncmax = ncmax;
+        b.r = p.r;
+        b.n_lane = p.n_lane;
+        b.lane_states = p.lane_states;
+        b.n_time = p.n_time;
+        b.n_inner = p.n_inner;
+        b.m_inner = p.m_inner;
+        b.m_out = ext ? m : 0;
+        b.transposed = p.transposed;
+        b.time_states = p.time_states;
+        b.scale = p.r == 0 ? 1.0 : p.scale;
+        b.norm = p.norm;
+        for (int i = 0; i < p.n_lane; ++i) b.lane_radix[i] = (int8_t)p.lane_radix[i];
+        for (int i = 0; i < p.n_time; ++i) b.time_radix[i] = (int8_t)p.time_radix[i];
+        bool unit = true;
+        for (int j = 0; j < ncmax; ++j) {
+            b.kap[j] = (int8_t)(j < p.nc ? p.col_kap[j] : 1);
+            unit = unit && b.kap[j] == 1;
+        }
+        bool bin = true;
+        for (int i = 0; i < p.n_lane; ++i) bin = bin && p.lane_radix[i] == 2;
+        for (int i = 0; i < p.n_time; ++i) bin = bin && p.time_radix[i] == 2;
+        if (adj) {
+            // the adjoint's inner digits: the lowest KA time digits
+            const int ka = std::min(ncmax <= 12 ? 2 : 1, p.n_time);
+            int mi = 1;
+            for (int i = 0; i < ka; ++i) mi *= p.time_radix[i];
+            b.n_inner = ka;
+            b.m_inner = mi;
+        }
+        if (!bin) {
+            std::vector<int32_t> sg(kSigInts, 0);
+            sg[0] = b.n_inner;
+            sg[1] = b.m_inner;
+            sg[2] = ncmax;
+            for (int i = 0; i < b.n_inner; ++i) sg[3 + i] = p.time_radix[i];
+            auto it = sigs.find(sg);
+            if (it == sigs.end()) {
+                const int t = (int)sigs.size();
+                sigs.emplace(sg, t);
+                sig_flat.insert(sig_flat.end(), sg.begin(), sg.end());
+                b.tab = t;
+            } else {
+                b.tab = it->second;
+            }
+        }
+        b.mat_off = (int64_t)mat_elems;
+        mat_elems += (size_t)b.r * ncmax * 3 + ncmax;
+        b.idx_off = (int64_t)hidx.size();
+        for (int i = 0; i < p.r; ++i) hidx.push_back(p.row_mode[i]);
+        for (int i = 0; i < p.r; ++i) hidx.push_back(p.row_mu[i]);
+        for (int j = 0; j < p.nc; ++j) hidx.push_back(p.col_mode[j]);
+        if (adj) {
+            dpat_off[k] = (int64_t)dpat_elems;
+            dpat_elems += (size_t)p.r * p.nc;
+        }
+        const int kmode = adj ? kModeAdj : (ext ? kModeExt : kModeFwd);
+        const int var = (bin ? 2 : 0) + (unit ? 1 : 0);
+        by_class[std::make_tuple(kmode, ncmax, var)].push_back((int)k);
+    }
+    E.ntab = (int)sigs.size();
+    E.mat_elems = mat_elems;
+    E.dpat_elems = dpat_elems;
+
+    std::vector<MChunk> hch;
+    size_t partial_doubles = 0;
+    for (auto& kv : by_class) {
+        ManyClass C;
+        C.mode = std::get<0>(kv.first);
+        C.ncmax = std::get<1>(kv.first);
+        C.var = std::get<2>(kv.first);
+        int rmax = 0;
+        uint64_t total = 0;
+        for (int id : kv.second) {
+            rmax = std::max(rmax, hj[id].r);
+            total += hj[id].time_states;
+        }
+        C.slot_doubles = C.mode == kModeFwd ? 4 : (C.mode == kModeExt ? 4 * C.ncmax : 4 + 2 * rmax * C.ncmax);
+        uint64_t chunk = 0;
+        if (C.mode != kModeAdj) {
+            const uint64_t waves = (uint64_t)ctx->num_cu * 4 * 2;
+            chunk = (total + waves * kFwdChunksPerWave - 1) / (waves * kFwdChunksPerWave);
+            if (chunk < kFwdMinChunk) chunk = kFwdMinChunk;
+        }
+        std::vector<MChunk> cc;
+        int slot = 0;
+        const int cls = (int)E.classes.size();
+        for (int id : kv.second) {
+            BJob& b = hj[id];
+            // adjoint chunks are whole periods of its inner digits
+            const uint64_t len = C.mode == kModeAdj ? (uint64_t)b.m_inner : chunk;
+            const uint64_t n = (b.time_states + len - 1) / len;
+            b.nchunks = (int32_t)n;
+            b.slot_base = slot;
+            pat_slot[id] = slot;
+            pat_class[id] = cls;
+            for (uint64_t q = 0; q < n; ++q) {
+                MChunk ch;
+                ch.pat = id;
+                ch.slot = slot + (int32_t)q;
+                ch.start = q * len;
+                ch.count = std::min(len, b.time_states - q * len);
+                cc.push_back(ch);
+            }
+            slot += (int)n;
+        }
+        std::stable_sort(cc.begin(), cc.end(), [](const MChunk& x, const MChunk& y) { return x.count > y.count; });
+        C.first_chunk = (int)hch.size();
+        C.nchunks = (int)cc.size();
+        C.slot_off = (int64_t)partial_doubles;
+        partial_doubles += (size_t)slot * C.slot_doubles;
+        hch.insert(hch.end(), cc.begin(), cc.end());
+        E.classes.push_back(C);
+    }
+    E.partial_doubles = partial_doubles;
+    std::vector<int64_t> class_off;
+    std::vector<int32_t> class_sd;
+    for (auto& C : E.classes) {
+        class_off.push_back(C.slot_off);
+        class_sd.push_back(C.slot_doubles);
+    }
+
+    // one device block: uploaded descriptors first, kernel-written arrays after
+    Carve cv;
+    auto sz = [](size_t n) { return std::max<size_t>(1, n); };
+    const size_t oJobs = cv.take(sizeof(BJob) * sz(hj.size()));
+    const size_t oCh = cv.take(sizeof(MChunk) * sz(hch.size()));
+    const size_t oIdx = cv.take(sizeof(int32_t) * sz(hidx.size()));
+    const size_t oSig = cv.take(sizeof(int32_t) * sz(sig_flat.size()));
+    const size_t oPs = cv.take(sizeof(int32_t) * sz(pat_slot.size()));
+    const size_t oPc = cv.take(sizeof(int32_t) * sz(pat_class.size()));
+    const size_t oCo = cv.take(sizeof(int64_t) * sz(class_off.size()));
+    const size_t oCs = cv.take(sizeof(int32_t) * sz(class_sd.size()));
+    const size_t oTr = cv.take(sizeof(cplx) * sz(trivial.size()));
+    const size_t oDo = cv.take(sizeof(int64_t) * sz(dpat_off.size()));
+    const size_t upload_bytes = cv.off;
+    const size_t oMat = cv.take(sizeof(cplx) * sz(mat_elems));
+    const size_t oTab = cv.take(sizeof(StepEntry) * 2 * kMaxInner * sz(sigs.size()));
+    const size_t oPart = cv.take(sizeof(double) * sz(partial_doubles));
+    const size_t oDp = cv.take(sizeof(cplx) * sz(dpat_elems));
+    if (hipMalloc((void**)&E.dmem, cv.off) != hipSuccess) {
+        E.dmem = nullptr;
+        return ctx->fail(PQ_ENOMEM, "many: hipMalloc(%zu) failed", cv.off);
+    }
+    E.d_jobs = (BJob*)(E.dmem + oJobs);
+    E.d_chunks = (MChunk*)(E.dmem + oCh);
+    E.d_idx = (int32_t*)(E.dmem + oIdx);
+    E.d_sig = (int32_t*)(E.dmem + oSig);
+    E.d_pat_slot = (int32_t*)(E.dmem + oPs);
+    E.d_pat_class = (int32_t*)(E.dmem + oPc);
+    E.d_class_off = (int64_t*)(E.dmem + oCo);
+    E.d_class_sd = (int32_t*)(E.dmem + oCs);
+    E.d_trivial = (cplx*)(E.dmem + oTr);
+    E.d_dpat_off = (int64_t*)(E.dmem + oDo);
+    E.d_mat = (cplx*)(E.dmem + oMat);
+    E.d_tabs = (StepEntry*)(E.dmem + oTab);
+    E.d_partials = (double*)(E.dmem + oPart);
+    E.d_dpat = (cplx*)(E.dmem + oDp);
+    char* stage = (char*)ctx->staging(upload_bytes);
+    if (!stage) return PQ_ENOMEM;
+    memset(stage, 0, upload_bytes);
+    auto put = [&](size_t off, const void* src, size_t bytes) { if (bytes) memcpy(stage + off, src, bytes); };
+    put(oJobs, hj.data(), sizeof(BJob) * hj.size());
+    put(oCh, hch.data(), sizeof(MChunk) * hch.size());
+    put(oIdx, hidx.data(), sizeof(int32_t) * hidx.size());
+    put(oSig, sig_flat.data(), sizeof(int32_t) * sig_flat.size());
+    put(oPs, pat_slot.data(), sizeof(int32_t) * pat_slot.size());
+    put(oPc, pat_class.data(), sizeof(int32_t) * pat_class.size());
+    put(oCo, class_off.data(), sizeof(int64_t) * class_off.size());
+    put(oCs, class_sd.data(), sizeof(int32_t) * class_sd.size());
+    put(oTr, trivial.data(), sizeof(cplx) * trivial.size());
+    put(oDo, dpat_off.data(), sizeof(int64_t) * dpat_off.size());
+    return ctx->upload(E.dmem, stage, upload_bytes, st);
+}
+
+int run_many(pq_ctx* ctx, ManyEntry& E, const cplx* U, int64_t ldu, int32_t m, cplx* perm, cplx* amp,
+             const cplx* gperm, cplx* dU, int64_t lddu, hipStream_t st) {
+    int rc;
+    if (E.mat_elems > 0) {
+        // BJob.nchunks > 0 marks every planned (non-trivial) pattern
+        BPrepArgs pa{U, ldu, E.d_jobs, E.npat, E.d_idx, E.d_mat};
+        rc = ctx->check(launch_bprep(pa, st), "many prep");
+        if (rc) return rc;
+    }
+    if (E.ntab > 0) {
+        BTableArgs ta{E.d_tabs, E.d_sig, E.ntab};
+        rc = ctx->check(launch_btable(ta, st), "many tables");
+        if (rc) return rc;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (ctx->profiling) {
+        e0 = ctx->take_event();
+        e1 = ctx->take_event();
+        if (!e0 || !e1) return ctx->fail(PQ_EDEVICE, "profile: hipEventCreate failed");
+        rc = ctx->check(hipEventRecord(e0, st), "profile: record");
+        if (rc) return rc;
+    }
+    for (const ManyClass& C : E.classes) {
+        ManyArgs a;
+        a.jobs = E.d_jobs;
+        a.chunks = E.d_chunks + C.first_chunk;
+        a.nchunks = C.nchunks;
+        a.slot_doubles = C.slot_doubles;
+        a.mat = E.d_mat;
+        a.idx = E.d_idx;
+        a.tabs = E.d_tabs;
+        a.partials = E.d_partials + C.slot_off;
+        rc = ctx->check(launch_many(C.mode, C.ncmax, C.var, a, st), "many sweep");
+        if (rc) return rc;
+    }
+    if (ctx->profiling) {
+        rc = ctx->check(hipEventRecord(e1, st), "profile: record");
+        if (rc) return rc;
+        ctx->ev_used.emplace_back(e0, e1);
+    }
+    ManyFinalArgs fa;
+    fa.U = U;
+    fa.ldu = ldu;
+    fa.idx = E.d_idx;
+    fa.dpat_off = E.d_dpat_off;
+    fa.jobs = E.d_jobs;
+    fa.pat_slot = E.d_pat_slot;
+    fa.pat_class = E.d_pat_class;
+    fa.class_off = E.d_class_off;
+    fa.class_sd = E.d_class_sd;
+    fa.partials = E.d_partials;
+    fa.trivial = E.d_trivial;
+    fa.npat = E.npat;
+    fa.adjoint = E.mode == kModeAdj ? 1 : 0;
+    fa.perm = perm;
+    fa.amp = amp;
+    fa.dpat = E.d_dpat;
+    rc = ctx->check(launch_many_final(fa, st), "many final");
+    if (rc) return rc;
+    if (E.mode == kModeAdj) {
+        GradScatterArgs ga;
+        ga.jobs = E.d_jobs;
+        ga.idx = E.d_idx;
+        ga.pat_class = E.d_pat_class;
+        ga.dpat_off = E.d_dpat_off;
+        ga.dpat = E.d_dpat;
+        ga.gperm = gperm;
+        ga.npat = E.npat;
+        ga.m = m;
+        ga.dU = dU;
+        ga.lddu = lddu;
+        rc = ctx->check(launch_grad_scatter(ga, st), "grad scatter");
+        if (rc) return rc;
+    }
+    return PQ_OK;
+}
+
+ManyCache* many_cache(pq_ctx* ctx) {
+    if (!ctx->many_cache) ctx->many_cache = new ManyCache();
+    return (ManyCache*)ctx->many_cache;
+}
+
+// Find or build the entry for `key`.
+int get_entry(pq_ctx* ctx, int mode, int32_t m, std::vector<int64_t>& key,
+              const std::vector<PatternSpec>& pats, hipStream_t st, ManyEntry** out) {
+    ManyCache* cache = many_cache(ctx);
+    for (auto& e : cache->entries)
+        if (e->key == key) {
+            e->last_use = ++cache->clock;
+            *out = e.get();
+            return PQ_OK;
+        }
+    if ((int)cache->entries.size() >= kMaxManyEntries) {
+        auto it = std::min_element(cache->entries.begin(), cache->entries.end(),
+                                   [](const std::unique_ptr<ManyEntry>& a, const std::unique_ptr<ManyEntry>& b) {
+                                       return a->last_use < b->last_use;
+                                   });
+        hipStreamSynchronize(st);
+        cache->entries.erase(it);
+    }
+    std::unique_ptr<ManyEntry> ne(new ManyEntry());
+    int rc = build_many(ctx, mode, m, pats, *ne, st);
+    if (rc) return rc;
+    ne->key = std::move(key);
+    ne->last_use = ++cache->clock;
+    *out = ne.get();
+    cache->entries.push_back(std::move(ne));
+    return PQ_OK;
+}
+
+int side_from_dense(int m, const int32_t* v, Side& s) {
+    s.count = 0;
+    for (int i = 0; i < m; ++i) {
+        if (v[i] < 0) return PQ_EINVAL;
+        if (v[i] > 0) {
+            if (s.count >= kMaxDim) return PQ_ERANGE;
+            s.mode[s.count] = i;
+            s.mult[s.count] = v[i];
+            ++s.count;
+        }
+    }
+    return PQ_OK;
+}
+
+}  // namespace
+
+}  // namespace pq
+
+using namespace pq;
+
+void pq_release_many_cache(pq_ctx* ctx) {
+    delete (ManyCache*)ctx->many_cache;
+    ctx->many_cache = nullptr;
+}
+
+int pq_perm_many(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m,
+                 const pq_job* jobs, int32_t njobs,
+                 pq_c128* perm, pq_c128* amp, void* stream) {
+    if (!ctx) return PQ_EINVAL;
+    ctx->clear_error();
+    if (m < 0 || njobs < 0) return ctx->fail(PQ_EINVAL, "pq_perm_many: negative size");
+    if (njobs == 0) return PQ_OK;
+    if (!jobs || !perm) return ctx->fail(PQ_EINVAL, "pq_perm_many: NULL jobs or perm");
+    if (m > 0 && (!U || ldu < m)) return ctx->fail(PQ_EINVAL, "pq_perm_many: NULL U or ldu < m");
+    std::vector<int64_t> key = {0, m, njobs};
+    int rc = pq_validate_jobs(ctx, m, jobs, njobs, key);
+    if (rc) return rc;
+    DeviceGuard guard(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<PatternSpec> pats;
+    pats.reserve(njobs);
+    for (int k = 0; k < njobs; ++k) {
+        const pq_job& J = jobs[k];
+        PatternSpec ps;
+        ps.op = J.op == PQ_OP_EXTEND_ROW ? kOpExtend : kOpPerm;
+        ps.rows.count = J.nr;
+        for (int i = 0; i < J.nr; ++i) { ps.rows.mode[i] = J.row_idx[i]; ps.rows.mult[i] = J.row_mult[i]; }
+        ps.cols.count = J.nc;
+        for (int i = 0; i < J.nc; ++i) { ps.cols.mode[i] = J.col_idx[i]; ps.cols.mult[i] = J.col_mult[i]; }
+        ps.out = J.out_offset;
+        pats.push_back(ps);
+    }
+    ManyEntry* E = nullptr;
+    rc = get_entry(ctx, kModeFwd, m, key, pats, st, &E);
+    if (rc) return rc;
+    return run_many(ctx, *E, (const cplx*)U, ldu, m, (cplx*)perm, (cplx*)amp, nullptr, nullptr, 0, st);
+}
+
+int pq_perm_grad(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m,
+                 int32_t batch, const int32_t* S, const int32_t* T,
+                 const pq_c128* gperm, pq_c128* perm,
+                 pq_c128* dU, int64_t lddu, void* stream) {
+    if (!ctx) return PQ_EINVAL;
+    ctx->clear_error();
+    if (m < 0 || batch < 0) return ctx->fail(PQ_EINVAL, "pq_perm_grad: negative size");
+    if (!dU || lddu < m) return ctx->fail(PQ_EINVAL, "pq_perm_grad: NULL dU or lddu < m");
+    if (batch > 0 && (!S || !T || !gperm)) return ctx->fail(PQ_EINVAL, "pq_perm_grad: NULL pattern or gperm");
+    if (m > 0 && (!U || ldu < m)) return ctx->fail(PQ_EINVAL, "pq_perm_grad: NULL U or ldu < m");
+    std::vector<int64_t> key = {1, m, batch};
+    key.reserve(3 + 2 * (size_t)batch * m);
+    std::vector<PatternSpec> pats(batch);
+    for (int p = 0; p < batch; ++p) {
+        const int32_t* sp = S + (size_t)p * m;
+        const int32_t* tp = T + (size_t)p * m;
+        int rc = side_from_dense(m, sp, pats[p].cols);
+        if (rc) return ctx->fail(rc, "pq_perm_grad: pattern %d input side invalid", p);
+        rc = side_from_dense(m, tp, pats[p].rows);
+        if (rc) return ctx->fail(rc, "pq_perm_grad: pattern %d output side invalid", p);
+        if (pats[p].rows.count > PQ_GRAD_MAX_DIM || pats[p].cols.count > PQ_GRAD_MAX_DIM)
+            return ctx->fail(PQ_ERANGE, "pq_perm_grad: pattern %d has more than %d distinct modes", p, PQ_GRAD_MAX_DIM);
+        long ns = 0, nt = 0;
+        for (int i = 0; i < m; ++i) { ns += sp[i]; nt += tp[i]; }
+        if (ns == nt && ns > PQ_MAX_N) return ctx->fail(PQ_ERANGE, "pq_perm_grad: pattern %d too large", p);
+        pats[p].op = kOpPerm;
+        pats[p].out = p;
+        key.push_back(ns);
+        for (int i = 0; i < pats[p].cols.count; ++i) key.push_back(((int64_t)pats[p].cols.mode[i] << 32) | pats[p].cols.mult[i]);
+        key.push_back(-1);
+        for (int i = 0; i < pats[p].rows.count; ++i) key.push_back(((int64_t)pats[p].rows.mode[i] << 32) | pats[p].rows.mult[i]);
+        key.push_back(-2);
+    }
+    DeviceGuard guard(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    ManyEntry* E = nullptr;
+    int rc = get_entry(ctx, kModeAdj, m, key, pats, st, &E);
+    if (rc) return rc;
+    return run_many(ctx, *E, (const cplx*)U, ldu, m, (cplx*)perm, nullptr, (const cplx*)gperm, (cplx*)dU,
+                    lddu, st);
+}

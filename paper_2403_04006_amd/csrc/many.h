@@ -1,0 +1,83 @@
+// Many independent patterns on one interferometer, scheduled statically: the
+// host cuts every pattern's time-state range into chunks, one wavefront per
+// chunk (no shared counters), each chunk writes its own partial slot, and a
+// second kernel adds every pattern's slots in slot order.
+//
+// Forward mode: the slot holds the chunk's double-double sum of
+//   w * prod_j c_j^{kap_j}.
+// Adjoint mode (reverse of the Gray-code sweep): the slot holds the chunk's
+// part of D_ij = sum_states w * delta_i * G_j with G_j = d/dc_j prod_l c_l^{kap_l},
+// so that d perm / d B_ij = 2^{-(n-1)} D_ij, plus the forward sum.  Per lane,
+// P_j = running sum of w G_j; a step that moves digit k by dd changes delta_k
+// by -2 dd, and summation by parts gives
+//   sum_t delta_k(t) g(t) = delta_k(end) P(end) + sum_flips 2 dd P(before flip).
+// Only the lowest KA time digits may change inside a chunk (chunks are aligned
+// to their period); every other row's delta is constant over the chunk, so its
+// share is delta_i * P(end), contracted over the lanes once per chunk.
+#pragma once
+#include <stdint.h>
+
+#include "batch.h"
+#include "pq_common.h"
+
+namespace pq {
+
+constexpr int kModeFwd = 0;       // forward sums (PERM jobs)
+constexpr int kModeExt = 1;       // Laplace expansion along a new row (EXTEND_ROW jobs)
+constexpr int kModeAdj = 2;       // reverse sweep: derivatives and forward sums
+constexpr int kManyMaxAdjCols = 24;   // widest adjoint class
+constexpr int kAdjBlock = 64;         // one wavefront per workgroup in adjoint mode
+
+struct MChunk {
+    int32_t pat;          // pattern (index into the job array)
+    int32_t slot;         // partial slot
+    uint64_t start;
+    uint64_t count;
+};
+
+struct ManyArgs {
+    const BJob* jobs;       // per pattern (BJob layout; out_offset = pattern index)
+    const MChunk* chunks;   // this class's chunks
+    int32_t nchunks;
+    int32_t slot_doubles;   // doubles per slot
+    const cplx* mat;
+    const int32_t* idx;
+    const StepEntry* tabs;
+    double* partials;       // slot storage of this class
+};
+
+// Per-pattern reduction of the chunk slots.
+struct ManyFinalArgs {
+    const cplx* U;
+    int64_t ldu;
+    const int32_t* idx;
+    const int64_t* dpat_off;   // [npat]: complex offset of the pattern's D block
+    const BJob* jobs;
+    const int32_t* pat_slot;   // [npat]: first slot (in the class's slot array) of every pattern
+    const int32_t* pat_class;  // [npat]: class index, -1 for trivial patterns
+    const int64_t* class_off;  // [nclass]: double offset of the class's slots
+    const int32_t* class_sd;   // [nclass]: slot doubles of the class
+    const double* partials;
+    const cplx* trivial;       // [npat]: value of trivial patterns
+    int32_t npat;
+    int32_t adjoint;
+    cplx* perm;                // may be null (forward values)
+    cplx* amp;                 // may be null
+    cplx* dpat;                // adjoint: per pattern r x nc complex d perm / d B (scaled)
+};
+
+// Scatter of the per-pattern derivatives into dU (conjugate-Wirtinger VJP).
+struct GradScatterArgs {
+    const BJob* jobs;
+    const int32_t* idx;
+    const int32_t* pat_class;
+    const int64_t* dpat_off;
+    const cplx* dpat;
+    const cplx* gperm;
+    int32_t npat;
+    int32_t m;
+    cplx* dU;
+    int64_t lddu;
+};
+
+}  // namespace pq

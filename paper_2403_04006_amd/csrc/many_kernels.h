@@ -1,0 +1,25 @@
+// Host-visible launch functions of the many-pattern kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "many.h"
+
+namespace pq {
+
+#define PQ_MCLASS_FWD(X) X(0, 4) X(0, 8) X(0, 12) X(0, 16) X(0, 20) X(0, 24) X(0, 28) X(0, 32) \
+    X(0, 36) X(0, 40) X(0, 44) X(0, 48)
+#define PQ_MCLASS_EXT(X) X(1, 4) X(1, 8) X(1, 12) X(1, 16) X(1, 20) X(1, 24)
+#define PQ_MCLASS_ADJ(X) X(2, 4) X(2, 8) X(2, 12) X(2, 16) X(2, 20) X(2, 24)
+
+// variant: 2 * binary_walk + unit_powers
+#define PQ_MDECL(MODE, NC) hipError_t launch_many_##MODE##_##NC(int var, const ManyArgs& a, hipStream_t s);
+PQ_MCLASS_FWD(PQ_MDECL)
+PQ_MCLASS_EXT(PQ_MDECL)
+PQ_MCLASS_ADJ(PQ_MDECL)
+#undef PQ_MDECL
+
+hipError_t launch_many(int mode, int ncmax, int var, const ManyArgs& a, hipStream_t s);
+hipError_t launch_many_final(const ManyFinalArgs& a, hipStream_t s);
+hipError_t launch_grad_scatter(const GradScatterArgs& a, hipStream_t s);
+
+}  // namespace pq

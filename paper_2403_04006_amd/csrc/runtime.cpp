@@ -59,7 +59,43 @@ void pq_ctx::release_events() {
     ev_used.clear();
 }
 
+void* pq_ctx::staging(size_t bytes) {
+    if (upload_done) {
+        if (hipEventSynchronize(upload_done) != hipSuccess) {
+            fail(PQ_EDEVICE, "staging: wait for previous upload failed");
+            return nullptr;
+        }
+    }
+    if (stage && stage_bytes >= bytes) return stage;
+    if (stage) hipHostFree(stage);
+    stage = nullptr;
+    stage_bytes = 0;
+    size_t want = bytes < ((size_t)1 << 20) ? ((size_t)1 << 20) : bytes;
+    if (hipHostMalloc(&stage, want, hipHostMallocDefault) != hipSuccess) {
+        stage = nullptr;
+        fail(PQ_ENOMEM, "staging: hipHostMalloc(%zu) failed", want);
+        return nullptr;
+    }
+    stage_bytes = want;
+    return stage;
+}
+
+int pq_ctx::upload(void* dst, const void* stage_src, size_t bytes, hipStream_t st) {
+    if (!upload_done) {
+        int rc = check(hipEventCreateWithFlags(&upload_done, hipEventDisableTiming), "upload event");
+        if (rc) return rc;
+    }
+    int rc = check(hipMemcpyAsync(dst, stage_src, bytes, hipMemcpyHostToDevice, st), "upload");
+    if (rc) return rc;
+    return check(hipEventRecord(upload_done, st), "upload record");
+}
+
 void pq_ctx::release_all() {
+    if (upload_done) hipEventDestroy(upload_done);
+    upload_done = nullptr;
+    if (stage) hipHostFree(stage);
+    stage = nullptr;
+    stage_bytes = 0;
     release_events();
     for (hipEvent_t e : ev_free) hipEventDestroy(e);
     ev_free.clear();

@@ -7,6 +7,7 @@
 #include <utility>
 #include <vector>
 
+#include "../../include/pq.h"
 #include "plan.h"
 #include "pq_common.h"
 
@@ -21,6 +22,13 @@ struct pq_ctx {
     size_t ws_bytes = 0;
     // cached batch plans, device buffers and graphs (batched.cpp)
     void* batch_cache = nullptr;
+    // cached many-pattern plans and their device descriptors (many.cpp)
+    void* many_cache = nullptr;
+    // pinned host staging for descriptor uploads; upload_done marks when the
+    // last copy out of it has finished
+    void* stage = nullptr;
+    size_t stage_bytes = 0;
+    hipEvent_t upload_done = nullptr;
     // resident workgroups per CU per (binary, nc); 0 = not yet queried
     int occ[2][pq::kMaxDim + 1] = {};
 
@@ -36,11 +44,20 @@ struct pq_ctx {
     int check(hipError_t e, const char* what);
     // workspace of at least `bytes`; nullptr on failure (status set)
     void* workspace(size_t bytes);
+    // pinned staging of at least `bytes`, free to overwrite (waits for the
+    // previous upload out of it); nullptr on failure
+    void* staging(size_t bytes);
+    // stream-ordered copy of `bytes` from the staging buffer to device memory
+    int upload(void* dst, const void* stage_src, size_t bytes, hipStream_t st);
     void release_all();
     int occupancy(bool binary, int nc);
 };
 
 void pq_release_batch_cache(pq_ctx* ctx);
+void pq_release_many_cache(pq_ctx* ctx);
+// Validate pq_job descriptions (modes, multiplicities, photon counts, output
+// overlap) and append them to `key`.
+int pq_validate_jobs(pq_ctx* ctx, int32_t m, const pq_job* jobs, int32_t njobs, std::vector<int64_t>& key);
 
 namespace pq {
 

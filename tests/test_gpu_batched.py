@@ -5,7 +5,14 @@ import pytest
 import oracle
 import workloads
 
-pytestmark = pytest.mark.gpu
+# The persistent work-queue path of pq_perm_batched hung on its first GPU run
+# (graph-captured batch of 495 small permanents, killed for silence; the GPU
+# kept answering).  CPU emulation of the same host planning and kernels, with
+# 64-lane wavefronts and with concurrent wavefronts, completes with correct
+# results, so the cause is not shown; the path is switched off in the library
+# (pq_perm_batched returns PQ_EDEVICE) and these tests stay off the GPU.
+pytestmark = [pytest.mark.gpu, pytest.mark.skip(
+    reason="persistent batched work-queue path hung on its first GPU run; cause not shown, path disabled")]
 
 torch = pytest.importorskip("torch")
 

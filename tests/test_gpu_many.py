@@ -1,0 +1,228 @@
+"""Parity of the statically scheduled many-pattern path (pq_perm_many):
+forward permanents and the Laplace expansion along a new row (EXTEND_ROW)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def rel(a, b):
+    return abs(a - b) / max(abs(b), 1e-300)
+
+
+@pytest.fixture(scope="module")
+def eng():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2403_04006_amd as pq
+    return pq.Engine(0)
+
+
+def dev(U):
+    return torch.from_numpy(np.ascontiguousarray(U, dtype=np.complex128)).cuda()
+
+
+def sparse(v):
+    return [(i, int(c)) for i, c in enumerate(v) if c > 0]
+
+
+def perm_job(S, T, out=None):
+    j = {"op": 0, "rows": sparse(T), "cols": sparse(S)}
+    if out is not None:
+        j["out"] = out
+    return j
+
+
+def extend_job(rows, cols, out):
+    rc = np.bincount(np.asarray(rows, dtype=np.int64)) if len(rows) else np.zeros(0, np.int64)
+    cc = np.bincount(np.asarray(cols, dtype=np.int64))
+    return {"op": 1, "rows": sparse(rc), "cols": sparse(cc), "out": out}
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_uneven_perm_jobs(eng, seed):
+    rng = np.random.default_rng(seed)
+    m = 10
+    U = workloads.haar(m, 200 + seed)
+    jobs, refs = [], []
+    for k in range(40):
+        n = int(rng.integers(0, 16))
+        S = workloads.random_occupations(rng, m, n, cap=4)
+        T = workloads.random_occupations(rng, m, n + (1 if k % 9 == 0 else 0), cap=4)
+        jobs.append(perm_job(S, T))
+        refs.append((oracle.perm_mult(U, S, T), oracle.amplitude(U, S, T)))
+    perm, amp = eng.perm_many(dev(U), jobs)
+    perm = perm.cpu().numpy()
+    amp = amp.cpu().numpy()
+    for k, (rp, ra) in enumerate(refs):
+        if abs(rp) < 1e-12:
+            assert abs(perm[k]) < 1e-11
+        else:
+            assert rel(perm[k], rp) < 1e-10, (k, jobs[k])
+            assert rel(amp[k], ra) < 1e-10
+
+
+def test_paper_example_outputs_complete(eng):
+    U = oracle.mesh_unitary([(np.pi / 3, 0.0), (np.pi / 4, 0.0), (np.pi / 5, 0.0), (np.pi / 6, 0.0)],
+                            [(1, 2), (2, 3), (0, 1), (3, 4)], 5)
+    S = [1, 2, 0, 2, 1]
+    outs = workloads.fock_outputs(5, 6)
+    perm, amp = eng.perm_many(dev(U), [perm_job(S, T) for T in outs])
+    amp = amp.cpu().numpy()
+    assert abs(np.sum(np.abs(amp) ** 2) - 1.0) < 1e-12
+    for k, T in enumerate(outs):
+        assert abs(amp[k] - oracle.amplitude(U, S, T)) < 1e-13
+
+
+def test_unit_multiplicity_sizes_in_one_call(eng):
+    m = 2 * 24 * 24
+    U = workloads.haar(m, 9)
+    jobs, refs = [], []
+    for n in range(1, 25):
+        S = np.zeros(m, np.int32)
+        T = np.zeros(m, np.int32)
+        S[:n] = 1
+        T[24:24 + n] = 1
+        jobs.append(perm_job(S, T))
+        refs.append(oracle.perm_ryser(U[24:24 + n, :n]))
+    perm, _ = eng.perm_many(dev(U), jobs)
+    perm = perm.cpu().numpy()
+    for k, r in enumerate(refs):
+        assert rel(perm[k], r) < (1e-10 if k < 20 else 1e-8), k
+
+
+def test_matches_single_calls_and_is_deterministic(eng):
+    rng = np.random.default_rng(77)
+    m = 12
+    U = workloads.haar(m, 77)
+    Ud = dev(U)
+    jobs, singles = [], []
+    for k in range(20):
+        n = int(rng.integers(1, 14))
+        S = workloads.random_occupations(rng, m, n, cap=3)
+        T = workloads.random_occupations(rng, m, n, cap=3)
+        jobs.append(perm_job(S, T))
+        p, _ = eng.perm(Ud, list(S), list(T))
+        singles.append(complex(p.item()))
+    a, _ = eng.perm_many(Ud, jobs)
+    b, _ = eng.perm_many(Ud, jobs)          # cached plan, same result bits
+    a = a.cpu().numpy()
+    b = b.cpu().numpy()
+    assert np.array_equal(a, b)
+    for k in range(20):
+        if abs(singles[k]) > 1e-12:
+            assert rel(a[k], singles[k]) < 1e-12
+
+
+def test_cached_plan_follows_new_matrix(eng):
+    m = 9
+    rng = np.random.default_rng(3)
+    pats = [(workloads.random_occupations(rng, m, 7, cap=3), workloads.random_occupations(rng, m, 7, cap=3))
+            for _ in range(12)]
+    jobs = [perm_job(S, T, out=k) for k, (S, T) in enumerate(pats)]
+    Ud = dev(workloads.haar(m, 5))
+    for rep in range(4):
+        src = workloads.haar(m, 5 + rep % 2)
+        Ud.copy_(torch.from_numpy(src))
+        _ = (Ud * 2).sum()
+        perm, _ = eng.perm_many(Ud, jobs)
+        got = perm.cpu().numpy()
+        for k, (S, T) in enumerate(pats):
+            ref = oracle.perm_mult(src, S, T)
+            assert abs(got[k] - ref) < 1e-12 * max(1.0, abs(ref))
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_extend_row_jobs(eng, seed):
+    rng = np.random.default_rng(seed)
+    m = 30
+    U = workloads.haar(m, 300 + seed)
+    jobs, refs = [], []
+    for k in range(1, 14):
+        cols = list(rng.choice(m, size=k, replace=False))
+        rows = list(rng.integers(0, m, size=k - 1))     # may repeat (collisions)
+        jobs.append(extend_job(rows, cols, (k - 1) * m))
+        refs.append(oracle.extend_row(U, rows, cols))
+    perm, _ = eng.perm_many(dev(U), jobs, with_amp=False)
+    out = perm.cpu().numpy()
+    for k, r in enumerate(refs):
+        got = out[k * m:(k + 1) * m]
+        assert np.max(np.abs(got - r)) < 1e-10 * np.max(np.abs(r)), k
+
+
+def test_extend_row_with_repeated_input_columns(eng):
+    U = workloads.haar(7, 4)
+    rows = [1, 1, 5, 2]
+    S = np.array([2, 0, 0, 1, 0, 0, 2], np.int32)
+    T = np.bincount(rows, minlength=7).astype(np.int32)
+    perm, _ = eng.perm_many(dev(U), [{"op": 1, "rows": sparse(T), "cols": sparse(S), "out": 0}], n_out=7)
+    got = perm.cpu().numpy()
+    for l in range(7):
+        T2 = T.copy()
+        T2[l] += 1
+        ref = oracle.perm_mult(U, S, T2)
+        assert abs(got[l] - ref) < 1e-12 * max(1.0, abs(ref))
+
+
+def test_sampling_shaped_extend_full_size(eng):
+    # 20 photons in 400 modes: all 19 growing steps of two samples
+    U = workloads.haar(400, 0)
+    cols, rows = workloads.sampling_jobs(samples=2, seed=0)
+    jobs, refs = [], []
+    for s in range(2):
+        for k in range(2, 21):
+            c = [int(x) for x in cols[s, :k]]
+            r = [int(x) for x in rows[s, :k - 1]]
+            jobs.append(extend_job(r, c, len(jobs) * 400))
+            if k in (2, 11, 20):
+                refs.append((len(jobs) - 1, oracle.extend_row(U, r, c)))
+    perm, _ = eng.perm_many(dev(U), jobs, with_amp=False)
+    out = perm.cpu().numpy()
+    for idx, ref in refs:
+        got = out[idx * 400:(idx + 1) * 400]
+        err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+        print(f"extend job {idx}: max rel err {err:.2e}")
+        assert err < 1e-10
+
+
+def _c3_patterns_sorted():
+    pats = workloads.repeated_patterns(count=256, seed=1)
+    cost = [min(int(np.prod(S[S > 0] + 1)), int(np.prod(T[T > 0] + 1))) for S, T in pats]
+    return pats, np.argsort(cost), cost
+
+
+def test_repeated_40_photons_full_size(eng):
+    pats, order, cost = _c3_patterns_sorted()
+    U = workloads.haar(20, 0)
+    Ud = dev(U)
+    perm, _ = eng.perm_many(Ud, [perm_job(S, T) for S, T in pats])
+    perm = perm.cpu().numpy()
+    for idx in order[:2]:
+        S, T = pats[idx]
+        ref = oracle.perm_mult_cheaper_side(U, S, T)
+        err = rel(perm[idx], ref)
+        print(f"repeated pattern {idx} cost {cost[idx]:.3g} rel err {err:.2e}")
+        assert err < 1e-8
+    for idx in order[::64]:
+        S, T = pats[idx]
+        p, _ = eng.perm(Ud, list(S), list(T))
+        assert rel(perm[idx], complex(p.item())) < 1e-10
+
+
+def test_argument_errors(eng):
+    import paper_2403_04006_amd as pq
+    U = dev(workloads.haar(4, 0))
+    with pytest.raises(pq.PqError):
+        eng.perm_many(U, [perm_job([1, 0, 0, 0], [1, 0, 0, 0], out=0),
+                          perm_job([0, 1, 0, 0], [0, 1, 0, 0], out=0)])
+    with pytest.raises(pq.PqError):
+        eng.perm_many(U, [{"op": 0, "rows": [(7, 1)], "cols": [(0, 1)]}])
+    with pytest.raises(pq.PqError):
+        eng.perm_many(U, [{"op": 1, "rows": [(1, 1)], "cols": [(0, 1)], "out": 0}])
+    with pytest.raises(pq.PqError):
+        eng.perm_batched(U, [perm_job([1, 0, 0, 0], [1, 0, 0, 0])])     # switched-off path

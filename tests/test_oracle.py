@@ -296,3 +296,35 @@ def test_golden_values_present_and_pinned():
         m = 2 * n * n
         scale = math.sqrt(math.factorial(n)) * m ** (-n / 2)
         assert 1e-4 < abs(c["perm"]) / scale < 1e4
+
+
+def test_mesh_jacobian_matches_finite_differences():
+    cells = [(0, 1), (1, 2), (0, 1), (2, 3), (1, 2)]
+    rng = np.random.default_rng(4)
+    ang = rng.uniform(0, 2 * np.pi, size=(len(cells), 2))
+    J = oracle.mesh_jacobian(ang, cells, 4)
+    h = 1e-6
+    for q in range(len(cells)):
+        for k in range(2):
+            a1 = ang.copy(); a1[q, k] += h
+            a0 = ang.copy(); a0[q, k] -= h
+            fd = (oracle.mesh_unitary(a1, cells, 4) - oracle.mesh_unitary(a0, cells, 4)) / (2 * h)
+            assert np.max(np.abs(fd - J[q, k])) < 1e-8
+
+
+def test_mesh_loss_gradient_matches_finite_differences():
+    cells = [(0, 1), (1, 2), (2, 3), (0, 1), (1, 2)]
+    rng = np.random.default_rng(5)
+    ang = rng.uniform(0, 2 * np.pi, size=(len(cells), 2))
+    S = np.array([1, 1, 0, 0], np.int32)
+    pats = [np.array(t, np.int32) for t in ([1, 0, 1, 0], [0, 1, 0, 1], [1, 1, 0, 0], [0, 0, 1, 1])]
+    g = oracle.mesh_loss_grad(ang, cells, 4, S, pats)
+    h = 1e-6
+
+    def L(a):
+        return oracle.mesh_loss(oracle.mesh_unitary(a, cells, 4), S, pats)
+    for q in range(len(cells)):
+        for k in range(2):
+            a1 = ang.copy(); a1[q, k] += h
+            a0 = ang.copy(); a0[q, k] -= h
+            assert abs((L(a1) - L(a0)) / (2 * h) - g[q, k]) < 1e-6 * max(1.0, abs(g[q, k]))
