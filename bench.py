@@ -41,6 +41,7 @@ def main() -> int:
     ap.add_argument("--seeds", type=int, default=16)
     ap.add_argument("--cpu-sample-n", type=int, default=28)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-grad", action="store_true")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -96,6 +97,35 @@ def main() -> int:
     algo_flops = terms * flops_per_term(n)
     achieved_tflops = algo_flops / avg_sweep_s / 1e12
 
+    # differentiation workload: 12-mode mesh (132 angles), 8 photons in modes
+    # 0..7, loss over 4096 collision-free output patterns; forward = mesh +
+    # permanents + loss, backward = loss.backward() through the adjoint sweep
+    grad_ratio = None
+    if not args.no_grad:
+        import paper_2403_04006_amd.autograd as ag
+        ang0 = torch.from_numpy(workloads.mesh_angles(0)).to(dev)
+        S8 = np.zeros(workloads.MESH_MODES, np.int32)
+        S8[:8] = 1
+        pats = list(workloads.mesh_patterns(count=4096, seed=1))
+        tf = tb = 0.0
+        reps = 5
+        for it in range(reps + 1):
+            a = ang0.clone().requires_grad_(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            loss = ag.mesh_loss(a, workloads.MESH_CELLS, workloads.MESH_MODES, S8, pats)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            loss.backward()
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            if it > 0:
+                tf += t1 - t0
+                tb += t2 - t1
+        grad_ratio = {"forward_ms": 1e3 * tf / reps, "backward_ms": 1e3 * tb / reps, "ratio": tb / tf,
+                      "workload": "12-mode mesh, 132 angles, 8 photons, 4096 output patterns"}
+        print(f"# grad/forward {tb / tf:.2f}", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -145,6 +175,7 @@ def main() -> int:
             "flops_per_launch": algo_flops,
         },
         "cpu_baseline": cpu,
+        "grad_forward": grad_ratio,
     }
     print(json.dumps(line), flush=True)
     eng.close()

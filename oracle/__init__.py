@@ -49,7 +49,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp"
         subprocess.run(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-Wall",
-                        _SRC_PATH, "-o", tmp], check=True)
+                        _SRC_PATH, "-o", tmp, "-lquadmath"], check=True)
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -66,7 +66,9 @@ def _lib():
     lib.orc_perm_ryser.argtypes = [dptr, ctypes.c_int, ctypes.c_int64, ldptr]
     lib.orc_perm_ryser_mult.argtypes = [dptr, ctypes.c_int64, ctypes.c_int, iptr, iptr, ldptr]
     lib.orc_perm_grad.argtypes = [dptr, ctypes.c_int64, ctypes.c_int, iptr, iptr, ldptr]
-    for f in ("orc_perm_bruteforce", "orc_perm_ryser", "orc_perm_ryser_mult", "orc_perm_grad"):
+    lib.orc_perm_ryser_mult_q.argtypes = [dptr, ctypes.c_int64, ctypes.c_int, iptr, iptr, dptr]
+    for f in ("orc_perm_bruteforce", "orc_perm_ryser", "orc_perm_ryser_mult", "orc_perm_grad",
+              "orc_perm_ryser_mult_q"):
         getattr(lib, f).restype = ctypes.c_int
     lib.orc_num_threads.restype = ctypes.c_int
     lib.orc_long_double_mantissa_bits.restype = ctypes.c_int
@@ -151,6 +153,20 @@ def perm_mult(U, S, T) -> complex:
     """perm(U_{T,S}): rows = output modes (t_i copies), cols = input modes (s_j copies)."""
     re, im = perm_mult_ld(U, S, T)
     return complex(float(re), float(im))
+
+
+def perm_mult_quad(U, S, T) -> tuple:
+    """perm(U_{T,S}) by the multiplicity formula in IEEE quad precision;
+    returns (value as complex, (re_hi, re_lo, im_hi, im_lo))."""
+    U = _cplx(U)
+    m = U.shape[0]
+    S, T = _occ(S, m), _occ(T, m)
+    out = (ctypes.c_double * 4)()
+    ip = ctypes.POINTER(ctypes.c_int32)
+    st = _lib().orc_perm_ryser_mult_q(_dp(U), m, m, S.ctypes.data_as(ip), T.ctypes.data_as(ip), out)
+    if st:
+        raise RuntimeError(f"oracle error {st}")
+    return complex(out[0] + out[1], out[2] + out[3]), tuple(out)
 
 
 def perm_mult_cheaper_side(U, S, T) -> complex:

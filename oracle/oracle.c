@@ -19,6 +19,10 @@
  *                           output occupations T (Appendix, Eq. BS_prob; the
  *                           multiplicity generalisation in Benchmarks / Boson
  *                           Sampling).
+ *   orc_perm_ryser_mult_q -- the same sum in IEEE quad precision (__float128,
+ *                           113-bit mantissa) for large photon numbers, where
+ *                           the alternating sum cancels beyond what 64 bits
+ *                           of mantissa can hold.
  *   orc_perm_grad        -- d perm(U_{T,S}) / d U_ij = t_i s_j perm(U_{T-e_i,S-e_j}).
  *
  * Complex matrices are interleaved (re, im) doubles, row-major with a leading
@@ -30,6 +34,7 @@
 #include <stdlib.h>
 #include <string.h>
 #include <omp.h>
+#include <quadmath.h>
 
 #if LDBL_MANT_DIG != 64
 #error "the oracle needs x87 80-bit long double (64-bit mantissa)"
@@ -228,6 +233,99 @@ int orc_perm_ryser_mult(const double* U, int64_t ldu, int m,
     free(bin);
     out[0] = s.re;
     out[1] = s.im;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* The multiplicity formula above, term for term, in __float128.  Returns the
+ * result rounded to doubles (re_hi, re_lo, im_hi, im_lo): hi the nearest
+ * double, lo the nearest double to the remainder.                           */
+typedef struct { __float128 re, im; } cq;
+static inline cq cq_make(__float128 re, __float128 im) { cq z = {re, im}; return z; }
+static inline cq cq_mul(cq a, cq b) {
+    return cq_make(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+
+int orc_perm_ryser_mult_q(const double* U, int64_t ldu, int m,
+                          const int32_t* S, const int32_t* T, double out[4]) {
+    if (m < 0 || ldu < m) return 1;
+    int cols[128], rows[128];
+    int nc = 0, nr = 0, ns = 0, nt = 0;
+    for (int i = 0; i < m; ++i) {
+        if (S[i] < 0 || T[i] < 0) return 1;
+        if (S[i] > 0) { if (nc >= 128) return 1; cols[nc++] = i; ns += S[i]; }
+        if (T[i] > 0) { if (nr >= 128) return 1; rows[nr++] = i; nt += T[i]; }
+    }
+    if (ns != nt) { out[0] = out[1] = out[2] = out[3] = 0.0; return 0; }
+    if (ns == 0) { out[0] = 1.0; out[1] = out[2] = out[3] = 0.0; return 0; }
+    const int n = ns;
+    uint64_t total = 1;
+    int radix[128];
+    for (int q = 0; q < nc; ++q) {
+        radix[q] = S[cols[q]] + 1;
+        if (total > (1ull << 62) / (uint64_t)radix[q]) return 2;
+        total *= (uint64_t)radix[q];
+    }
+    uint64_t nblocks = total < 1024 ? 1 : 1024;
+    cq* part = (cq*)calloc(nblocks, sizeof(cq));
+    if (!part) return 2;
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t b = 0; b < (int64_t)nblocks; ++b) {
+        uint64_t lo = (uint64_t)((unsigned __int128)total * (uint64_t)b / nblocks);
+        uint64_t hi = (uint64_t)((unsigned __int128)total * (uint64_t)(b + 1) / nblocks);
+        int k[128];
+        uint64_t x = lo;
+        int sumk = 0;
+        for (int q = 0; q < nc; ++q) { k[q] = (int)(x % (uint64_t)radix[q]); x /= (uint64_t)radix[q]; sumk += k[q]; }
+        cq rs[128];
+        for (int p = 0; p < nr; ++p) {
+            rs[p] = cq_make(0, 0);
+            for (int q = 0; q < nc; ++q) {
+                const double* u = U + 2 * ((int64_t)rows[p] * ldu + cols[q]);
+                rs[p].re += (__float128)k[q] * (__float128)u[0];
+                rs[p].im += (__float128)k[q] * (__float128)u[1];
+            }
+        }
+        cq acc = cq_make(0, 0);
+        for (uint64_t idx = lo; idx < hi; ++idx) {
+            if (idx != lo) {
+                for (int q = 0; q < nc; ++q) {
+                    if (k[q] + 1 < radix[q]) {
+                        k[q] += 1; sumk += 1;
+                        for (int p = 0; p < nr; ++p) {
+                            const double* u = U + 2 * ((int64_t)rows[p] * ldu + cols[q]);
+                            rs[p].re += (__float128)u[0];
+                            rs[p].im += (__float128)u[1];
+                        }
+                        break;
+                    }
+                    for (int p = 0; p < nr; ++p) {
+                        const double* u = U + 2 * ((int64_t)rows[p] * ldu + cols[q]);
+                        rs[p].re -= (__float128)k[q] * (__float128)u[0];
+                        rs[p].im -= (__float128)k[q] * (__float128)u[1];
+                    }
+                    sumk -= k[q];
+                    k[q] = 0;
+                }
+            }
+            __float128 w = 1;
+            for (int q = 0; q < nc; ++q) w *= (__float128)binom_ld(S[cols[q]], k[q]);
+            if ((n - sumk) & 1) w = -w;
+            cq p = cq_make(1, 0);
+            for (int r = 0; r < nr; ++r)
+                for (int e = 0; e < T[rows[r]]; ++e) p = cq_mul(p, rs[r]);
+            acc.re += w * p.re;
+            acc.im += w * p.im;
+        }
+        part[b] = acc;
+    }
+    cq s = cq_make(0, 0);
+    for (uint64_t b = 0; b < nblocks; ++b) { s.re += part[b].re; s.im += part[b].im; }
+    free(part);
+    out[0] = (double)s.re;
+    out[1] = (double)(s.re - (__float128)out[0]);
+    out[2] = (double)s.im;
+    out[3] = (double)(s.im - (__float128)out[2]);
     return 0;
 }
 

@@ -25,3 +25,28 @@ def load_single(path):
         cases.append({"n": n, "seed": seed, "perm": perm, "A": np.array(rows)})
         i += 2 + n
     return cases
+
+
+def load_repeated(path):
+    """Parse repeated_permanents.txt: the unitary block, then per pattern its
+    index, S, T and the value as (re_hi, re_lo, im_hi, im_lo)."""
+    with open(path) as f:
+        lines = [ln.strip() for ln in f if ln.strip() and not ln.startswith("#")]
+    head = lines[0].split()
+    assert head[0] == "unitary"
+    m = int(head[1])
+    rows = []
+    for r in range(m):
+        v = np.array([float(x) for x in lines[1 + r].split()])
+        rows.append(v[0::2] + 1j * v[1::2])
+    U = np.array(rows)
+    cases = []
+    i = 1 + m
+    while i < len(lines):
+        idx = int(lines[i].split()[1])
+        S = np.array([int(x) for x in lines[i + 1].split()[1:]], dtype=np.int32)
+        T = np.array([int(x) for x in lines[i + 2].split()[1:]], dtype=np.int32)
+        q = [float(x) for x in lines[i + 3].split()[1:]]
+        cases.append({"index": idx, "S": S, "T": T, "perm": complex(q[0] + q[1], q[2] + q[3])})
+        i += 4
+    return U, cases

@@ -328,3 +328,31 @@ def test_mesh_loss_gradient_matches_finite_differences():
             a1 = ang.copy(); a1[q, k] += h
             a0 = ang.copy(); a0[q, k] -= h
             assert abs((L(a1) - L(a0)) / (2 * h) - g[q, k]) < 1e-6 * max(1.0, abs(g[q, k]))
+
+
+def test_quad_precision_multiplicity_formula():
+    rng = np.random.default_rng(21)
+    for _ in range(6):
+        U = workloads.haar(5, int(rng.integers(0, 1000)))
+        S = workloads.random_occupations(rng, 5, 6, cap=3)
+        T = workloads.random_occupations(rng, 5, 6, cap=3)
+        q, _ = oracle.perm_mult_quad(U, S, T)
+        ref = oracle.perm_bruteforce(oracle.expand(U, S, T))
+        assert abs(q - ref) <= 1e-14 * max(1.0, abs(ref))
+    # integer pins: perm(J_n) = n! and the identity with repeats
+    n = 14
+    q, parts = oracle.perm_mult_quad(np.ones((1, 1)), [n], [n])
+    assert q == math.factorial(n)
+    q, _ = oracle.perm_mult_quad(np.eye(4), [3, 0, 2, 1], [3, 0, 2, 1])
+    assert q == 12
+
+
+def test_golden_repeated_values_present():
+    path = os.path.join(GOLDEN, "repeated_permanents.txt")
+    if not os.path.exists(path):
+        pytest.skip("golden file not generated")
+    from tests.golden import load_repeated
+    U, cases = load_repeated(path)
+    assert U.shape == (20, 20) and np.max(np.abs(U @ U.conj().T - np.eye(20))) < 1e-13
+    for c in cases:
+        assert c["S"].sum() == 40 and c["T"].sum() == 40 and c["S"].max() <= 4 and c["T"].max() <= 4
