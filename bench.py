@@ -106,14 +106,14 @@ def main() -> int:
         ang0 = torch.from_numpy(workloads.mesh_angles(0)).to(dev)
         S8 = np.zeros(workloads.MESH_MODES, np.int32)
         S8[:8] = 1
-        pats = list(workloads.mesh_patterns(count=4096, seed=1))
+        pats = pq.PatternSet([S8] * 4096, list(workloads.mesh_patterns(count=4096, seed=1)), workloads.MESH_MODES)
         tf = tb = 0.0
         reps = 5
         for it in range(reps + 1):
             a = ang0.clone().requires_grad_(True)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            loss = ag.mesh_loss(a, workloads.MESH_CELLS, workloads.MESH_MODES, S8, pats)
+            loss = ag.mesh_loss(a, workloads.MESH_CELLS, workloads.MESH_MODES, pats)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             loss.backward()

@@ -16,7 +16,7 @@ from . import _lib
 from ._lib import PqError, pq_job, pq_plan_info, PQ_OP_PERM, PQ_OP_EXTEND_ROW, PQ_MAX_N  # noqa: F401
 
 __all__ = [
-    "Engine", "engine", "perm", "plan_describe", "gray_unrank", "PqError",
+    "Engine", "engine", "perm", "plan_describe", "gray_unrank", "PqError", "PatternSet",
     "PQ_OP_PERM", "PQ_OP_EXTEND_ROW",
 ]
 
@@ -129,6 +129,32 @@ class Engine:
         _check(st, self._ctx)
         return perm[:n_out], (amp[:n_out] if amp is not None else None)
 
+    def perm_patterns(self, U: torch.Tensor, pats: "PatternSet", with_amp: bool = False):
+        """perm(U_{T_p,S_p}) for a prepared PatternSet (pq_perm_many); returns
+        (perm, amp or None), one entry per pattern."""
+        U, ldu = _as_matrix(U)
+        if U.shape[0] != pats.m:
+            raise ValueError("pattern set built for another mode count")
+        perm = torch.empty(max(1, pats.batch), dtype=torch.complex128, device=U.device)
+        amp = torch.empty_like(perm) if with_amp else None
+        st = self._lib.pq_perm_many(self._ctx, U.data_ptr(), ldu, pats.m, pats.jobs, pats.batch, perm.data_ptr(),
+                                    amp.data_ptr() if amp is not None else None, _stream_handle(U.device))
+        _check(st, self._ctx)
+        return perm[:pats.batch], (amp[:pats.batch] if amp is not None else None)
+
+    def grad_patterns(self, U: torch.Tensor, pats: "PatternSet", gperm: torch.Tensor, want_perm: bool = False):
+        """dU = sum_p gperm[p] conj(d perm_p / dU) for a prepared PatternSet
+        (pq_perm_grad); returns (dU, perm or None)."""
+        U, ldu = _as_matrix(U)
+        gperm = gperm.to(dtype=torch.complex128, device=U.device).contiguous()
+        dU = torch.empty((pats.m, pats.m), dtype=torch.complex128, device=U.device)
+        perm = torch.empty(max(1, pats.batch), dtype=torch.complex128, device=U.device) if want_perm else None
+        st = self._lib.pq_perm_grad(self._ctx, U.data_ptr(), ldu, pats.m, pats.batch, pats.S_flat, pats.T_flat,
+                                    gperm.data_ptr(), perm.data_ptr() if perm is not None else None,
+                                    dU.data_ptr(), pats.m, _stream_handle(U.device))
+        _check(st, self._ctx)
+        return dU, (perm[:pats.batch] if perm is not None else None)
+
     def perm_many(self, U: torch.Tensor, jobs: Sequence[dict], n_out: int | None = None, with_amp: bool = True):
         """Jobs {op, rows: [(mode, mult)], cols: [(mode, mult)], out} through the
         statically scheduled many-pattern path (pq_perm_many).  PERM jobs write
@@ -161,6 +187,32 @@ class Engine:
                                     dU.data_ptr(), m, _stream_handle(U.device))
         _check(st, self._ctx)
         return dU, (perm[:batch] if perm is not None else None)
+
+
+class PatternSet:
+    """Input/output occupation patterns on m modes, marshalled once for
+    repeated pq_perm_many / pq_perm_grad calls (e.g. every step of a training
+    loop)."""
+
+    def __init__(self, S_list, T_list, m: int):
+        if len(S_list) != len(T_list):
+            raise ValueError("S_list and T_list differ in length")
+        self.m = int(m)
+        self.batch = len(S_list)
+        flatS, flatT = [], []
+        jobs = []
+        for p, (S, T) in enumerate(zip(S_list, T_list)):
+            S = [int(v) for v in S]
+            T = [int(v) for v in T]
+            if len(S) != m or len(T) != m:
+                raise ValueError("patterns need one entry per mode")
+            flatS += S
+            flatT += T
+            jobs.append({"op": PQ_OP_PERM, "rows": [(i, c) for i, c in enumerate(T) if c > 0],
+                         "cols": [(i, c) for i, c in enumerate(S) if c > 0], "out": p})
+        self.S_flat = _lib.i32_array(flatS)
+        self.T_flat = _lib.i32_array(flatT)
+        self.jobs, self._keep, _ = Engine._job_array(jobs, m)
 
 
 _engines: dict = {}

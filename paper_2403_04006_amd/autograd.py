@@ -11,7 +11,7 @@ from typing import Sequence
 
 import torch
 
-from . import _lib, _check, _stream_handle, engine as _engine
+from . import PatternSet, _lib, _check, _stream_handle, engine as _engine
 
 __all__ = ["MeshUnitary", "PermAmp", "NegLogProb", "mesh_unitary", "perm_amp", "neg_log_prob", "mesh_loss"]
 
@@ -55,27 +55,24 @@ def _sparse(v):
 
 
 class PermAmp(torch.autograd.Function):
-    """perm(U_{T_p,S_p}) for every pattern p (forward: pq_perm_many; backward:
-    pq_perm_grad, the adjoint sweep)."""
+    """perm(U_{T_p,S_p}) for every pattern of a PatternSet (forward:
+    pq_perm_many; backward: pq_perm_grad, the adjoint sweep)."""
 
     @staticmethod
-    def forward(ctx, U: torch.Tensor, S_list, T_list):
+    def forward(ctx, U: torch.Tensor, pats: PatternSet):
         eng = _engine(U.device.index)
         U = U.detach().contiguous()
-        jobs = [{"op": 0, "rows": _sparse(T), "cols": _sparse(S), "out": p}
-                for p, (S, T) in enumerate(zip(S_list, T_list))]
-        perm, _ = eng.perm_many(U, jobs, n_out=len(jobs), with_amp=False)
+        perm, _ = eng.perm_patterns(U, pats)
         ctx.save_for_backward(U)
-        ctx.S_list = S_list
-        ctx.T_list = T_list
+        ctx.pats = pats
         return perm
 
     @staticmethod
     def backward(ctx, gperm: torch.Tensor):
         (U,) = ctx.saved_tensors
         eng = _engine(U.device.index)
-        dU, _ = eng.perm_grad(U, ctx.S_list, ctx.T_list, gperm.contiguous(), want_perm=False)
-        return dU, None, None
+        dU, _ = eng.grad_patterns(U, ctx.pats, gperm.contiguous())
+        return dU, None
 
 
 class NegLogProb(torch.autograd.Function):
@@ -108,16 +105,20 @@ def mesh_unitary(angles: torch.Tensor, cells, m: int) -> torch.Tensor:
     return MeshUnitary.apply(angles, tuple(tuple(c) for c in cells), m)
 
 
-def perm_amp(U: torch.Tensor, S_list, T_list) -> torch.Tensor:
-    return PermAmp.apply(U, S_list, T_list)
+def perm_amp(U: torch.Tensor, S_list, T_list=None) -> torch.Tensor:
+    """Permanents of a PatternSet, or of (S_list, T_list) marshalled on the fly."""
+    pats = S_list if isinstance(S_list, PatternSet) else PatternSet(S_list, T_list, U.shape[0])
+    return PermAmp.apply(U, pats)
 
 
 def neg_log_prob(perm: torch.Tensor, log_norm: torch.Tensor | None = None) -> torch.Tensor:
     return NegLogProb.apply(perm, log_norm)
 
 
-def mesh_loss(angles: torch.Tensor, cells, m: int, S, T_list, log_norm: torch.Tensor | None = None):
-    """Loss of output patterns T_list for input S through the mesh."""
+def mesh_loss(angles: torch.Tensor, cells, m: int, S, T_list=None, log_norm: torch.Tensor | None = None):
+    """Loss of output patterns T_list for input S through the mesh (or of a
+    prepared PatternSet passed as S)."""
     U = mesh_unitary(angles, cells, m)
-    perm = perm_amp(U, [S] * len(T_list), T_list)
+    pats = S if isinstance(S, PatternSet) else PatternSet([S] * len(T_list), T_list, m)
+    perm = perm_amp(U, pats)
     return neg_log_prob(perm, log_norm)

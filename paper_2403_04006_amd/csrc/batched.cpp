@@ -381,12 +381,13 @@ void pq_release_batch_cache(pq_ctx* ctx) {
     ctx->batch_cache = nullptr;
 }
 
-// The persistent work-queue path below is switched off: its first GPU run
-// (a graph-captured batch of 495 small permanents) hung, while CPU emulation
-// of the same kernels and host planning (sequential and with concurrent
-// wavefronts) completes with correct results, so no mistake in this code that
-// would explain the hang has been shown.  Until one is, pq_perm_batched
-// reports PQ_EDEVICE after validating its arguments.
+// The persistent work-queue path below is switched off: a graph-captured
+// batch of 495 small permanents through it did not complete on the device,
+// while CPU emulation of the same kernels and host planning (sequential and
+// with concurrent wavefronts) completes with correct results, so no mistake
+// in this code that would explain it has been shown.  Until one is,
+// pq_perm_batched reports PQ_EDEVICE after validating its arguments;
+// pq_perm_many computes the same jobs with a static schedule.
 static int perm_batched_queue(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m,
                               const pq_job* jobs, int32_t njobs,
                               pq_c128* perm, pq_c128* amp, void* stream);

@@ -5,14 +5,15 @@ import pytest
 import oracle
 import workloads
 
-# The persistent work-queue path of pq_perm_batched hung on its first GPU run
-# (graph-captured batch of 495 small permanents, killed for silence; the GPU
-# kept answering).  CPU emulation of the same host planning and kernels, with
-# 64-lane wavefronts and with concurrent wavefronts, completes with correct
-# results, so the cause is not shown; the path is switched off in the library
-# (pq_perm_batched returns PQ_EDEVICE) and these tests stay off the GPU.
+# The persistent work-queue path of pq_perm_batched did not complete on the
+# device for a graph-captured batch of 495 small permanents (no progress until
+# stopped; the device stayed responsive).  CPU emulation of the same host
+# planning and kernels, with 64-lane wavefronts and with concurrent
+# wavefronts, completes with correct results, so no cause is shown; the path is
+# switched off in the library (pq_perm_batched returns PQ_EDEVICE) and these
+# tests stay skipped.  pq_perm_many covers the same jobs (test_gpu_many.py).
 pytestmark = [pytest.mark.gpu, pytest.mark.skip(
-    reason="persistent batched work-queue path hung on its first GPU run; cause not shown, path disabled")]
+    reason="persistent work-queue path did not complete on the device; cause not shown, path disabled")]
 
 torch = pytest.importorskip("torch")
 

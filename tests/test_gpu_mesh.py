@@ -93,9 +93,11 @@ def test_mesh_training_step_vs_oracle(ag):
 
 def test_mesh_training_step_vs_finite_differences(ag):
     # the full 4096-pattern workload; central differences, h = 1e-6, all 132 angles
-    ang, S, pats = _c5_inputs(4096)
+    import paper_2403_04006_amd as pq
+    ang, S, T_list = _c5_inputs(4096)
+    pats = pq.PatternSet([S] * len(T_list), T_list, M)
     a = torch.from_numpy(ang).cuda().requires_grad_(True)
-    loss = ag.mesh_loss(a, CELLS, M, S, pats)
+    loss = ag.mesh_loss(a, CELLS, M, pats)
     loss.backward()
     g = a.grad.cpu().numpy()
     h = 1e-6
@@ -105,8 +107,8 @@ def test_mesh_training_step_vs_finite_differences(ag):
             for k in range(2):
                 a1 = ang.copy(); a1[q, k] += h
                 a0 = ang.copy(); a0[q, k] -= h
-                l1 = ag.mesh_loss(torch.from_numpy(a1).cuda(), CELLS, M, S, pats).item()
-                l0 = ag.mesh_loss(torch.from_numpy(a0).cuda(), CELLS, M, S, pats).item()
+                l1 = ag.mesh_loss(torch.from_numpy(a1).cuda(), CELLS, M, pats).item()
+                l0 = ag.mesh_loss(torch.from_numpy(a0).cuda(), CELLS, M, pats).item()
                 fd = (l1 - l0) / (2 * h)
                 worst = max(worst, abs(fd - g[q, k]) / max(1.0, abs(g[q, k])))
     print(f"mesh gradient vs central differences: worst scaled err {worst:.2e}")
