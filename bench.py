@@ -42,6 +42,8 @@ def main() -> int:
     ap.add_argument("--cpu-sample-n", type=int, default=28)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="copy a buffer of this many MiB once (calibrates traffic counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -63,6 +65,12 @@ def main() -> int:
     n = args.n
     m = 2 * n * n
     dev = torch.device("cuda", 0)
+    if args.calib_copy_mib > 0:
+        src = torch.ones(args.calib_copy_mib * (1 << 20) // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     t0 = time.time()
     blocks = [torch.from_numpy(workloads.collision_free_block(n, s)).to(dev) for s in range(args.seeds)]
     print(f"# inputs ready ({time.time() - t0:.1f}s)", file=sys.stderr, flush=True)
