@@ -82,27 +82,18 @@ hipError_t launch_many_final(const ManyFinalArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-// dU[a][b] = sum_p g_p conj(d perm_p / d U_ab), patterns added in order.  For
-// a pattern iterated over its output side, B_ij = U[row_mode_i][col_mode_j];
-// over its input side (transposed), B_ij = U[col_mode_j][row_mode_i].
+// dU[a][b] = sum_p g_p conj(d perm_p / d U_ab): one wavefront per entry; lane
+// L adds items L, L+64, ... in order, then a fixed-order butterfly.
 __global__ __launch_bounds__(256) void grad_scatter_kernel(const GradScatterArgs a) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= a.m * a.m) return;
-    const int ra = e / a.m, cb = e % a.m;
+    const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int nent = a.m * a.m;
+    if (e >= nent) return;
+    const int beg = a.offsets[e], end = a.offsets[e + 1];
     double re = 0.0, im = 0.0;
-    for (int p = 0; p < a.npat; ++p) {
-        if (a.pat_class[p] < 0) continue;
-        const BJob& J = a.jobs[p];
-        const int32_t* rmode = a.idx + J.idx_off;
-        const int32_t* cmode = rmode + 2 * J.r;
-        const int want_row = J.transposed ? cb : ra;
-        const int want_col = J.transposed ? ra : cb;
-        int i = -1, j = -1;
-        for (int q = 0; q < J.r; ++q) if (rmode[q] == want_row) { i = q; break; }
-        if (i < 0) continue;
-        for (int q = 0; q < J.nc; ++q) if (cmode[q] == want_col) { j = q; break; }
-        if (j < 0) continue;
-        const cplx d = a.dpat[a.dpat_off[p] + (size_t)i * J.nc + j];
+    for (int k = beg + lane; k < end; k += 64) {
+        const int p = a.items[2 * k];
+        const cplx d = a.dpat[a.items[2 * k + 1]];
         const cplx g = a.gperm[p];
         // g * conj(d)
         re = __builtin_fma(g.re, d.re, re);
@@ -110,12 +101,17 @@ __global__ __launch_bounds__(256) void grad_scatter_kernel(const GradScatterArgs
         im = __builtin_fma(g.im, d.re, im);
         im = __builtin_fma(-g.re, d.im, im);
     }
-    a.dU[(size_t)ra * (size_t)a.lddu + cb] = cplx{re, im};
+#pragma unroll
+    for (int msk = 32; msk >= 1; msk >>= 1) {
+        re += __shfl_xor(re, msk, 64);
+        im += __shfl_xor(im, msk, 64);
+    }
+    if (lane == 0) a.dU[(size_t)(e / a.m) * (size_t)a.lddu + (e % a.m)] = cplx{re, im};
 }
 
 hipError_t launch_grad_scatter(const GradScatterArgs& a, hipStream_t s) {
     const int n = a.m * a.m;
-    hipLaunchKernelGGL(grad_scatter_kernel, dim3((n + 255) / 256 > 0 ? (n + 255) / 256 : 1), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(grad_scatter_kernel, dim3((n + 3) / 4 > 0 ? (n + 3) / 4 : 1), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

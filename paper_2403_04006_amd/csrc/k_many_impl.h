@@ -106,6 +106,7 @@ __global__ __launch_bounds__(64) void many_kernel(const ManyArgs a) {
         constexpr int KA = AdjDigits<NC>::value;
         __shared__ cplx sP[64][NC];
         __shared__ cplx sA[64][KA][NC];
+        __shared__ double sDel[kMaxLaneDigits][64];
         AdjBody<NC, UNIT, KA> body;
         body.kap = J.kap;
         const double wl = sweep_chunk<NC, BIN>(J, mat, a.tabs, lane, ch.start, ch.count, body);
@@ -129,6 +130,15 @@ __global__ __launch_bounds__(64) void many_kernel(const ManyArgs a) {
 #pragma unroll
             for (int q = 0; q < KA; ++q) sA[lane][q][j] = cplx{body.A[q][j].re * wl, body.A[q][j].im * wl};
         }
+        {
+            // delta of every lane row at this lane's digits
+            int rest = lane;
+            for (int q = 0; q < J.n_lane; ++q) {
+                const int d = rest % J.lane_radix[q];
+                rest /= J.lane_radix[q];
+                sDel[q][lane] = (double)(rmu[q] - 2 * d);
+            }
+        }
         cdd fv = wave_reduce(to_cdd(cplx{body.fwd.re * wl, body.fwd.im * wl}));
         if (lane == 0) store_cdd_slot(slot, fv);
         __syncthreads();
@@ -140,15 +150,8 @@ __global__ __launch_bounds__(64) void many_kernel(const ManyArgs a) {
             double re = 0.0, im = 0.0;
             if (i < J.n_lane) {
                 // lane row: delta_i depends on the lane's digit
-                const int mu = rmu[i];
                 for (int L = 0; L < 64; ++L) {
-                    int rest = L;
-                    int d = 0;
-                    for (int q = 0; q <= i; ++q) {
-                        d = rest % J.lane_radix[q];
-                        rest /= J.lane_radix[q];
-                    }
-                    const double del = (double)(mu - 2 * d);
+                    const double del = sDel[i][L];
                     re = __builtin_fma(del, sP[L][j].re, re);
                     im = __builtin_fma(del, sP[L][j].im, im);
                 }

@@ -40,14 +40,35 @@ __device__ __forceinline__ BS cell_matrix(double th, double ph) {
 __device__ __forceinline__ cplx cadd(cplx a, cplx b) { return cplx{a.re + b.re, a.im + b.im}; }
 __device__ __forceinline__ cplx cconj(cplx a) { return cplx{a.re, -a.im}; }
 
+// cos/sin of every cell's angles, computed by the 64 threads together
+__device__ __forceinline__ void cell_trig(const double* angles, int ncell, double (*trig)[4]) {
+    for (int q = threadIdx.x; q < ncell; q += blockDim.x) {
+        trig[q][0] = cos(angles[2 * q]);
+        trig[q][1] = sin(angles[2 * q]);
+        trig[q][2] = cos(angles[2 * q + 1]);
+        trig[q][3] = sin(angles[2 * q + 1]);
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ BS cell_from_trig(const double* tg) {
+    BS b;
+    b.t = cplx{tg[0], 0.0};
+    b.r = cplx{tg[2] * tg[1], tg[3] * tg[1]};
+    b.mrc = cplx{-tg[2] * tg[1], tg[3] * tg[1]};
+    return b;
+}
+
 __global__ __launch_bounds__(64) void mesh_forward_kernel(const MeshArgs a) {
     __shared__ cplx sU[kMeshMaxModes][kMeshMaxModes];
+    __shared__ double trig[kMeshMaxCells][4];
+    cell_trig(a.angles, a.ncell, trig);
     const int col = threadIdx.x;
     if (col < a.m)
         for (int r = 0; r < a.m; ++r) sU[r][col] = cplx{r == col ? 1.0 : 0.0, 0.0};
     for (int q = 0; q < a.ncell; ++q) {
         const int k = a.modes[2 * q], l = a.modes[2 * q + 1];
-        const BS b = cell_matrix(a.angles[2 * q], a.angles[2 * q + 1]);
+        const BS b = cell_from_trig(trig[q]);
         if (col < a.m) {
             const cplx uk = sU[k][col], ul = sU[l][col];
             sU[k][col] = cadd(cmul(b.t, uk), cmul(b.mrc, ul));
@@ -61,6 +82,8 @@ __global__ __launch_bounds__(64) void mesh_forward_kernel(const MeshArgs a) {
 __global__ __launch_bounds__(64) void mesh_vjp_kernel(const MeshVjpArgs a) {
     __shared__ cplx sU[kMeshMaxModes][kMeshMaxModes];
     __shared__ cplx sG[kMeshMaxModes][kMeshMaxModes];
+    __shared__ double trig[kMeshMaxCells][4];
+    cell_trig(a.angles, a.ncell, trig);
     const int col = threadIdx.x;
     const bool act = col < a.m;
     if (act)
@@ -70,7 +93,7 @@ __global__ __launch_bounds__(64) void mesh_vjp_kernel(const MeshVjpArgs a) {
         }
     for (int q = 0; q < a.ncell; ++q) {
         const int k = a.modes[2 * q], l = a.modes[2 * q + 1];
-        const BS b = cell_matrix(a.angles[2 * q], a.angles[2 * q + 1]);
+        const BS b = cell_from_trig(trig[q]);
         if (act) {
             const cplx uk = sU[k][col], ul = sU[l][col];
             sU[k][col] = cadd(cmul(b.t, uk), cmul(b.mrc, ul));
@@ -79,8 +102,7 @@ __global__ __launch_bounds__(64) void mesh_vjp_kernel(const MeshVjpArgs a) {
     }
     for (int q = a.ncell - 1; q >= 0; --q) {
         const int k = a.modes[2 * q], l = a.modes[2 * q + 1];
-        const double th = a.angles[2 * q], ph = a.angles[2 * q + 1];
-        const BS b = cell_matrix(th, ph);
+        const BS b = cell_from_trig(trig[q]);
         double gth = 0.0, gph = 0.0;
         if (act) {
             // U_{q-1} = B^H U_q on rows (k, l): B^H = [[t, r*], [-r, t]]
@@ -91,7 +113,7 @@ __global__ __launch_bounds__(64) void mesh_vjp_kernel(const MeshVjpArgs a) {
             sU[l][col] = pl;
             const cplx gk = sG[k][col], gl = sG[l][col];
             // dB/dtheta = [[-s, -e^{-i phi} c], [e^{i phi} c, -s]]
-            const double c = cos(th), s = sin(th), cp = cos(ph), sp = sin(ph);
+            const double c = trig[q][0], s = trig[q][1], cp = trig[q][2], sp = trig[q][3];
             const cplx dk_th = cadd(cmul(cplx{-s, 0.0}, pk), cmul(cplx{-cp * c, sp * c}, pl));
             const cplx dl_th = cadd(cmul(cplx{cp * c, sp * c}, pk), cmul(cplx{-s, 0.0}, pl));
             // dB/dphi = [[0, i e^{-i phi} s], [i e^{i phi} s, 0]]

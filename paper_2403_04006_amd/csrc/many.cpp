@@ -5,6 +5,7 @@
 // one kernel per column class (one wavefront per chunk), and reduces every
 // pattern's chunk slots in slot order.
 #include <hip/hip_runtime.h>
+#include <stdint.h>
 #include <string.h>
 
 #include <algorithm>
@@ -57,6 +58,8 @@ struct ManyEntry {
     StepEntry* d_tabs = nullptr;
     double* d_partials = nullptr;
     cplx* d_dpat = nullptr;
+    int32_t* d_sc_off = nullptr;     // adjoint: scatter lists (CSR over dU entries)
+    int32_t* d_sc_items = nullptr;
     uint64_t last_use = 0;
     ~ManyEntry() {
         if (dmem) hipFree(dmem);
@@ -227,6 +230,42 @@ int build_many(pq_ctx* ctx, int mode, int32_t m, const std::vector<PatternSpec>&
         class_sd.push_back(C.slot_doubles);
     }
 
+    // adjoint: for every dU entry, the (pattern, D index) pairs touching it,
+    // in pattern order (a counting sort by entry)
+    std::vector<int32_t> sc_off, sc_items;
+    if (adj) {
+        if (dpat_elems > (size_t)INT32_MAX / 2)
+            return ctx->fail(PQ_ERANGE, "gradient: %zu derivative entries exceed the 32-bit scatter index", dpat_elems);
+        const size_t nent = (size_t)m * m;
+        sc_off.assign(nent + 1, 0);
+        auto entry_of = [&](const BJob& b, int i, int j) {
+            const int32_t* rmode = hidx.data() + b.idx_off;
+            const int32_t* cmode = rmode + 2 * b.r;
+            const int out = b.transposed ? cmode[j] : rmode[i];
+            const int in = b.transposed ? rmode[i] : cmode[j];
+            return (size_t)out * m + in;
+        };
+        for (size_t k = 0; k < pats.size(); ++k) {
+            if (pat_class[k] < 0) continue;
+            const BJob& b = hj[k];
+            for (int i = 0; i < b.r; ++i)
+                for (int j = 0; j < b.nc; ++j) sc_off[entry_of(b, i, j) + 1] += 1;
+        }
+        for (size_t e = 0; e < nent; ++e) sc_off[e + 1] += sc_off[e];
+        std::vector<int32_t> fill(sc_off.begin(), sc_off.end() - 1);
+        sc_items.assign(2 * (size_t)sc_off[nent], 0);
+        for (size_t k = 0; k < pats.size(); ++k) {
+            if (pat_class[k] < 0) continue;
+            const BJob& b = hj[k];
+            for (int i = 0; i < b.r; ++i)
+                for (int j = 0; j < b.nc; ++j) {
+                    const int32_t slot = fill[entry_of(b, i, j)]++;
+                    sc_items[2 * (size_t)slot] = (int32_t)k;
+                    sc_items[2 * (size_t)slot + 1] = (int32_t)(dpat_off[k] + (int64_t)i * b.nc + j);
+                }
+        }
+    }
+
     // one device block: uploaded descriptors first, kernel-written arrays after
     Carve cv;
     auto sz = [](size_t n) { return std::max<size_t>(1, n); };
@@ -240,6 +279,8 @@ int build_many(pq_ctx* ctx, int mode, int32_t m, const std::vector<PatternSpec>&
     const size_t oCs = cv.take(sizeof(int32_t) * sz(class_sd.size()));
     const size_t oTr = cv.take(sizeof(cplx) * sz(trivial.size()));
     const size_t oDo = cv.take(sizeof(int64_t) * sz(dpat_off.size()));
+    const size_t oSo = cv.take(sizeof(int32_t) * sz(sc_off.size()));
+    const size_t oSi = cv.take(sizeof(int32_t) * sz(sc_items.size()));
     const size_t upload_bytes = cv.off;
     const size_t oMat = cv.take(sizeof(cplx) * sz(mat_elems));
     const size_t oTab = cv.take(sizeof(StepEntry) * 2 * kMaxInner * sz(sigs.size()));
@@ -259,6 +300,8 @@ int build_many(pq_ctx* ctx, int mode, int32_t m, const std::vector<PatternSpec>&
     E.d_class_sd = (int32_t*)(E.dmem + oCs);
     E.d_trivial = (cplx*)(E.dmem + oTr);
     E.d_dpat_off = (int64_t*)(E.dmem + oDo);
+    E.d_sc_off = (int32_t*)(E.dmem + oSo);
+    E.d_sc_items = (int32_t*)(E.dmem + oSi);
     E.d_mat = (cplx*)(E.dmem + oMat);
     E.d_tabs = (StepEntry*)(E.dmem + oTab);
     E.d_partials = (double*)(E.dmem + oPart);
@@ -277,6 +320,8 @@ int build_many(pq_ctx* ctx, int mode, int32_t m, const std::vector<PatternSpec>&
     put(oCs, class_sd.data(), sizeof(int32_t) * class_sd.size());
     put(oTr, trivial.data(), sizeof(cplx) * trivial.size());
     put(oDo, dpat_off.data(), sizeof(int64_t) * dpat_off.size());
+    put(oSo, sc_off.data(), sizeof(int32_t) * sc_off.size());
+    put(oSi, sc_items.data(), sizeof(int32_t) * sc_items.size());
     return ctx->upload(E.dmem, stage, upload_bytes, st);
 }
 
@@ -341,13 +386,10 @@ int run_many(pq_ctx* ctx, ManyEntry& E, const cplx* U, int64_t ldu, int32_t m, c
     if (rc) return rc;
     if (E.mode == kModeAdj) {
         GradScatterArgs ga;
-        ga.jobs = E.d_jobs;
-        ga.idx = E.d_idx;
-        ga.pat_class = E.d_pat_class;
-        ga.dpat_off = E.d_dpat_off;
+        ga.offsets = E.d_sc_off;
+        ga.items = E.d_sc_items;
         ga.dpat = E.d_dpat;
         ga.gperm = gperm;
-        ga.npat = E.npat;
         ga.m = m;
         ga.dU = dU;
         ga.lddu = lddu;

@@ -67,14 +67,13 @@ struct ManyFinalArgs {
 };
 
 // Scatter of the per-pattern derivatives into dU (conjugate-Wirtinger VJP).
+// For every entry e = a*m + b of dU, items[offsets[e] .. offsets[e+1]) list
+// the (pattern, index into dpat) pairs that touch it, in pattern order.
 struct GradScatterArgs {
-    const BJob* jobs;
-    const int32_t* idx;
-    const int32_t* pat_class;
-    const int64_t* dpat_off;
+    const int32_t* offsets;    // [m*m + 1]
+    const int32_t* items;      // [2 * total]: pattern, then the D index (complex)
     const cplx* dpat;
     const cplx* gperm;
-    int32_t npat;
     int32_t m;
     cplx* dU;
     int64_t lddu;
