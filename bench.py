@@ -24,6 +24,37 @@ sys.path.insert(0, ROOT)
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CUs x 2.4 GHz x 128 FP64 flop/clk/CU
 
+# HBM traffic of one n=30 sweep launch, from two rocprofv3 --pmc passes
+# (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) over this script with
+# --calib-copy-mib 256; each scaled by what the same counter read for a plain
+# 256 MiB device-to-device copy in the same run (FETCH 131088.9 KiB, WRITE
+# 262144 KiB, against 262144 KiB moved each way).  Valid only for the sources
+# it was measured on: the hash covers every file that shapes the launch.
+SWEEP_TRAFFIC = {
+    "sources": ["k_glynn_impl.h", "k_glynn_p2.hip", "sweep_common.h", "device.h", "pq_common.h",
+                "runtime.cpp", "runtime.h", "plan.cpp", "plan.h", "api.cpp", "k_misc.hip"],
+    "sha256": "c503252c49d36841c2655d1b966435b5624267256cda96755a09d2bc567e1cb4",
+    "n": 30,
+    "fetch_kib": 246.25, "write_kib": 24.0,
+    "fetch_factor": 262144.0 / 131088.9375, "write_factor": 1.0,
+}
+
+
+def sweep_traffic_bytes(n: int):
+    """Calibrated HBM bytes per sweep launch, or None when the kernel sources
+    differ from those the counters were taken on."""
+    import hashlib
+    t = SWEEP_TRAFFIC
+    if n != t["n"]:
+        return None
+    h = hashlib.sha256()
+    for f in t["sources"]:
+        with open(os.path.join(ROOT, "paper_2403_04006_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != t["sha256"]:
+        return None
+    return 1024.0 * (t["fetch_kib"] * t["fetch_factor"] + t["write_kib"] * t["write_factor"])
+
 
 def flops_per_term(n: int) -> int:
     # per Gray-code term at unit multiplicities: n complex adds (row update),
@@ -178,7 +209,7 @@ def main() -> int:
             "peak": FP64_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved_tflops / FP64_VECTOR_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": sweep_traffic_bytes(n),
             "kernel": f"glynn_bin<{n}>",
             "flops_per_launch": algo_flops,
         },
