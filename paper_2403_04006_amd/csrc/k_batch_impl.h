@@ -108,16 +108,17 @@ __device__ __forceinline__ double sweep_chunk(const BJob& J, const cplx* __restr
         for (int k = 0; k < J.n_time; ++k)
             if ((g >> k) & 1ull) add_row(c, trows + (size_t)k * 2 * NC);
         double w = (__builtin_popcountll(g) & 1) ? -1.0 : 1.0;
-        body.term(c, w);
         const uint64_t end = start + count;
+        // each pass takes the term of state t-1, then moves to state t
         for (uint64_t t = start + 1; t < end; ++t) {
             const int i = __builtin_ctzll(t);
             const int sel = (int)((t >> (i + 1)) & 1ull);
+            body.term(c, w);
             body.flip(i, sel ? -1 : 1);          // time digit i moves by +1 (sel 0) or -1
             add_row(c, trows + ((size_t)i * 2 + sel) * NC);
             w = -w;
-            body.term(c, w);
         }
+        body.term(c, w);
     } else {
         const uint64_t M = (uint64_t)J.m_inner;
         const int n_high = J.n_time - J.n_inner;
@@ -151,13 +152,15 @@ __device__ __forceinline__ double sweep_chunk(const BJob& J, const cplx* __restr
             for (int k = 0; k < J.n_inner; ++k)
                 if (gi[k]) fma_row(c, (double)gi[k], trows + (size_t)k * 2 * NC);
             const StepEntry* tab = refl ? tb : tf;
-            body.term(c, wh * tab[pos0].w);
+            double wcur = wh * tab[pos0].w;
             for (int p = pos0 + 1; p < pos0 + len; ++p) {
+                body.term(c, wcur);
                 const int off = tab[p].off;
                 body.flip(off / (2 * NC), ((off / NC) & 1) ? -1 : 1);
                 add_row(c, trows + off);
-                body.term(c, wh * tab[p].w);
+                wcur = wh * tab[p].w;
             }
+            body.term(c, wcur);
             s = seg_end;
         }
     }

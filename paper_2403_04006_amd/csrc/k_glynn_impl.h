@@ -52,17 +52,17 @@ __global__ __launch_bounds__(kBlock) void glynn_bin(const GlynnArgs a) {
             for (int k = 0; k < a.n_time; ++k)
                 if ((g >> k) & 1ull) add_row(c, trows + (size_t)k * 2 * NC);
             double w = (__builtin_popcountll(g) & 1) ? -1.0 : 1.0;
-            cfma_to(acc, w, product_unit_powers(c));
             const uint64_t end = start + count;
+            // each pass takes the term of state t-1 and moves the sums to state t
             for (uint64_t t = start + 1; t < end; ++t) {
                 const int i = __builtin_ctzll(t);
                 // the new value of Gray bit i is 1 - bit (i+1) of t:
                 // 1 -> digit up -> -2B row (sel 0); 0 -> +2B row (sel 1)
                 const int sel = (int)((t >> (i + 1)) & 1ull);
-                add_row(c, trows + ((size_t)i * 2 + sel) * NC);
+                cfma_to(acc, w, product_then_add(c, trows + ((size_t)i * 2 + sel) * NC));
                 w = -w;
-                cfma_to(acc, w, product_unit_powers(c));
             }
+            cfma_to(acc, w, product_unit_powers(c));
             acc.re *= wl;
             acc.im *= wl;
         }
@@ -110,11 +110,15 @@ __global__ __launch_bounds__(kBlock) void glynn_mix(const GlynnArgs a) {
                 if (gi[k]) fma_row(c, (double)gi[k], trows + (size_t)k * 2 * NC);
             const StepEntry* tab = refl ? a.tab_bwd : a.tab_fwd;
             cplx seg{0.0, 0.0};
-            cfma_to(seg, tab[pos0].w, product_powers(c, a.kap));
+            // each pass takes the term of the current state, then applies
+            // the next step's row (its loads overlap the product)
+            double wcur = tab[pos0].w;
             for (int p = pos0 + 1; p < pos0 + len; ++p) {
+                cfma_to(seg, wcur, product_powers(c, a.kap));
                 add_row(c, trows + tab[p].off);
-                cfma_to(seg, tab[p].w, product_powers(c, a.kap));
+                wcur = tab[p].w;
             }
+            cfma_to(seg, wcur, product_powers(c, a.kap));
             cfma_to(acc, wh, seg);
             s = seg_end;
         }

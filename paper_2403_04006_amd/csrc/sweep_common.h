@@ -22,6 +22,17 @@ __device__ __forceinline__ cplx product_unit_powers(const cplx (&c)[NC]) {
     }
 }
 
+// prod_j c_j of the current sums, then c += r: the row update of the next
+// Gray step is placed after the product that still needs the old sums, so
+// the row's scalar loads are in flight while the product chain runs instead
+// of stalling the step's start.
+template <int NC>
+__device__ __forceinline__ cplx product_then_add(cplx (&c)[NC], const cplx* __restrict__ r) {
+    const cplx p = product_unit_powers(c);
+    add_row(c, r);
+    return p;
+}
+
 // prod_j c_j^{kap_j}; kap_j >= 1 are wavefront-uniform (kernel arguments).
 template <int NC, class KapT>
 __device__ __forceinline__ cplx product_powers(const cplx (&c)[NC], const KapT* kap) {
