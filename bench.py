@@ -165,6 +165,40 @@ def main() -> int:
                       "workload": "12-mode mesh, 132 angles, 8 photons, 4096 output patterns"}
         print(f"# grad/forward {tb / tf:.2f}", file=sys.stderr, flush=True)
 
+    # kernel-level reverse/forward sweep time for one collision-free block
+    # (the derivatives of every entry from one reverse sweep, against the
+    # forward sweep of the same block), both timed with the sweep events
+    grad_kernel = None
+    if not args.no_grad:
+        grad_kernel = []
+        for nk in (20, n):
+            Uk = torch.from_numpy(workloads.collision_free_block(nk, 0)).to(dev)
+            onesk = np.ones(nk, np.int32)
+            pk = pq.PatternSet([onesk], [onesk], nk)
+            gk = torch.ones(1, dtype=torch.complex128, device=dev)
+            # sustained load first (the clock ramps up under load), then the
+            # forward and reverse sweeps back to back, each over ~0.1 s or more
+            reps_f = max(10, int(0.1 / (2.9e-3 * 2.0 ** (nk - 30))))
+            reps_b = max(4, reps_f // 4)
+            for _ in range(reps_f):
+                eng.perm(Uk, onesk, onesk)
+            eng.grad_patterns(Uk, pk, gk)
+            torch.cuda.synchronize()
+            eng.profile(True)
+            eng.profile_read()
+            for _ in range(reps_f):
+                eng.perm(Uk, onesk, onesk)
+            torch.cuda.synchronize()
+            nf, msf = eng.profile_read()
+            for _ in range(reps_b):
+                eng.grad_patterns(Uk, pk, gk)
+            torch.cuda.synchronize()
+            nb, msb = eng.profile_read()
+            eng.profile(False)
+            grad_kernel.append({"n": nk, "forward_sweep_ms": msf / nf, "reverse_sweep_ms": msb / nb,
+                                "ratio": (msb / nb) / (msf / nf)})
+        print(f"# reverse/forward sweeps: {grad_kernel}", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -215,6 +249,7 @@ def main() -> int:
         },
         "cpu_baseline": cpu,
         "grad_forward": grad_ratio,
+        "grad_kernel": grad_kernel,
     }
     print(json.dumps(line), flush=True)
     eng.close()

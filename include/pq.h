@@ -159,9 +159,11 @@ int pq_perm_many(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m,
  *   dU     device, m x m, leading dimension lddu >= m; OVERWRITTEN
  *          (entries outside every pattern's support are set to 0).
  * Per pattern the compact matrix may have at most PQ_GRAD_MAX_DIM distinct
- * rows and columns (PQ_ERANGE otherwise).
+ * rows and columns; more than 24 distinct columns are supported only when
+ * every occupation is 0 or 1 (collision-free patterns; PQ_ERANGE otherwise).
+ * Calls that overlap on one ctx are not allowed (the ctx is not thread-safe).
  */
-#define PQ_GRAD_MAX_DIM 24
+#define PQ_GRAD_MAX_DIM 32
 int pq_perm_grad(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m,
                  int32_t batch, const int32_t* S, const int32_t* T,
                  const pq_c128* gperm, pq_c128* perm,

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libpq.so")
 PQ_OK, PQ_EINVAL, PQ_ERANGE, PQ_ENOMEM, PQ_EDEVICE, PQ_ECANCELLED = range(6)
 PQ_OP_PERM, PQ_OP_EXTEND_ROW = 0, 1
 PQ_MAX_N = 48
-PQ_GRAD_MAX_DIM = 24
+PQ_GRAD_MAX_DIM = 32
 
 
 class pq_c128(ctypes.Structure):

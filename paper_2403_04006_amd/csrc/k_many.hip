@@ -127,6 +127,14 @@ hipError_t launch_many(int mode, int ncmax, int var, const ManyArgs& a, hipStrea
     if (mode == 0 && k < (int)(sizeof(g_m_fwd) / sizeof(g_m_fwd[0]))) return g_m_fwd[k](var, a, s);
     if (mode == 1 && k < (int)(sizeof(g_m_ext) / sizeof(g_m_ext[0]))) return g_m_ext[k](var, a, s);
     if (mode == 2 && k < (int)(sizeof(g_m_adj) / sizeof(g_m_adj[0]))) return g_m_adj[k](var, a, s);
+    if (mode == kModeAdjWalk) {
+        switch (ncmax) {
+#define PQ_WCASE(NC) case NC: return launch_adjw_##NC(a, s);
+            PQ_WCLASS(PQ_WCASE)
+#undef PQ_WCASE
+            default: break;
+        }
+    }
     return hipErrorInvalidValue;
 }
 

@@ -27,6 +27,7 @@ namespace {
 
 constexpr uint64_t kFwdMinChunk = 64;
 constexpr uint64_t kFwdChunksPerWave = 2;
+constexpr uint64_t kWalkMinChunk = 256;
 constexpr int kMaxManyEntries = 4;
 
 struct ManyClass {
@@ -105,8 +106,20 @@ int build_many(pq_ctx* ctx, int mode, int32_t m, const std::vector<PatternSpec>&
             continue;
         }
         const int ncmax = ((p.nc + 3) / 4) * 4;
+        // wide collision-free patterns take the walk kernel (four lanes per term)
+        bool walk = false;
+        if (adj && p.binary && ncmax >= kWalkMinCols && ncmax <= kWalkMaxCols) {
+            Plan pw;
+            plan_sparse(ps.rows, ps.cols, !ext, pw, ext, kWalkLaneStates);
+            if (!pw.status && !pw.trivial && pw.n_lane <= 4 && pw.n_time <= ncmax - 5) {
+                p = pw;
+                walk = true;
+            }
+        }
         if (ext && ncmax > kMaxExtendCols) return ctx->fail(PQ_ERANGE, "pattern %zu: more than %d columns", k, kMaxExtendCols);
-        if (adj && ncmax > kManyMaxAdjCols) return ctx->fail(PQ_ERANGE, "pattern %zu: more than %d columns", k, kManyMaxAdjCols);
+        if (adj && !walk && ncmax > kManyMaxAdjCols)
+            return ctx->fail(PQ_ERANGE, "pattern %zu: more than %d columns needs every mode at most once", k,
+                             kManyMaxAdjCols);
         b.nc = p.nc;
         b.ncmax = ncmax;
         b.r = p.r;
@@ -130,7 +143,7 @@ int build_many(pq_ctx* ctx, int mode, int32_t m, const std::vector<PatternSpec>&
         bool bin = true;
         for (int i = 0; i < p.n_lane; ++i) bin = bin && p.lane_radix[i] == 2;
         for (int i = 0; i < p.n_time; ++i) bin = bin && p.time_radix[i] == 2;
-        if (adj) {
+        if (adj && !walk) {
             // the adjoint's inner digits: the lowest KA time digits
             const int ka = std::min(ncmax <= 12 ? 2 : 1, p.n_time);
             int mi = 1;
@@ -164,7 +177,7 @@ int build_many(pq_ctx* ctx, int mode, int32_t m, const std::vector<PatternSpec>&
             dpat_off[k] = (int64_t)dpat_elems;
             dpat_elems += (size_t)p.r * p.nc;
         }
-        const int kmode = adj ? kModeAdj : (ext ? kModeExt : kModeFwd);
+        const int kmode = adj ? (walk ? kModeAdjWalk : kModeAdj) : (ext ? kModeExt : kModeFwd);
         const int var = (bin ? 2 : 0) + (unit ? 1 : 0);
         by_class[std::make_tuple(kmode, ncmax, var)].push_back((int)k);
     }
@@ -187,10 +200,15 @@ int build_many(pq_ctx* ctx, int mode, int32_t m, const std::vector<PatternSpec>&
         }
         C.slot_doubles = C.mode == kModeFwd ? 4 : (C.mode == kModeExt ? 4 * C.ncmax : 4 + 2 * rmax * C.ncmax);
         uint64_t chunk = 0;
-        if (C.mode != kModeAdj) {
+        if (C.mode == kModeFwd || C.mode == kModeExt) {
             const uint64_t waves = (uint64_t)ctx->num_cu * 4 * 2;
             chunk = (total + waves * kFwdChunksPerWave - 1) / (waves * kFwdChunksPerWave);
             if (chunk < kFwdMinChunk) chunk = kFwdMinChunk;
+        } else if (C.mode == kModeAdjWalk) {
+            // two rounds of two resident wavefronts per SIMD
+            const uint64_t waves = (uint64_t)ctx->num_cu * 4 * 2 * 2;
+            chunk = (total + waves - 1) / waves;
+            if (chunk < kWalkMinChunk) chunk = kWalkMinChunk;
         }
         std::vector<MChunk> cc;
         int slot = 0;
@@ -199,7 +217,9 @@ int build_many(pq_ctx* ctx, int mode, int32_t m, const std::vector<PatternSpec>&
             BJob& b = hj[id];
             // adjoint chunks are whole periods of its inner digits
             const uint64_t len = C.mode == kModeAdj ? (uint64_t)b.m_inner : chunk;
-            const uint64_t n = (b.time_states + len - 1) / len;
+            uint64_t n = (b.time_states + len - 1) / len;
+            // walk classes: whole workgroups per pattern (padding walks are empty)
+            if (C.mode == kModeAdjWalk) n = (n + kWalkWaves - 1) / kWalkWaves * kWalkWaves;
             b.nchunks = (int32_t)n;
             b.slot_base = slot;
             pat_slot[id] = slot;
@@ -209,12 +229,14 @@ int build_many(pq_ctx* ctx, int mode, int32_t m, const std::vector<PatternSpec>&
                 ch.pat = id;
                 ch.slot = slot + (int32_t)q;
                 ch.start = q * len;
-                ch.count = std::min(len, b.time_states - q * len);
+                ch.count = q * len < b.time_states ? std::min(len, b.time_states - q * len) : 0;
                 cc.push_back(ch);
             }
             slot += (int)n;
         }
-        std::stable_sort(cc.begin(), cc.end(), [](const MChunk& x, const MChunk& y) { return x.count > y.count; });
+        // longest first; walk classes keep every pattern's workgroup groups together
+        if (C.mode != kModeAdjWalk)
+            std::stable_sort(cc.begin(), cc.end(), [](const MChunk& x, const MChunk& y) { return x.count > y.count; });
         C.first_chunk = (int)hch.size();
         C.nchunks = (int)cc.size();
         C.slot_off = (int64_t)partial_doubles;

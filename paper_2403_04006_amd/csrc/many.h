@@ -25,6 +25,12 @@ namespace pq {
 constexpr int kModeFwd = 0;       // forward sums (PERM jobs)
 constexpr int kModeExt = 1;       // Laplace expansion along a new row (EXTEND_ROW jobs)
 constexpr int kModeAdj = 2;       // reverse sweep: derivatives and forward sums
+constexpr int kModeAdjWalk = 3;   // reverse sweep of wide collision-free patterns (k_adjw_impl.h)
+constexpr int kWalkMinCols = 16;  // padded column range of the walk classes
+constexpr int kWalkMaxCols = 32;
+constexpr int kWalkLaneStates = 16;   // lane-digit states per wavefront (four lanes per term)
+constexpr int kWalkTerms = 16;        // terms per wavefront
+constexpr int kWalkWaves = 4;         // wavefronts per workgroup, all on one pattern
 constexpr int kManyMaxAdjCols = 24;   // widest adjoint class
 constexpr int kAdjBlock = 64;         // one wavefront per workgroup in adjoint mode
 

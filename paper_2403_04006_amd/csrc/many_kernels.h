@@ -10,6 +10,8 @@ namespace pq {
     X(0, 36) X(0, 40) X(0, 44) X(0, 48)
 #define PQ_MCLASS_EXT(X) X(1, 4) X(1, 8) X(1, 12) X(1, 16) X(1, 20) X(1, 24)
 #define PQ_MCLASS_ADJ(X) X(2, 4) X(2, 8) X(2, 12) X(2, 16) X(2, 20) X(2, 24)
+// reverse-sweep walk classes (binary digits, unit powers), padded column counts
+#define PQ_WCLASS(X) X(16) X(20) X(24) X(28) X(32)
 
 // variant: 2 * binary_walk + unit_powers
 #define PQ_MDECL(MODE, NC) hipError_t launch_many_##MODE##_##NC(int var, const ManyArgs& a, hipStream_t s);
@@ -17,6 +19,9 @@ PQ_MCLASS_FWD(PQ_MDECL)
 PQ_MCLASS_EXT(PQ_MDECL)
 PQ_MCLASS_ADJ(PQ_MDECL)
 #undef PQ_MDECL
+#define PQ_WDECL(NC) hipError_t launch_adjw_##NC(const ManyArgs& a, hipStream_t s);
+PQ_WCLASS(PQ_WDECL)
+#undef PQ_WDECL
 
 hipError_t launch_many(int mode, int ncmax, int var, const ManyArgs& a, hipStream_t s);
 hipError_t launch_many_final(const ManyFinalArgs& a, hipStream_t s);

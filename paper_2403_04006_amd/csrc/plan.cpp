@@ -27,8 +27,8 @@ bool term_count(const Side& it, uint64_t& terms, int& fixed_index) {
 }
 
 // Choose lane digits among the free rows: the subset whose radix product is
-// the largest value <= 64 (first subset found in row order for each product).
-static void choose_lane_digits(int nfree, const int* radix, int* chosen, int& nchosen, int& product) {
+// the largest value <= cap (first subset found in row order for each product).
+static void choose_lane_digits(int nfree, const int* radix, int cap, int* chosen, int& nchosen, int& product) {
     // reach[p] = bitmask (over free rows, nfree <= 48) giving product p
     uint64_t reach[65];
     bool ok[65];
@@ -36,10 +36,10 @@ static void choose_lane_digits(int nfree, const int* radix, int* chosen, int& nc
     ok[1] = true;
     reach[1] = 0;
     for (int i = 0; i < nfree; ++i) {
-        for (int p = 64; p >= 1; --p) {
+        for (int p = cap; p >= 1; --p) {
             if (!ok[p]) continue;
             long q = (long)p * radix[i];
-            if (q > 64 || ok[q]) continue;
+            if (q > cap || ok[q]) continue;
             // only extend subsets that do not already use row i
             if (reach[p] >> i & 1ull) continue;
             ok[q] = true;
@@ -47,7 +47,7 @@ static void choose_lane_digits(int nfree, const int* radix, int* chosen, int& nc
         }
     }
     int best = 1;
-    for (int p = 64; p >= 1; --p)
+    for (int p = cap; p >= 1; --p)
         if (ok[p]) { best = p; break; }
     product = best;
     nchosen = 0;
@@ -55,7 +55,7 @@ static void choose_lane_digits(int nfree, const int* radix, int* chosen, int& nc
         if (reach[best] >> i & 1ull) chosen[nchosen++] = i;
 }
 
-void plan_sparse(const Side& rows, const Side& cols, bool allow_transpose, Plan& p, bool extend) {
+void plan_sparse(const Side& rows, const Side& cols, bool allow_transpose, Plan& p, bool extend, int max_lane_states) {
     p = Plan();
     int nr = 0, nc_ = 0;
     for (int i = 0; i < rows.count; ++i) nr += rows.mult[i];
@@ -104,7 +104,8 @@ void plan_sparse(const Side& rows, const Side& cols, bool allow_transpose, Plan&
     for (int k = 0; k < nfree; ++k) free_radix[k] = radix[free_idx[k]];
 
     int lane_sel[kMaxDim], nlane = 0, lane_prod = 1;
-    choose_lane_digits(nfree, free_radix, lane_sel, nlane, lane_prod);
+    const int cap = max_lane_states < 1 ? 1 : (max_lane_states > 64 ? 64 : max_lane_states);
+    choose_lane_digits(nfree, free_radix, cap, lane_sel, nlane, lane_prod);
     bool used[kMaxDim];
     memset(used, 0, sizeof(used));
     int pos = 0;

@@ -45,7 +45,10 @@ struct Side {
 // plans the row sweep of a Laplace expansion along one more row: the column
 // side then holds one photon more than the row side, the rows are always the
 // iterated side, and n is the row count (zero rows is allowed).
-void plan_sparse(const Side& rows, const Side& cols, bool allow_transpose, Plan& p, bool extend = false);
+// `max_lane_states` (1..64) bounds the product of the lane digits' radices:
+// 64 when every lane of a wavefront owns one term, 16 when four lanes share one.
+void plan_sparse(const Side& rows, const Side& cols, bool allow_transpose, Plan& p, bool extend = false,
+                 int max_lane_states = 64);
 
 // Plan from dense occupation vectors of length m (validates them).
 void plan_dense(int m, const int32_t* S, const int32_t* T, Plan& p);

@@ -23,11 +23,25 @@ def dev(U):
     return torch.from_numpy(np.ascontiguousarray(U, dtype=np.complex128)).cuda()
 
 
+def oracle_vjp(U, Ss, Ts, g):
+    """oracle.perm_vjp on each pattern's own modes (the oracle's gradient takes
+    at most 128 modes; perm(U_{T,S}) only reads the rows of T and columns of S)."""
+    m = U.shape[0]
+    if m <= 128:
+        return oracle.perm_vjp(U, Ss, Ts, g)
+    dU = np.zeros((m, m), dtype=np.complex128)
+    for S, T, gp in zip(Ss, Ts, g):
+        modes = np.union1d(np.flatnonzero(S), np.flatnonzero(T))
+        sub = oracle.perm_vjp(U[np.ix_(modes, modes)], [np.asarray(S)[modes]], [np.asarray(T)[modes]], [gp])
+        dU[np.ix_(modes, modes)] += sub
+    return dU
+
+
 def check(eng, U, Ss, Ts, g, tol=1e-10):
     dU, perm = eng.perm_grad(dev(U), Ss, Ts, torch.from_numpy(np.asarray(g, dtype=np.complex128)))
     dU = dU.cpu().numpy()
     perm = perm.cpu().numpy()
-    ref = oracle.perm_vjp(U, Ss, Ts, g)
+    ref = oracle_vjp(U, Ss, Ts, g)
     scale = max(1e-300, np.max(np.abs(ref)))
     err = np.max(np.abs(dU - ref)) / scale
     for p, (S, T) in enumerate(zip(Ss, Ts)):
@@ -98,3 +112,116 @@ def test_trivial_patterns_have_zero_gradient(eng):
                              torch.ones(2, dtype=torch.complex128))
     assert np.all(dU.cpu().numpy() == 0)
     assert np.array_equal(perm.cpu().numpy(), np.array([0, 1], dtype=np.complex128))
+
+
+def _wide_patterns(m, ns, seed):
+    rng = np.random.default_rng(seed)
+    Ss, Ts = [], []
+    for n in ns:
+        S = np.zeros(m, np.int32)
+        T = np.zeros(m, np.int32)
+        S[rng.choice(m, n, replace=False)] = 1
+        T[rng.choice(m, n, replace=False)] = 1
+        Ss.append(S)
+        Ts.append(T)
+    g = [complex(rng.standard_normal(), rng.standard_normal()) for _ in ns]
+    return Ss, Ts, g
+
+
+@pytest.mark.parametrize("ns", [(13,), (16, 14), (17, 8, 3), (20,)])
+def test_wide_collision_free_patterns(eng, ns):
+    # 13..20 distinct columns: the long-walk reverse sweep (four lanes per
+    # term), mixed with small patterns that take the chunked reverse sweep
+    n = max(ns)
+    m = 2 * n * n
+    U = workloads.haar(m, 300 + n)
+    Ss, Ts, g = _wide_patterns(m, ns, n)
+    check(eng, U, Ss, Ts, g, tol=1e-10)
+
+
+def _laplace_check(U, S, T, d, p, tol):
+    # collision-free: sum_j U_ij d perm/dU_ij = perm for every row i of the
+    # pattern, and the same down every column (Laplace expansion)
+    rows = np.flatnonzero(T)
+    cols = np.flatnonzero(S)
+    worst = 0.0
+    for i in rows:
+        terms = U[i, cols] * d[i, cols]
+        worst = max(worst, abs(np.sum(terms) - p) / np.sum(np.abs(terms)))
+    for j in cols:
+        terms = U[rows, j] * d[rows, j]
+        worst = max(worst, abs(np.sum(terms) - p) / np.sum(np.abs(terms)))
+    assert worst < tol, worst
+    return worst
+
+
+@pytest.mark.parametrize("n", [22, 24, 27])
+def test_wide_gradient_sampled_entries(eng, n):
+    # 6, 6 and 7 columns per lane; oracle minors on sampled entries
+    m = 2 * n * n
+    U = workloads.haar(m, n)
+    Ss, Ts, _ = _wide_patterns(m, (n,), 5)
+    S, T = Ss[0], Ts[0]
+    dU, perm = eng.perm_grad(dev(U), [S], [T], torch.ones(1, dtype=torch.complex128))
+    d = np.conj(dU.cpu().numpy())
+    p = complex(perm.cpu().numpy()[0])
+    ref_p = oracle.perm_mult(U, S, T)
+    assert abs(p - ref_p) < 1e-8 * abs(ref_p)
+    _laplace_check(U, S, T, d, p, 1e-9)
+    rows = np.flatnonzero(T)
+    cols = np.flatnonzero(S)
+    for (a, b) in [(0, 0), (5, n - 7), (n - 1, 11), (12, n - 1)]:
+        i, j = rows[a], cols[b]
+        S1, T1 = S.copy(), T.copy()
+        S1[j] -= 1
+        T1[i] -= 1
+        want = oracle.perm_mult(U, S1, T1)
+        assert abs(d[i, j] - want) < 1e-8 * abs(want), (a, b)
+    # entries outside the pattern's support are zero
+    mask = np.ones((m, m), bool)
+    mask[np.ix_(rows, cols)] = False
+    assert np.all(dU.cpu().numpy()[mask] == 0)
+
+
+def test_wide_gradient_full_size_n30(eng):
+    # n = 30 (32 padded columns, 8 per lane): the forward value of the same
+    # sweep against the forward kernel, and the Laplace expansion along every
+    # row and column of the pattern
+    n, m = 30, 1800
+    U = workloads.haar(m, 30)
+    S = np.zeros(m, np.int32)
+    T = np.zeros(m, np.int32)
+    S[:n] = 1
+    T[:n] = 1
+    dU, perm = eng.perm_grad(dev(U), [S], [T], torch.ones(1, dtype=torch.complex128))
+    d = np.conj(dU.cpu().numpy())
+    p = complex(perm.cpu().numpy()[0])
+    pf, _ = eng.perm(dev(U), S, T)
+    pf = complex(pf.cpu().numpy())
+    assert abs(p - pf) < 1e-10 * abs(pf)
+    worst = _laplace_check(U, S, T, d, p, 1e-9)
+    print(f"n=30 gradient: Laplace identity worst relative residual {worst:.2e}")
+
+
+def test_wide_gradient_is_deterministic(eng):
+    n, m = 20, 800
+    U = workloads.haar(m, 31)
+    Ss, Ts, g = _wide_patterns(m, (n, 18), 7)
+    gt = torch.from_numpy(np.asarray(g, dtype=np.complex128))
+    a, _ = eng.perm_grad(dev(U), Ss, Ts, gt)
+    b, _ = eng.perm_grad(dev(U), Ss, Ts, gt)
+    assert torch.equal(a, b)
+
+
+def test_wide_pattern_with_repeats_is_rejected(eng):
+    # more than 24 distinct columns is supported for collision-free patterns only
+    import paper_2403_04006_amd as pq
+    m = 60
+    U = workloads.haar(m, 2)
+    S = np.zeros(m, np.int32)
+    T = np.zeros(m, np.int32)
+    S[:26] = 1
+    T[:24] = 1
+    T[30] = 2
+    with pytest.raises(pq.PqError):
+        eng.perm_grad(dev(U), [S], [T], torch.ones(1, dtype=torch.complex128))
