@@ -41,7 +41,8 @@ struct BJob {
     int8_t lane_radix[kMaxLaneDigits];
     int8_t pad1[2];
     int8_t time_radix[kMaxDim];
-    int8_t kap[kMaxDim];  // padded with 1 up to ncmax
+    int8_t kap[kMaxDim];  // ascending; padding columns (sums 1) repeat the largest power
+    PowSteps pw;          // structure of kap[0..ncmax) for product_grouped
 };
 
 struct BChunk {

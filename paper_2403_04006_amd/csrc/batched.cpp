@@ -239,9 +239,10 @@ static int build_entry(pq_ctx* ctx, const cplx* U, int64_t ldu, int32_t m, const
         for (int i = 0; i < p.n_time; ++i) b.time_radix[i] = (int8_t)p.time_radix[i];
         bool unit = true;
         for (int j = 0; j < b.ncmax; ++j) {
-            b.kap[j] = (int8_t)(j < p.nc ? p.col_kap[j] : 1);
+            b.kap[j] = (int8_t)(j < p.nc ? p.col_kap[j] : (p.nc > 0 ? p.col_kap[p.nc - 1] : 1));
             unit = unit && b.kap[j] == 1;
         }
+        make_pow_steps(b.kap, b.ncmax, b.pw);
         bool bin = true;
         for (int i = 0; i < p.n_lane; ++i) bin = bin && p.lane_radix[i] == 2;
         for (int i = 0; i < p.n_time; ++i) bin = bin && p.time_radix[i] == 2;

@@ -97,6 +97,17 @@ __device__ __forceinline__ void block_reduce_store(cdd v, double* partials) {
 __device__ __forceinline__ cdd to_cdd(cplx v) { return cdd{{v.re, 0.0}, {v.im, 0.0}}; }
 
 // Wavefront index as a scalar (uniform) value.
+// Values that are equal in every lane but computed through per-lane storage
+// (private arrays): mark them uniform so what depends on them (table
+// pointers, loop bounds) stays in scalar registers.
+__device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ double uniform_double(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)b);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 __device__ __forceinline__ uint32_t wave_id_uniform() {
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6)));
 }

@@ -22,14 +22,19 @@
 namespace pq {
 
 // ------------------------------------------------------------ term bodies
-template <int NC, bool UNIT>
+// POW: 0 products of powers through product_grouped, 1 through per-column
+// loops (power steps product_grouped does not cover), -1 chosen per job.
+template <int NC, bool UNIT, int POW = -1>
 struct PermBody {
     cplx acc{0.0, 0.0};
     const int8_t* kap;
+    const PowSteps* pw;
     __device__ __forceinline__ void flip(int, int) {}
     __device__ __forceinline__ void term(const cplx (&c)[NC], double w) {
         if constexpr (UNIT) cfma_to(acc, w, product_unit_powers(c));
-        else cfma_to(acc, w, product_powers(c, kap));
+        else if constexpr (POW == 0) cfma_to(acc, w, product_grouped(c, *pw));
+        else if constexpr (POW == 1) cfma_to(acc, w, product_powers(c, kap));
+        else cfma_to(acc, w, pw->general ? product_powers(c, kap) : product_grouped(c, *pw));
     }
 };
 
@@ -134,23 +139,21 @@ __device__ __forceinline__ double sweep_chunk(const BJob& J, const cplx* __restr
             const int len = (int)(seg_end - s);
             if (!first) wl = lane_init<NC>(base, rows2, J.n_lane, J.lane_states, J.lane_radix, lane, c);
             first = false;
-            int32_t radix_hi[kMaxDim];
-            for (int k = 0; k < n_high; ++k) radix_hi[k] = J.time_radix[J.n_inner + k];
-            int32_t gh[kMaxDim];
-            gray_unrank(n_high, radix_hi, hi, gh);
-            int refl = 0;
+            // high digits at the segment index, inner digits at the table
+            // position (no digit arrays: every value stays uniform)
+            const int8_t* tr = J.time_radix;
+            const int n_in = J.n_inner;
             double wh = 1.0;
-            for (int k = 0; k < n_high; ++k) {
-                refl ^= gh[k] & 1;
-                wh *= digit_weight(radix_hi[k], gh[k]);
-                if (gh[k]) fma_row(c, (double)gh[k], trows + (size_t)(J.n_inner + k) * 2 * NC);
-            }
+            int refl = gray_digits_desc(n_high, [&](int k) { return (int)tr[n_in + k]; }, hi, 0, [&](int k, int g) {
+                wh *= digit_weight((int)tr[n_in + k], g);
+                if (g) fma_row(c, (double)g, trows + (size_t)(n_in + k) * 2 * NC);
+            });
+            refl = uniform_int(refl);
+            wh = uniform_double(wh);
             const int q0 = refl ? (int)M - 1 - pos0 : pos0;
-            int32_t radix_in[16], gi[16];
-            for (int k = 0; k < J.n_inner; ++k) radix_in[k] = J.time_radix[k];
-            gray_unrank(J.n_inner, radix_in, (uint64_t)q0, gi);
-            for (int k = 0; k < J.n_inner; ++k)
-                if (gi[k]) fma_row(c, (double)gi[k], trows + (size_t)k * 2 * NC);
+            gray_digits_desc(n_in, [&](int k) { return (int)tr[k]; }, (uint64_t)q0, 0, [&](int k, int g) {
+                if (g) fma_row(c, (double)g, trows + (size_t)k * 2 * NC);
+            });
             const StepEntry* tab = refl ? tb : tf;
             double wcur = wh * tab[pos0].w;
             for (int p = pos0 + 1; p < pos0 + len; ++p) {
@@ -193,6 +196,7 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(const BatchArgs a) {
         if constexpr (OP == kOpPerm) {
             PermBody<NC, UNIT> body;
             body.kap = J.kap;
+            body.pw = &J.pw;
             const double wl = sweep_chunk<NC, BIN>(J, mat, a.tabs, lane, ch.start, ch.count, body);
             cdd v = wave_reduce(to_cdd(cplx{body.acc.re * wl, body.acc.im * wl}));
             if (lane == 0) store_cdd(slot, v);

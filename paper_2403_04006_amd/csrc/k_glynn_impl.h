@@ -70,7 +70,7 @@ __global__ __launch_bounds__(kBlock) void glynn_bin(const GlynnArgs a) {
     block_reduce_store(to_cdd(acc), a.partials);
 }
 
-template <int NC>
+template <int NC, bool GEN>
 __global__ __launch_bounds__(kBlock) void glynn_mix(const GlynnArgs a) {
     const int lane = threadIdx.x & 63;
     const uint32_t wave = wave_id_uniform();
@@ -92,33 +92,32 @@ __global__ __launch_bounds__(kBlock) void glynn_mix(const GlynnArgs a) {
             const int len = (int)(seg_end - s);
             cplx c[NC];
             wl = lane_init<NC>(a, lane, c);
-            // high digits (Gray state of the segment index)
-            int32_t gh[kMaxDim];
-            gray_unrank(n_high, a.time_radix + a.n_inner, hi, gh);
-            int refl = 0;
+            // high digits (Gray state of the segment index), then the inner
+            // digits at the forward-table index of position pos0 (no digit
+            // arrays: every value stays uniform)
             double wh = 1.0;
-            for (int k = 0; k < n_high; ++k) {
-                refl ^= gh[k] & 1;
-                wh *= digit_weight(a.time_radix[a.n_inner + k], gh[k]);
-                if (gh[k]) fma_row(c, (double)gh[k], trows + (size_t)(a.n_inner + k) * 2 * NC);
-            }
-            // inner digits at the forward-table index of position pos0
+            int refl = gray_digits_desc(n_high, [&](int k) { return a.time_radix[a.n_inner + k]; }, hi, 0,
+                                        [&](int k, int g) {
+                                            wh *= digit_weight(a.time_radix[a.n_inner + k], g);
+                                            if (g) fma_row(c, (double)g, trows + (size_t)(a.n_inner + k) * 2 * NC);
+                                        });
+            refl = uniform_int(refl);
+            wh = uniform_double(wh);
             const int q0 = refl ? (int)M - 1 - pos0 : pos0;
-            int32_t gi[16];
-            gray_unrank(a.n_inner, a.time_radix, (uint64_t)q0, gi);
-            for (int k = 0; k < a.n_inner; ++k)
-                if (gi[k]) fma_row(c, (double)gi[k], trows + (size_t)k * 2 * NC);
+            gray_digits_desc(a.n_inner, [&](int k) { return a.time_radix[k]; }, (uint64_t)q0, 0, [&](int k, int g) {
+                if (g) fma_row(c, (double)g, trows + (size_t)k * 2 * NC);
+            });
             const StepEntry* tab = refl ? a.tab_bwd : a.tab_fwd;
             cplx seg{0.0, 0.0};
             // each pass takes the term of the current state, then applies
             // the next step's row (its loads overlap the product)
             double wcur = tab[pos0].w;
             for (int p = pos0 + 1; p < pos0 + len; ++p) {
-                cfma_to(seg, wcur, product_powers(c, a.kap));
+                cfma_to(seg, wcur, (GEN ? product_powers(c, a.kap) : product_grouped(c, a.pw)));
                 add_row(c, trows + tab[p].off);
                 wcur = tab[p].w;
             }
-            cfma_to(seg, wcur, product_powers(c, a.kap));
+            cfma_to(seg, wcur, (GEN ? product_powers(c, a.kap) : product_grouped(c, a.pw)));
             cfma_to(acc, wh, seg);
             s = seg_end;
         }
@@ -129,28 +128,33 @@ __global__ __launch_bounds__(kBlock) void glynn_mix(const GlynnArgs a) {
 }
 
 // ------------------------------------------------------------- launchers
+// kind: kSweepMix (mixed digits, power steps within product_grouped's range),
+// kSweepBin (binary digits, unit powers), kSweepMixGeneral (any powers).
 template <int NC>
-static hipError_t launch_one(bool binary, const GlynnArgs& a, int grid, hipStream_t st) {
-    if (binary)
+static hipError_t launch_one(int kind, const GlynnArgs& a, int grid, hipStream_t st) {
+    if (kind == kSweepBin)
         hipLaunchKernelGGL(glynn_bin<NC>, dim3(grid), dim3(kBlock), 0, st, a);
+    else if (kind == kSweepMix)
+        hipLaunchKernelGGL((glynn_mix<NC, false>), dim3(grid), dim3(kBlock), 0, st, a);
     else
-        hipLaunchKernelGGL(glynn_mix<NC>, dim3(grid), dim3(kBlock), 0, st, a);
+        hipLaunchKernelGGL((glynn_mix<NC, true>), dim3(grid), dim3(kBlock), 0, st, a);
     return hipGetLastError();
 }
 
 template <int NC>
-static int occupancy_one(bool binary) {
+static int occupancy_one(int kind) {
     int nb = 0;
-    hipError_t e = binary
+    hipError_t e = kind == kSweepBin
         ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, glynn_bin<NC>, kBlock, 0)
-        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, glynn_mix<NC>, kBlock, 0);
+        : (kind == kSweepMix ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, glynn_mix<NC, false>, kBlock, 0)
+                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, glynn_mix<NC, true>, kBlock, 0));
     return e == hipSuccess ? nb : 0;
 }
 
 #define PQ_INST(NC)                                                                \
-    hipError_t launch_glynn_##NC(bool b, const GlynnArgs& a, int g, hipStream_t s) { \
-        return launch_one<NC>(b, a, g, s);                                         \
+    hipError_t launch_glynn_##NC(int k, const GlynnArgs& a, int g, hipStream_t s) { \
+        return launch_one<NC>(k, a, g, s);                                         \
     }                                                                              \
-    int occupancy_glynn_##NC(bool b) { return occupancy_one<NC>(b); }
+    int occupancy_glynn_##NC(int k) { return occupancy_one<NC>(k); }
 
 }  // namespace pq

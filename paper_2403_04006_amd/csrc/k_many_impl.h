@@ -76,7 +76,7 @@ __device__ __forceinline__ void store_cdd_slot(double* p, cdd v) {
     p[0] = v.re.hi; p[1] = v.re.lo; p[2] = v.im.hi; p[3] = v.im.lo;
 }
 
-template <int MODE, int NC, bool BIN, bool UNIT>
+template <int MODE, int NC, bool BIN, bool UNIT, bool GEN = false>
 __global__ __launch_bounds__(64) void many_kernel(const ManyArgs a) {
     const int lane = threadIdx.x & 63;
     const int ci = (int)blockIdx.x;
@@ -86,8 +86,9 @@ __global__ __launch_bounds__(64) void many_kernel(const ManyArgs a) {
     const cplx* mat = a.mat + J.mat_off;
     double* slot = a.partials + (size_t)ch.slot * a.slot_doubles;
     if constexpr (MODE == kModeFwd) {
-        PermBody<NC, UNIT> body;
+        PermBody<NC, UNIT, GEN ? 1 : 0> body;
         body.kap = J.kap;
+        body.pw = &J.pw;
         const double wl = sweep_chunk<NC, BIN>(J, mat, a.tabs, lane, ch.start, ch.count, body);
         cdd v = wave_reduce(to_cdd(cplx{body.acc.re * wl, body.acc.im * wl}));
         if (lane == 0) store_cdd_slot(slot, v);

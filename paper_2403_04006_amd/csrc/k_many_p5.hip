@@ -5,6 +5,7 @@
 namespace pq {
 
 #define PQ_MKER(MODE, NC, B, U) many_kernel<MODE, NC, B, U>
+#define PQ_MKERG(MODE, NC, B) many_kernel<MODE, NC, B, false, (MODE) == 0>
 #define PQ_MINST(MODE, NC)                                                                       \
     hipError_t launch_many_##MODE##_##NC(int var, const ManyArgs& a, hipStream_t s) {              \
         const dim3 grid(a.nchunks > 0 ? a.nchunks : 1), block(64);                               \
@@ -12,7 +13,10 @@ namespace pq {
             case 0: hipLaunchKernelGGL((PQ_MKER(MODE, NC, false, false)), grid, block, 0, s, a); break; \
             case 1: hipLaunchKernelGGL((PQ_MKER(MODE, NC, false, true)), grid, block, 0, s, a); break; \
             case 2: hipLaunchKernelGGL((PQ_MKER(MODE, NC, true, false)), grid, block, 0, s, a); break; \
-            default: hipLaunchKernelGGL((PQ_MKER(MODE, NC, true, true)), grid, block, 0, s, a); break; \
+            case 3: hipLaunchKernelGGL((PQ_MKER(MODE, NC, true, true)), grid, block, 0, s, a); break; \
+            case 4: hipLaunchKernelGGL((PQ_MKERG(MODE, NC, false)), grid, block, 0, s, a); break; \
+            case 6: hipLaunchKernelGGL((PQ_MKERG(MODE, NC, true)), grid, block, 0, s, a); break; \
+            default: return hipErrorInvalidValue;                                                \
         }                                                                                        \
         return hipGetLastError();                                                                \
     }

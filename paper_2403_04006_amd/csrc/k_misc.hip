@@ -155,22 +155,22 @@ hipError_t launch_fill(cplx* perm, cplx* amp, cplx value, hipStream_t s) {
 }
 
 // --------------------------------------------------------------- dispatch
-typedef hipError_t (*launch_fn)(bool, const GlynnArgs&, int, hipStream_t);
-typedef int (*occ_fn)(bool);
+typedef hipError_t (*launch_fn)(int, const GlynnArgs&, int, hipStream_t);
+typedef int (*occ_fn)(int);
 
 #define PQ_LAUNCH_PTR(NC) &launch_glynn_##NC,
 #define PQ_OCC_PTR(NC) &occupancy_glynn_##NC,
 static const launch_fn g_launch[kMaxDim] = {PQ_NC_LIST(PQ_LAUNCH_PTR)};
 static const occ_fn g_occ[kMaxDim] = {PQ_NC_LIST(PQ_OCC_PTR)};
 
-hipError_t launch_glynn(bool binary, int nc, const GlynnArgs& a, int grid, hipStream_t s) {
-    if (nc < 1 || nc > kMaxDim) return hipErrorInvalidValue;
-    return g_launch[nc - 1](binary, a, grid, s);
+hipError_t launch_glynn(int kind, int nc, const GlynnArgs& a, int grid, hipStream_t s) {
+    if (nc < 1 || nc > kMaxDim || kind < 0 || kind > 2) return hipErrorInvalidValue;
+    return g_launch[nc - 1](kind, a, grid, s);
 }
 
-int occupancy_glynn(bool binary, int nc) {
-    if (nc < 1 || nc > kMaxDim) return 0;
-    return g_occ[nc - 1](binary);
+int occupancy_glynn(int kind, int nc) {
+    if (nc < 1 || nc > kMaxDim || kind < 0 || kind > 2) return 0;
+    return g_occ[nc - 1](kind);
 }
 
 }  // namespace pq

@@ -12,16 +12,21 @@ namespace pq {
     X(32) X(33) X(34) X(35) X(36) X(37) X(38) X(39) X(40) X(41) X(42) X(43) X(44) X(45) X(46)    \
     X(47) X(48)
 
+// sweep kinds
+constexpr int kSweepMix = 0;         // mixed digits or powers (product_grouped)
+constexpr int kSweepBin = 1;         // binary digits, unit powers
+constexpr int kSweepMixGeneral = 2;  // powers whose steps product_grouped does not cover
+
 #define PQ_DECL(NC)                                                              \
-    hipError_t launch_glynn_##NC(bool binary, const GlynnArgs& a, int grid, hipStream_t s); \
-    int occupancy_glynn_##NC(bool binary);
+    hipError_t launch_glynn_##NC(int kind, const GlynnArgs& a, int grid, hipStream_t s); \
+    int occupancy_glynn_##NC(int kind);
 PQ_NC_LIST(PQ_DECL)
 #undef PQ_DECL
 
 // Forward sweep for nc distinct columns (1..kMaxDim).
-hipError_t launch_glynn(bool binary, int nc, const GlynnArgs& a, int grid, hipStream_t s);
+hipError_t launch_glynn(int kind, int nc, const GlynnArgs& a, int grid, hipStream_t s);
 // Resident 256-thread workgroups per compute unit for that kernel (0 on error).
-int occupancy_glynn(bool binary, int nc);
+int occupancy_glynn(int kind, int nc);
 
 hipError_t launch_prep(const PrepArgs& a, hipStream_t s);
 hipError_t launch_table(const TableArgs& a, hipStream_t s);

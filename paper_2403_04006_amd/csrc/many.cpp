@@ -137,9 +137,10 @@ int build_many(pq_ctx* ctx, int mode, int32_t m, const std::vector<PatternSpec>&
         for (int i = 0; i < p.n_time; ++i) b.time_radix[i] = (int8_t)p.time_radix[i];
         bool unit = true;
         for (int j = 0; j < ncmax; ++j) {
-            b.kap[j] = (int8_t)(j < p.nc ? p.col_kap[j] : 1);
+            b.kap[j] = (int8_t)(j < p.nc ? p.col_kap[j] : (p.nc > 0 ? p.col_kap[p.nc - 1] : 1));
             unit = unit && b.kap[j] == 1;
         }
+        make_pow_steps(b.kap, ncmax, b.pw);
         bool bin = true;
         for (int i = 0; i < p.n_lane; ++i) bin = bin && p.lane_radix[i] == 2;
         for (int i = 0; i < p.n_time; ++i) bin = bin && p.time_radix[i] == 2;
@@ -178,7 +179,9 @@ int build_many(pq_ctx* ctx, int mode, int32_t m, const std::vector<PatternSpec>&
             dpat_elems += (size_t)p.r * p.nc;
         }
         const int kmode = adj ? (walk ? kModeAdjWalk : kModeAdj) : (ext ? kModeExt : kModeFwd);
-        const int var = (bin ? 2 : 0) + (unit ? 1 : 0);
+        // variant: 2 * binary digits + unit powers, + 4 for powers whose steps
+        // the grouped product does not cover (forward jobs only)
+        const int var = (bin ? 2 : 0) + (unit ? 1 : 0) + (!unit && kmode == kModeFwd && b.pw.general ? 4 : 0);
         by_class[std::make_tuple(kmode, ncmax, var)].push_back((int)k);
     }
     E.ntab = (int)sigs.size();

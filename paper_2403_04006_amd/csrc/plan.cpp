@@ -89,7 +89,19 @@ void plan_sparse(const Side& rows, const Side& cols, bool allow_transpose, Plan&
     p.fixed_row = use_cols ? f_cols : f_rows;
     p.r = it.count;
     p.nc = pw.count;
-    for (int j = 0; j < pw.count; ++j) { p.col_mode[j] = pw.mode[j]; p.col_kap[j] = pw.mult[j]; }
+    // power columns in ascending power (stable in mode order): products of
+    // powers then take one multiply per column plus one per change of power
+    {
+        int order[kMaxDim];
+        for (int j = 0; j < pw.count; ++j) order[j] = j;
+        for (int a = 1; a < pw.count; ++a) {
+            const int v = order[a];
+            int b = a - 1;
+            while (b >= 0 && pw.mult[order[b]] > pw.mult[v]) { order[b + 1] = order[b]; --b; }
+            order[b + 1] = v;
+        }
+        for (int j = 0; j < pw.count; ++j) { p.col_mode[j] = pw.mode[order[j]]; p.col_kap[j] = pw.mult[order[j]]; }
+    }
     p.scale = p.n > 0 ? ldexp(1.0, -(p.n - 1)) : 1.0;
 
     // radices in ascending-mode order

@@ -19,7 +19,7 @@ struct Plan {
     int row_mode[kMaxDim] = {};
     int row_mu[kMaxDim] = {};
     int row_radix[kMaxDim] = {};
-    int col_mode[kMaxDim] = {};
+    int col_mode[kMaxDim] = {};   // power columns, ascending power (ties in mode order)
     int col_kap[kMaxDim] = {};
     int n_lane = 0, lane_states = 1;
     int n_time = 0, n_inner = 0, m_inner = 1;

@@ -47,6 +47,28 @@ struct StepEntry {
 };
 
 // Argument block of the forward sweep kernels (passed by value).
+// Power structure of prod_j c_j^{kap_j} over columns sorted by ascending power
+// (see product_grouped): bit j of step[q] is set when the power rises by more
+// than q from column j-1 to column j; low is the power of column 0.  general
+// is 1 when a rise exceeds 3 or low exceeds 4 (the per-column loops are used).
+struct PowSteps {
+    uint64_t step[3];
+    int32_t low;
+    int32_t general;
+};
+
+template <class KapT>
+inline void make_pow_steps(const KapT* kap, int n, PowSteps& ps) {
+    ps.step[0] = ps.step[1] = ps.step[2] = 0;
+    ps.low = n > 0 ? (int)kap[0] : 1;
+    ps.general = (ps.low < 1 || ps.low > 4) ? 1 : 0;
+    for (int j = 1; j < n; ++j) {
+        const int d = (int)kap[j] - (int)kap[j - 1];
+        if (d < 0 || d > 3) ps.general = 1;
+        for (int q = 0; q < d && q < 3; ++q) ps.step[q] |= 1ull << j;
+    }
+}
+
 struct GlynnArgs {
     const cplx* B;        // [r][NC]   compact matrix, iterated rows in digit order
     const cplx* rows2;    // [r][2][NC] per row: -2B (digit up), +2B (digit down)
@@ -63,7 +85,8 @@ struct GlynnArgs {
     int32_t m_inner;      // product of inner radices
     int32_t lane_radix[kMaxLaneDigits];
     int32_t time_radix[kMaxDim];
-    int32_t kap[kMaxDim]; // column powers
+    int32_t kap[kMaxDim]; // column powers (ascending)
+    PowSteps pw;          // their structure for product_grouped
 };
 
 // Prep kernel arguments: gather the compact matrix from U and build the
@@ -119,6 +142,26 @@ PQ_HD void gray_unrank(int d, const int32_t* radix, uint64_t rank, int32_t* g, i
         g[k] = par ? radix[k] - 1 - a[k] : a[k];
         par ^= (g[k] & 1);
     }
+}
+
+// The same digits without a digit array: f(k, g_k) for k = d-1 down to 0,
+// with radix(k) the radix of digit k.  Each digit is recovered by dividing by
+// the product of the radices below it, so every value stays wavefront-uniform.
+// Returns the parity of the digit sum (with parity_in).
+template <class Radix, class F>
+PQ_HD int gray_digits_desc(int d, Radix radix, uint64_t rank, int parity_in, F&& f) {
+    uint64_t below = 1;
+    for (int k = 0; k < d; ++k) below *= (uint64_t)radix(k);
+    int par = parity_in;
+    for (int k = d - 1; k >= 0; --k) {
+        const uint64_t rk = (uint64_t)radix(k);
+        below /= rk;
+        const int a = (int)((rank / below) % rk);
+        const int g = par ? (int)rk - 1 - a : a;
+        par ^= g & 1;
+        f(k, g);
+    }
+    return par;
 }
 
 // C(a, b) for small non-negative integers, exact in double (a <= 48).

@@ -104,10 +104,10 @@ void pq_ctx::release_all() {
     ws_bytes = 0;
 }
 
-int pq_ctx::occupancy(bool binary, int nc) {
-    int& o = occ[binary ? 1 : 0][nc];
+int pq_ctx::occupancy(int kind, int nc) {
+    int& o = occ[kind][nc];
     if (o == 0) {
-        o = pq::occupancy_glynn(binary, nc);
+        o = pq::occupancy_glynn(kind, nc);
         if (o < 1) o = 1;
     }
     return o;
@@ -119,9 +119,17 @@ namespace pq {
 // sums are rebuilt from the digits, about (digits x NC) multiply-adds).
 static constexpr uint64_t kMinStepsPerWave = 32;
 
+// Sweep kernel kind of a plan (see kernels.h).
+int sweep_kind(const Plan& p) {
+    if (p.binary) return kSweepBin;
+    PowSteps ps;
+    make_pow_steps(p.col_kap, p.nc, ps);
+    return ps.general ? kSweepMixGeneral : kSweepMix;
+}
+
 Geometry sweep_geometry(pq_ctx* ctx, const Plan& p) {
     Geometry g;
-    const int occ = ctx->occupancy(p.binary, p.nc);
+    const int occ = ctx->occupancy(sweep_kind(p), p.nc);
     const uint64_t full = (uint64_t)occ * (uint64_t)ctx->num_cu * kWavesPerBlock;
     uint64_t waves = (p.time_states + kMinStepsPerWave - 1) / kMinStepsPerWave;
     if (waves > full) waves = full;
@@ -131,7 +139,7 @@ Geometry sweep_geometry(pq_ctx* ctx, const Plan& p) {
     return g;
 }
 
-int timed_sweep(pq_ctx* ctx, bool binary, int nc, const GlynnArgs& a, int grid, hipStream_t st) {
+int timed_sweep(pq_ctx* ctx, int kind, int nc, const GlynnArgs& a, int grid, hipStream_t st) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (ctx->profiling) {
         e0 = ctx->take_event();
@@ -140,7 +148,7 @@ int timed_sweep(pq_ctx* ctx, bool binary, int nc, const GlynnArgs& a, int grid, 
         int rc = ctx->check(hipEventRecord(e0, st), "profile: record");
         if (rc) return rc;
     }
-    int rc = ctx->check(launch_glynn(binary, nc, a, grid, st), "sweep");
+    int rc = ctx->check(launch_glynn(kind, nc, a, grid, st), "sweep");
     if (rc) return rc;
     if (ctx->profiling) {
         rc = ctx->check(hipEventRecord(e1, st), "profile: record");
@@ -197,6 +205,7 @@ int run_single(pq_ctx* ctx, const Plan& p, const cplx* U, int64_t ldu, cplx* per
     for (int k = 0; k < p.n_lane; ++k) ga.lane_radix[k] = p.lane_radix[k];
     for (int k = 0; k < p.n_time; ++k) ga.time_radix[k] = p.time_radix[k];
     for (int j = 0; j < nc; ++j) ga.kap[j] = p.col_kap[j];
+    make_pow_steps(ga.kap, nc, ga.pw);
 
     if (!p.binary) {
         TableArgs ta;
@@ -210,7 +219,7 @@ int run_single(pq_ctx* ctx, const Plan& p, const cplx* U, int64_t ldu, cplx* per
         rc = ctx->check(launch_table(ta, st), "table");
         if (rc) return rc;
     }
-    rc = timed_sweep(ctx, p.binary, nc, ga, geo.grid, st);
+    rc = timed_sweep(ctx, sweep_kind(p), nc, ga, geo.grid, st);
     if (rc) return rc;
 
     FinalArgs fa;

@@ -30,7 +30,7 @@ struct pq_ctx {
     size_t stage_bytes = 0;
     hipEvent_t upload_done = nullptr;
     // resident workgroups per CU per (binary, nc); 0 = not yet queried
-    int occ[2][pq::kMaxDim + 1] = {};
+    int occ[3][pq::kMaxDim + 1] = {};
 
     // sweep timing (pq_profile_enable / pq_profile_read)
     bool profiling = false;
@@ -50,7 +50,7 @@ struct pq_ctx {
     // stream-ordered copy of `bytes` from the staging buffer to device memory
     int upload(void* dst, const void* stage_src, size_t bytes, hipStream_t st);
     void release_all();
-    int occupancy(bool binary, int nc);
+    int occupancy(int kind, int nc);
 };
 
 void pq_release_batch_cache(pq_ctx* ctx);
@@ -90,7 +90,7 @@ struct Geometry {
 Geometry sweep_geometry(pq_ctx* ctx, const Plan& p);
 
 // Launch a sweep, bracketed by timing events when profiling is on.
-int timed_sweep(pq_ctx* ctx, bool binary, int nc, const GlynnArgs& a, int grid, hipStream_t st);
+int timed_sweep(pq_ctx* ctx, int kind, int nc, const GlynnArgs& a, int grid, hipStream_t st);
 
 // Full single-permanent sequence: prep, (table), sweep, final.
 int run_single(pq_ctx* ctx, const Plan& p, const cplx* U, int64_t ldu, cplx* perm, cplx* amp,

@@ -33,6 +33,50 @@ __device__ __forceinline__ cplx product_then_add(cplx (&c)[NC], const cplx* __re
     return p;
 }
 
+// Keeps a uniform branch whose body is only arithmetic from being turned into
+// unconditional arithmetic plus selects (emits no instruction).  Not volatile
+// and without memory operands, so it is no memory access and loads after it
+// can still come through the scalar cache.
+__device__ __forceinline__ void keep_branch(cplx& v) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    asm("" : "+v"(v.re), "+v"(v.im));
+#endif
+}
+
+// prod_j c_j^{kap_j} for powers in ascending order (padded columns, whose
+// sums are 1, carry the largest power).  With S_g the product of every column
+// from group g (equal powers) upward and d_g the rise of power into group g,
+//   prod_j c_j^{kap_j} = prod_g S_g^{d_g},
+// so one running suffix product and one multiply per unit of rise replace the
+// per-column repeated multiplies.  The rises come as uniform bit masks.
+template <int NC>
+__device__ __forceinline__ cplx product_grouped(const cplx (&c)[NC], const PowSteps& ps) {
+    cplx S = c[NC - 1];
+    cplx R{1.0, 0.0};
+#pragma unroll
+    for (int j = NC - 1; j >= 1; --j) {
+        if ((ps.step[0] >> j) & 1ull) {
+            R = cmul(R, S);
+            if ((ps.step[1] >> j) & 1ull) {
+                R = cmul(R, S);
+                if ((ps.step[2] >> j) & 1ull) R = cmul(R, S);
+            }
+            keep_branch(R);
+        }
+        S = cmul(S, c[j - 1]);
+    }
+    R = cmul(R, S);
+    if (ps.low > 1) {
+        R = cmul(R, S);
+        if (ps.low > 2) {
+            R = cmul(R, S);
+            if (ps.low > 3) R = cmul(R, S);
+        }
+        keep_branch(R);
+    }
+    return R;
+}
+
 // prod_j c_j^{kap_j}; kap_j >= 1 are wavefront-uniform (kernel arguments).
 template <int NC, class KapT>
 __device__ __forceinline__ cplx product_powers(const cplx (&c)[NC], const KapT* kap) {
