@@ -73,6 +73,8 @@ def main() -> int:
     ap.add_argument("--cpu-sample-n", type=int, default=28)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the repeated-pattern and sampling-replay batches")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="copy a buffer of this many MiB once (calibrates traffic counters)")
     args = ap.parse_args()
@@ -199,6 +201,59 @@ def main() -> int:
                                 "ratio": (msb / nb) / (msf / nf)})
         print(f"# reverse/forward sweeps: {grad_kernel}", file=sys.stderr, flush=True)
 
+    # batched workloads through pq_perm_many (sweep kernels timed with HIP
+    # events, wall time around the call with the job list marshalled once):
+    # 256 patterns of 40 photons in 20 modes (at most 4 per mode), and the
+    # replay of 1000 sampling runs of 20 photons in 400 modes (19 growing
+    # extend-row jobs per run)
+    batched = None
+    if not args.no_batched:
+        batched = {}
+        U20 = torch.from_numpy(workloads.haar(20, 0)).to(dev)
+        pats = workloads.repeated_patterns(count=256, seed=1)
+        ps = pq.PatternSet([p_[0] for p_ in pats], [p_[1] for p_ in pats], 20)
+        rterms = sum(pq.plan_describe(list(S_), list(T_))["terms"] for S_, T_ in pats)
+        eng.perm_patterns(U20, ps)
+        torch.cuda.synchronize()
+        eng.profile(True)
+        eng.profile_read()
+        tw = time.perf_counter()
+        for _ in range(3):
+            eng.perm_patterns(U20, ps)
+        torch.cuda.synchronize()
+        tw = (time.perf_counter() - tw) / 3
+        nl, ms = eng.profile_read()
+        eng.profile(False)
+        batched["repeated_40_photons"] = {
+            "patterns": 256, "gray_terms": rterms, "sweep_ms": ms / 3, "wall_ms": tw * 1e3,
+            "terms_per_s": rterms / (ms / 3 * 1e-3)}
+        U400 = torch.from_numpy(workloads.haar(400, 0)).to(dev)
+        cols, rows = workloads.sampling_jobs(samples=1000, seed=0)
+        jl = []
+        for s_ in range(1000):
+            for k in range(2, 21):
+                rr = {}
+                for x in rows[s_, :k - 1]:
+                    rr[int(x)] = rr.get(int(x), 0) + 1
+                jl.append({"op": pq.PQ_OP_EXTEND_ROW, "rows": sorted(rr.items()),
+                           "cols": [(int(x), 1) for x in sorted(cols[s_, :k])], "out": len(jl) * 400})
+        js = pq.JobSet(jl, 400)
+        eng.perm_many(U400, js, with_amp=False)
+        torch.cuda.synchronize()
+        eng.profile(True)
+        eng.profile_read()
+        tw = time.perf_counter()
+        for _ in range(3):
+            eng.perm_many(U400, js, with_amp=False)
+        torch.cuda.synchronize()
+        tw = (time.perf_counter() - tw) / 3
+        nl, ms = eng.profile_read()
+        eng.profile(False)
+        batched["sampling_replay"] = {
+            "samples": 1000, "jobs": len(jl), "sweep_ms": ms / 3, "wall_ms": tw * 1e3,
+            "samples_per_s": 1000 / tw}
+        print(f"# batched: {batched}", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -250,6 +305,7 @@ def main() -> int:
         "cpu_baseline": cpu,
         "grad_forward": grad_ratio,
         "grad_kernel": grad_kernel,
+        "batched": batched,
     }
     print(json.dumps(line), flush=True)
     eng.close()

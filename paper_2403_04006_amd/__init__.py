@@ -8,6 +8,8 @@ torch stream.
 from __future__ import annotations
 
 import ctypes
+
+import numpy as np
 from typing import Sequence
 
 import torch
@@ -43,6 +45,16 @@ def _as_matrix(U: torch.Tensor) -> tuple:
         U = U.contiguous()
     return U, U.stride(0)
 
+
+
+# numpy layout of struct pq_job (include/pq.h): three int32, four pointers at
+# 8-byte alignment, one int64
+_JOB_DTYPE = np.dtype({
+    "names": ["op", "nr", "nc", "row_idx", "row_mult", "col_idx", "col_mult", "out_offset"],
+    "formats": ["<i4", "<i4", "<i4", "<u8", "<u8", "<u8", "<u8", "<i8"],
+    "offsets": [0, 4, 8, 16, 24, 32, 40, 48],
+    "itemsize": 56,
+})
 
 class Engine:
     """One libpq context on one GPU (not thread-safe; one stream at a time)."""
@@ -100,27 +112,57 @@ class Engine:
     # ------------------------------------------------- batched job lists
     @staticmethod
     def _job_array(jobs: Sequence[dict], m: int):
-        keep = []
-        arr = (pq_job * max(1, len(jobs)))()
+        """pq_job array for `jobs` (argument marshalling): the index and
+        multiplicity lists of every job live in one int32 buffer and the
+        structs are filled column-wise; returns (pointer, keep-alive, n_out)."""
+        n = len(jobs)
+        ops = np.empty(max(1, n), np.int32)
+        nrs = np.zeros(max(1, n), np.int32)
+        ncs = np.zeros(max(1, n), np.int32)
+        outs = np.zeros(max(1, n), np.int64)
+        flat: list = []
         total = 0
         for k, j in enumerate(jobs):
             op = int(j.get("op", PQ_OP_PERM))
-            rows = list(j["rows"])
-            cols = list(j["cols"])
-            ri = _lib.i32_array([r for r, _ in rows])
-            rm = _lib.i32_array([c for _, c in rows])
-            ci = _lib.i32_array([r for r, _ in cols])
-            cm = _lib.i32_array([c for _, c in cols])
-            keep += [ri, rm, ci, cm]
+            rows = j["rows"]
+            cols = j["cols"]
+            ops[k] = op
+            nrs[k] = len(rows)
+            ncs[k] = len(cols)
+            flat.extend(int(r) for r, _ in rows)
+            flat.extend(int(c) for _, c in rows)
+            flat.extend(int(r) for r, _ in cols)
+            flat.extend(int(c) for _, c in cols)
             off = int(j.get("out", total))
-            arr[k] = pq_job(op, len(rows), len(cols), ri, rm, ci, cm, off)
+            outs[k] = off
             total = max(total, off + (m if op == PQ_OP_EXTEND_ROW else 1))
-        return arr, keep, total
+        buf = np.asarray(flat if flat else [0], dtype=np.int32)
+        arr = np.zeros(max(1, n), dtype=_JOB_DTYPE)
+        if n:
+            start = np.zeros(n, np.int64)
+            start[1:] = np.cumsum(2 * (nrs[:n].astype(np.int64) + ncs[:n]))[:-1]
+            base = buf.ctypes.data
+            arr["op"][:n] = ops[:n]
+            arr["nr"][:n] = nrs[:n]
+            arr["nc"][:n] = ncs[:n]
+            arr["row_idx"][:n] = base + 4 * start
+            arr["row_mult"][:n] = base + 4 * (start + nrs[:n])
+            arr["col_idx"][:n] = base + 4 * (start + 2 * nrs[:n])
+            arr["col_mult"][:n] = base + 4 * (start + 2 * nrs[:n] + ncs[:n])
+            arr["out_offset"][:n] = outs[:n]
+        ptr = ctypes.cast(arr.ctypes.data, ctypes.POINTER(pq_job))
+        return ptr, (buf, arr), total
 
     def _run_jobs(self, fn, U, jobs, n_out, with_amp):
         U, ldu = _as_matrix(U)
         m = U.shape[0]
-        arr, keep, total = self._job_array(jobs, m)
+        if isinstance(jobs, JobSet):
+            if jobs.m != m:
+                raise ValueError("job set built for another mode count")
+            arr, keep, total = jobs.jobs, None, jobs.n_out
+            jobs = range(jobs.njobs)
+        else:
+            arr, keep, total = self._job_array(jobs, m)
         n_out = total if n_out is None else n_out
         perm = torch.zeros(max(1, n_out), dtype=torch.complex128, device=U.device)
         amp = torch.zeros(max(1, n_out), dtype=torch.complex128, device=U.device) if with_amp else None
@@ -187,6 +229,16 @@ class Engine:
                                     dU.data_ptr(), m, _stream_handle(U.device))
         _check(st, self._ctx)
         return dU, (perm[:batch] if perm is not None else None)
+
+
+class JobSet:
+    """A job list (dicts as for Engine.perm_many) marshalled once for repeated
+    pq_perm_many / pq_perm_batched calls on interferometers with m modes."""
+
+    def __init__(self, jobs: Sequence[dict], m: int):
+        self.m = int(m)
+        self.njobs = len(jobs)
+        self.jobs, self._keep, self.n_out = Engine._job_array(jobs, self.m)
 
 
 class PatternSet:

@@ -151,3 +151,24 @@ def test_plan_repeated_workload_sizes():
         info = pq.plan_describe(list(S), list(T))
         assert info["status"] == 0 and info["n"] == 40
         assert info["terms"] == min(brute_terms(S[S > 0]), brute_terms(T[T > 0]))
+
+
+def test_job_marshalling_matches_struct_layout():
+    # the binding fills struct pq_job column-wise from numpy; read it back
+    # through the ctypes definition of the struct
+    jobs = [{"op": 0, "rows": [(1, 2), (3, 1)], "cols": [(0, 1), (2, 2)]},
+            {"op": 1, "rows": [(4, 1)], "cols": [(1, 1), (5, 1)], "out": 10},
+            {"op": 0, "rows": [], "cols": []}]
+    ptr, keep, total = pq.Engine._job_array(jobs, 8)
+    assert ctypes.sizeof(_lib.pq_job) == 56
+    want = [(0, [1, 3], [2, 1], [0, 2], [1, 2], 0), (1, [4], [1], [1, 5], [1, 1], 10), (0, [], [], [], [], 18)]
+    for k, (op, ri, rm, ci, cm, out) in enumerate(want):
+        j = ptr[k]
+        assert j.op == op and j.nr == len(ri) and j.nc == len(ci) and j.out_offset == out
+        assert [j.row_idx[i] for i in range(j.nr)] == ri
+        assert [j.row_mult[i] for i in range(j.nr)] == rm
+        assert [j.col_idx[i] for i in range(j.nc)] == ci
+        assert [j.col_mult[i] for i in range(j.nc)] == cm
+    assert total == 19
+    js = pq.JobSet(jobs, 8)
+    assert js.njobs == 3 and js.n_out == 19
