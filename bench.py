@@ -252,6 +252,24 @@ def main() -> int:
         batched["sampling_replay"] = {
             "samples": 1000, "jobs": len(jl), "sweep_ms": ms / 3, "wall_ms": tw * 1e3,
             "samples_per_s": 1000 / tw}
+        # every output amplitude of 10 photons in 16 modes (3268760 outputs)
+        U16 = torch.from_numpy(workloads.haar(16, 1)).to(dev)
+        S16 = [1] * 10 + [0] * 6
+        eng.perm_all_outputs(U16, S16)
+        torch.cuda.synchronize()
+        eng.profile(True)
+        eng.profile_read()
+        tw = time.perf_counter()
+        for _ in range(3):
+            _, amp16 = eng.perm_all_outputs(U16, S16)
+        torch.cuda.synchronize()
+        tw = (time.perf_counter() - tw) / 3
+        nl, ms = eng.profile_read()
+        eng.profile(False)
+        batched["all_outputs_10_in_16"] = {
+            "outputs": pq.fock_count(16, 10), "sweep_ms": ms / 3, "wall_ms": tw * 1e3,
+            "outputs_per_s": pq.fock_count(16, 10) / tw,
+            "completeness_error": abs(float(torch.sum(torch.abs(amp16) ** 2)) - 1.0)}
         print(f"# batched: {batched}", file=sys.stderr, flush=True)
 
     cpu = None

@@ -170,6 +170,38 @@ int pq_perm_grad(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m,
                  pq_c128* dU, int64_t lddu, void* stream);
 
 /*
+ * Passive-circuit simulation: every output amplitude of one input pattern
+ * (the output probabilities of a linear interferometer, Eq. BS_prob / per_def
+ * for every T; completeness sum_T |amp|^2 = 1 for unitary U).
+ *
+ * pq_perm_all_outputs -- perm(U_{T,S}) and amp = perm / sqrt(prod S! prod T!)
+ * for every output pattern T with sum T = sum S = n on m modes, in ascending
+ * lexicographic order of (T_0, ..., T_{m-1}): T = (0, ..., 0, n) first,
+ * (n, 0, ..., 0) last; pq_fock_count(m, n) = C(n+m-1, n) outputs.  One
+ * Gray-code sum over the input side serves every T: a term's m column sums
+ * c_i = sum_j delta_j U[i][j] give w prod_i c_i^{t_i} for all T at once.
+ *   U      device, m x m row-major, leading dimension ldu >= m.
+ *   S      host int32[m] input occupations, sum n <= 48.
+ *   perm   device, pq_fock_count(m, n) complex, written.
+ *   amp    device, same size, may be NULL.
+ * Limits (PQ_ERANGE): m <= 64; at most PQ_ALL_MAX_OUTPUTS outputs; at most
+ * 2^20 Gray terms (prod over occupied input modes of (s_j + 1), halved on the
+ * smallest).  n == 0 writes the single vacuum output perm = amp = 1.
+ */
+#define PQ_ALL_MAX_OUTPUTS (1ll << 31)
+int pq_perm_all_outputs(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m, const int32_t* S,
+                        pq_c128* perm, pq_c128* amp, void* stream);
+
+/* Number of occupation vectors with n photons on m modes, C(n+m-1, n);
+ * -1 for m < 1, n < 0, or a count above 2^62 (host, no GPU work). */
+int64_t pq_fock_count(int32_t m, int32_t n);
+
+/* T[0..m-1] = the occupation vector of rank `rank` in the order of
+ * pq_perm_all_outputs (host).  PQ_EINVAL for a rank outside
+ * [0, pq_fock_count(m, n)) or bad sizes, PQ_ERANGE when the count overflows. */
+int pq_fock_unrank(int32_t m, int32_t n, int64_t rank, int32_t* T);
+
+/*
  * Differentiable circuits (Beamsplitter gate section; differentiable
  * circuits in the simulator overview).
  *

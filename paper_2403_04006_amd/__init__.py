@@ -18,8 +18,8 @@ from . import _lib
 from ._lib import PqError, pq_job, pq_plan_info, PQ_OP_PERM, PQ_OP_EXTEND_ROW, PQ_MAX_N  # noqa: F401
 
 __all__ = [
-    "Engine", "engine", "perm", "plan_describe", "gray_unrank", "PqError", "PatternSet",
-    "PQ_OP_PERM", "PQ_OP_EXTEND_ROW",
+    "Engine", "engine", "perm", "plan_describe", "gray_unrank", "fock_count", "fock_unrank", "PqError",
+    "PatternSet", "JobSet", "PQ_OP_PERM", "PQ_OP_EXTEND_ROW",
 ]
 
 
@@ -197,6 +197,23 @@ class Engine:
         _check(st, self._ctx)
         return dU, (perm[:pats.batch] if perm is not None else None)
 
+    def perm_all_outputs(self, U: torch.Tensor, S: Sequence[int], with_amp: bool = True):
+        """perm(U_{T,S}) (and amplitudes) for every output pattern T with sum T =
+        sum S, in the order of fock_unrank (pq_perm_all_outputs)."""
+        U, ldu = _as_matrix(U)
+        m = U.shape[0]
+        if len(S) != m:
+            raise ValueError("S needs one entry per mode")
+        count = fock_count(m, int(sum(int(v) for v in S)))
+        if count < 0 or count > _lib.PQ_ALL_MAX_OUTPUTS:
+            raise PqError(_lib.PQ_ERANGE, f"more than {_lib.PQ_ALL_MAX_OUTPUTS} output patterns")
+        perm = torch.empty(max(1, count), dtype=torch.complex128, device=U.device)
+        amp = torch.empty_like(perm) if with_amp else None
+        st = self._lib.pq_perm_all_outputs(self._ctx, U.data_ptr(), ldu, m, _lib.i32_array(S), perm.data_ptr(),
+                                           amp.data_ptr() if amp is not None else None, _stream_handle(U.device))
+        _check(st, self._ctx)
+        return perm[:count], (amp[:count] if amp is not None else None)
+
     def perm_many(self, U: torch.Tensor, jobs: Sequence[dict], n_out: int | None = None, with_amp: bool = True):
         """Jobs {op, rows: [(mode, mult)], cols: [(mode, mult)], out} through the
         statically scheduled many-pattern path (pq_perm_many).  PERM jobs write
@@ -291,6 +308,19 @@ def plan_describe(S: Sequence[int], T: Sequence[int]) -> dict:
     m = len(S)
     lib.pq_plan_describe(m, _lib.i32_array(S), _lib.i32_array(T), ctypes.byref(info))
     return {name: getattr(info, name) for name, _ in pq_plan_info._fields_}
+
+
+def fock_count(m: int, n: int) -> int:
+    """Output patterns of n photons on m modes, C(n+m-1, n) (-1 on overflow)."""
+    return int(_lib.load().pq_fock_count(int(m), int(n)))
+
+
+def fock_unrank(m: int, n: int, rank: int) -> list:
+    """Occupation vector of `rank` in the output order of perm_all_outputs
+    (ascending lexicographic in (T_0, ..., T_{m-1}))."""
+    out = (ctypes.c_int32 * max(1, m))()
+    _check(_lib.load().pq_fock_unrank(int(m), int(n), int(rank), out))
+    return [out[i] for i in range(m)]
 
 
 def gray_unrank(radix: Sequence[int], rank: int) -> list:

@@ -18,6 +18,7 @@ PQ_OK, PQ_EINVAL, PQ_ERANGE, PQ_ENOMEM, PQ_EDEVICE, PQ_ECANCELLED = range(6)
 PQ_OP_PERM, PQ_OP_EXTEND_ROW = 0, 1
 PQ_MAX_N = 48
 PQ_GRAD_MAX_DIM = 32
+PQ_ALL_MAX_OUTPUTS = 1 << 31
 
 
 class pq_c128(ctypes.Structure):
@@ -80,6 +81,9 @@ _SIGNATURES = {
     "pq_neg_log_prob": ([_VP, ctypes.c_int32, _VP, _VP, _VP, _VP], ctypes.c_int),
     "pq_neg_log_prob_vjp": ([_VP, ctypes.c_int32, _VP, _VP, _VP, _VP], ctypes.c_int),
     "pq_profile_read": ([_VP, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "pq_perm_all_outputs": ([_VP, _VP, ctypes.c_int64, ctypes.c_int32, _I32P, _VP, _VP, _VP], ctypes.c_int),
+    "pq_fock_count": ([ctypes.c_int32, ctypes.c_int32], ctypes.c_int64),
+    "pq_fock_unrank": ([ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, _I32P], ctypes.c_int),
 }
 
 _lib = None

@@ -1,0 +1,120 @@
+// Kernels of the all-outputs sweep (see all.h).
+#include <hip/hip_runtime.h>
+
+#include "all.h"
+#include "device.h"
+
+namespace pq {
+
+// One thread per (delta term, output mode): c_i(delta) = sum_j delta_j U[i][j];
+// the mode-0 thread of each term also writes its weight.
+__global__ __launch_bounds__(kBlock) void all_sums_kernel(const AllSumsArgs a) {
+    const uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= a.terms * (uint64_t)a.m) return;
+    const uint64_t d = t / (uint64_t)a.m;
+    const int i = (int)(t - d * (uint64_t)a.m);
+    uint64_t rest = d;
+    double re = 0.0, im = 0.0, w = 1.0;
+    for (int j = 0; j < a.k; ++j) {
+        const int rho = a.radix[j];
+        const int dj = (int)(rest % (uint64_t)rho);
+        rest /= (uint64_t)rho;
+        const double delta = (double)(a.in_mult[j] - 2 * dj);
+        const cplx u = a.U[(size_t)i * (size_t)a.ldu + a.in_mode[j]];
+        re = __builtin_fma(delta, u.re, re);
+        im = __builtin_fma(delta, u.im, im);
+        // (-1)^d C(mu', d), mu' = s_f - 1 for the fixed group (j = 0), s_j otherwise
+        w *= digit_weight(j == 0 ? a.in_mult[j] : a.in_mult[j] + 1, dj);
+    }
+    a.csum[d * (uint64_t)a.m + i] = cplx{re, im};
+    if (i == 0) a.w[d] = w;
+}
+
+// One thread per output pattern T (lexicographic rank idx).  The thread's
+// photons are its output modes with repetition, r_0 <= ... <= r_{n-1}; per
+// delta term the product prod_q c_{r_q} takes n - 1 complex multiplies.
+template <int NMAX>
+__global__ __launch_bounds__(kBlock) void all_out_kernel(const AllOutArgs a) {
+    __shared__ cplx sC[kAllTile * kAllMaxModes];
+    __shared__ double sW[kAllTile];
+    __shared__ uint8_t sR[kBlock][NMAX];
+    const int tid = (int)threadIdx.x;
+    const int64_t idx = (int64_t)blockIdx.x * kBlock + tid;
+    const bool act = idx < a.outputs;
+    const int m = a.m, n = a.n;
+
+    // unrank: T_i for i = 0..m-2 by counting the patterns that start with a
+    // smaller T_i; T_{m-1} takes the rest
+    double tfact = 1.0;
+    {
+        uint64_t rank = act ? (uint64_t)idx : 0;
+        int rem = n, q = 0;
+        for (int i = 0; i < m; ++i) {
+            int v = rem;
+            if (i < m - 1) {
+                const uint64_t* cnt = a.count + (size_t)(m - 2 - i) * (size_t)(n + 1);
+                for (v = 0; v < rem; ++v) {
+                    const uint64_t c = cnt[rem - v];    // compositions of rem - v into m - 1 - i parts
+                    if (rank < c) break;
+                    rank -= c;
+                }
+            }
+            for (int e = 1; e <= v; ++e) {
+                tfact *= (double)e;
+                sR[tid][q++] = (uint8_t)i;
+            }
+            rem -= v;
+        }
+    }
+    __syncthreads();
+    int off[NMAX];
+#pragma unroll
+    for (int q = 0; q < NMAX; ++q) off[q] = q < n ? (int)sR[tid][q] : 0;
+
+    cdd acc = to_cdd(cplx{0.0, 0.0});
+    for (uint64_t d0 = 0; d0 < a.terms; d0 += kAllTile) {
+        const int nt = (int)((a.terms - d0) < (uint64_t)kAllTile ? (a.terms - d0) : (uint64_t)kAllTile);
+        __syncthreads();
+        for (int e = tid; e < nt * m; e += kBlock) sC[e] = a.csum[d0 * (uint64_t)m + e];
+        for (int e = tid; e < nt; e += kBlock) sW[e] = a.w[d0 + e];
+        __syncthreads();
+        cplx part{0.0, 0.0};
+        for (int dd = 0; dd < nt; ++dd) {
+            const cplx* cd = sC + dd * m;
+            cplx p = cd[off[0]];
+#pragma unroll
+            for (int q = 1; q < NMAX; ++q)
+                if (q < n) p = cmul(p, cd[off[q]]);
+            cfma_to(part, sW[dd], p);
+        }
+        acc = cdd_add(acc, to_cdd(part));
+    }
+    if (!act) return;
+    const double re = (acc.re.hi + acc.re.lo) * a.scale;
+    const double im = (acc.im.hi + acc.im.lo) * a.scale;
+    a.perm[idx] = cplx{re, im};
+    if (a.amp) {
+        const double nrm = a.norm_s / sqrt(tfact);
+        a.amp[idx] = cplx{re * nrm, im * nrm};
+    }
+}
+
+hipError_t launch_all_sums(const AllSumsArgs& a, hipStream_t s) {
+    const uint64_t threads = a.terms * (uint64_t)a.m;
+    const uint64_t blocks = (threads + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(all_sums_kernel, dim3((unsigned)(blocks > 0 ? blocks : 1)), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_all_out(const AllOutArgs& a, hipStream_t s) {
+    const uint64_t blocks = ((uint64_t)a.outputs + kBlock - 1) / kBlock;
+    const dim3 grid((unsigned)(blocks > 0 ? blocks : 1));
+    if (a.n <= 8) hipLaunchKernelGGL(all_out_kernel<8>, grid, dim3(kBlock), 0, s, a);
+    else if (a.n <= 16) hipLaunchKernelGGL(all_out_kernel<16>, grid, dim3(kBlock), 0, s, a);
+    else if (a.n <= 32) hipLaunchKernelGGL(all_out_kernel<32>, grid, dim3(kBlock), 0, s, a);
+    else if (a.n <= kAllMaxPhotons) hipLaunchKernelGGL(all_out_kernel<kAllMaxPhotons>, grid, dim3(kBlock), 0, s, a);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+}  // namespace pq

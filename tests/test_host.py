@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 import paper_2403_04006_amd as pq
+import workloads
 from paper_2403_04006_amd import _lib
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -172,3 +173,31 @@ def test_job_marshalling_matches_struct_layout():
     assert total == 19
     js = pq.JobSet(jobs, 8)
     assert js.njobs == 3 and js.n_out == 19
+
+
+@pytest.mark.parametrize("m,n", [(1, 0), (1, 5), (3, 0), (4, 3), (5, 4), (6, 6)])
+def test_fock_order_matches_enumeration(m, n):
+    # output order of pq_perm_all_outputs: ascending lexicographic in
+    # (T_0, ..., T_{m-1}), the order of the plain enumeration in workloads
+    outs = workloads.fock_outputs(m, n)
+    assert pq.fock_count(m, n) == math.comb(n + m - 1, n) == len(outs)
+    for r, T in enumerate(outs):
+        assert pq.fock_unrank(m, n, r) == [int(v) for v in T]
+
+
+def test_fock_count_and_unrank_errors():
+    assert pq.fock_count(0, 3) == -1
+    assert pq.fock_count(3, -1) == -1
+    assert pq.fock_count(200, 100) == -1          # above 2^62
+    with pytest.raises(pq.PqError):
+        pq.fock_unrank(4, 3, pq.fock_count(4, 3))
+    with pytest.raises(pq.PqError):
+        pq.fock_unrank(4, 3, -1)
+
+
+def test_binding_constants_match_header():
+    text = open(os.path.join(ROOT, "include", "pq.h")).read()
+    defs = {k: v.split("/*")[0].strip() for k, v in re.findall(r"#define\s+(PQ_\w+)\s+(.+)", text)}
+    assert int(defs["PQ_MAX_N"]) == _lib.PQ_MAX_N
+    assert int(defs["PQ_GRAD_MAX_DIM"]) == _lib.PQ_GRAD_MAX_DIM
+    assert defs["PQ_ALL_MAX_OUTPUTS"] == "(1ll << 31)" and _lib.PQ_ALL_MAX_OUTPUTS == 1 << 31
