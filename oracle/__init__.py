@@ -20,6 +20,9 @@ What it computes (each function cites the passage it follows):
                              used by chain-rule boson sampling (Clifford &
                              Clifford's algorithm A, named in the Boson
                              Sampling benchmark section).
+* ``chain_rule_sample(U, order, uniforms)`` -- one chain-rule draw sequence
+                             with given input order and uniforms (CDF
+                             inversion over the extend-row weights).
 * ``beamsplitter(theta, phi)``, ``mesh_unitary(angles)`` -- the beamsplitter
                              matrix of the "Beamsplitter gate" section and a
                              rectangular mesh of such cells.
@@ -311,6 +314,27 @@ def chain_rule_distribution(U, inputs_order, rows_so_far) -> np.ndarray:
     k = len(rows_so_far) + 1
     out = extend_row(U, rows_so_far, list(inputs_order[:k]))
     return np.abs(out) ** 2
+
+
+def chain_rule_sample(U, order, uniforms):
+    """One chain-rule sample (Clifford & Clifford's algorithm A, named in the
+    Boson Sampling benchmark section): with the input modes in the given order,
+    draw r_k for k = 1..n by inverting the cumulative weights
+    |perm(U_{rows + l, order[:k]})|^2 over l (summed in mode order) at
+    u_k * total: r_k is the first l whose cumulative weight exceeds it.
+    Returns (rows, margins): margins[k] is the distance of u_k * total from the
+    nearest cumulative weight, relative to the total (decisions closer than
+    rounding to a boundary may legitimately differ between implementations)."""
+    rows, margins = [], []
+    for k in range(1, len(order) + 1):
+        w = chain_rule_distribution(U, order, rows)
+        cdf = np.cumsum(w)
+        target = float(uniforms[k - 1]) * cdf[-1]
+        r = int(np.searchsorted(cdf, target, side="right"))
+        r = min(r, len(w) - 1)
+        rows.append(r)
+        margins.append(float(np.min(np.abs(cdf - target))) / cdf[-1])
+    return rows, margins
 
 
 def beamsplitter_derivatives(theta: float, phi: float) -> tuple:

@@ -356,3 +356,43 @@ def test_golden_repeated_values_present():
     assert U.shape == (20, 20) and np.max(np.abs(U @ U.conj().T - np.eye(20))) < 1e-13
     for c in cases:
         assert c["S"].sum() == 40 and c["T"].sum() == 40 and c["S"].max() <= 4 and c["T"].max() <= 4
+
+
+def test_chain_rule_sampler_reproduces_born_rule():
+    # averaged over every order of the input modes, the probability that the
+    # chain rule draws the multiset T (summed over draw sequences) is the
+    # Born-rule probability |perm(U_{T,S})|^2 / (prod S! prod T!)
+    import itertools as it
+    m, inputs = 4, [0, 2, 3]
+    U = workloads.haar(m, 11)
+    S = np.zeros(m, np.int32)
+    S[inputs] = 1
+    n = len(inputs)
+    prob = {}
+    orders = list(it.permutations(inputs))
+    for order in orders:
+        def walk(rows, p):
+            k = len(rows) + 1
+            if k > n:
+                T = tuple(np.bincount(rows, minlength=m))
+                prob[T] = prob.get(T, 0.0) + p / len(orders)
+                return
+            w = oracle.chain_rule_distribution(U, order, rows)
+            w = w / w.sum()
+            for l in range(m):
+                if w[l] > 0:
+                    walk(rows + [l], p * w[l])
+        walk([], 1.0)
+    for T in workloads.fock_outputs(m, n):
+        want = oracle.probability(U, S, T)
+        assert abs(prob.get(tuple(int(v) for v in T), 0.0) - want) < 1e-12, T
+    assert abs(sum(prob.values()) - 1.0) < 1e-12
+
+
+def test_chain_rule_sample_inverts_the_cdf():
+    U = workloads.haar(5, 2)
+    order = [3, 0, 1]
+    rows, margins = oracle.chain_rule_sample(U, order, [0.0, 0.5, 0.999999])
+    w0 = oracle.chain_rule_distribution(U, order, [])
+    assert rows[0] == int(np.argmax(w0 > 0))          # u = 0 picks the first mode with weight
+    assert len(rows) == 3 and all(0 <= r < 5 for r in rows) and len(margins) == 3
