@@ -252,6 +252,25 @@ def main() -> int:
         batched["sampling_replay"] = {
             "samples": 1000, "jobs": len(jl), "sweep_ms": ms / 3, "wall_ms": tw * 1e3,
             "samples_per_s": 1000 / tw}
+        # the same sampling runs drawn entirely on the device (the chain rule
+        # with uniforms and input orders as inputs)
+        rng_s = np.random.default_rng(1)
+        order_s = torch.from_numpy(np.stack([rng_s.permutation(20) for _ in range(1000)]).astype(np.int32)).to(dev)
+        u_s = torch.from_numpy(rng_s.random((1000, 20))).to(dev)
+        eng.sample_chain(U400, order_s, u_s)
+        torch.cuda.synchronize()
+        eng.profile(True)
+        eng.profile_read()
+        tw = time.perf_counter()
+        for _ in range(3):
+            eng.sample_chain(U400, order_s, u_s)
+        torch.cuda.synchronize()
+        tw = (time.perf_counter() - tw) / 3
+        nl, ms = eng.profile_read()
+        eng.profile(False)
+        batched["sampling_device_chain"] = {
+            "samples": 1000, "photons": 20, "modes": 400, "kernel_ms": ms / 3, "wall_ms": tw * 1e3,
+            "samples_per_s": 1000 / tw}
         # every output amplitude of 10 photons in 16 modes (3268760 outputs)
         U16 = torch.from_numpy(workloads.haar(16, 1)).to(dev)
         S16 = [1] * 10 + [0] * 6

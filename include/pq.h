@@ -192,6 +192,27 @@ int pq_perm_grad(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m,
 int pq_perm_all_outputs(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m, const int32_t* S,
                         pq_c128* perm, pq_c128* amp, void* stream);
 
+/*
+ * pq_sample_chain -- chain-rule boson sampling (Clifford & Clifford's
+ * algorithm A, named in the Boson Sampling benchmark section), every sample's
+ * whole draw sequence in one launch.  For sample s with input modes
+ * order[s][0..n-1] (a random order of the occupied input modes, one photon
+ * each) and uniforms u = uniforms[s][0..n-1] in [0, 1), step k = 1..n draws
+ *     r_k = the first mode l whose cumulative weight (modes in ascending
+ *           order) exceeds u_k times the total, with weights
+ *           |perm(U_{r_1..r_{k-1}, l ; order[0..k-1]})|^2,
+ * and writes out[s][k-1] = r_k.  Averaged over uniformly random orders and
+ * uniforms, the multiset {r_k} follows the Born rule of Eq. BS_prob.
+ *   U         device, m x m, leading dimension ldu >= m.
+ *   order     device int32[samples * n], input modes (distinct, < m).
+ *   uniforms  device double[samples * n].
+ *   out       device int32[samples * n], written.
+ * Limits (PQ_ERANGE): m <= 1024, n <= 24 and n <= m.  The random numbers are
+ * inputs, so a run replays exactly from its uniforms and orders.
+ */
+int pq_sample_chain(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m, int32_t n, int32_t samples,
+                    const int32_t* order, const double* uniforms, int32_t* out, void* stream);
+
 /* Number of occupation vectors with n photons on m modes, C(n+m-1, n);
  * -1 for m < 1, n < 0, or a count above 2^62 (host, no GPU work). */
 int64_t pq_fock_count(int32_t m, int32_t n);

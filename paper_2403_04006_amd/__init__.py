@@ -214,6 +214,23 @@ class Engine:
         _check(st, self._ctx)
         return perm[:count], (amp[:count] if amp is not None else None)
 
+    def sample_chain(self, U: torch.Tensor, order: torch.Tensor, uniforms: torch.Tensor) -> torch.Tensor:
+        """Chain-rule boson samples (pq_sample_chain): order (samples, n) int32
+        input modes and uniforms (samples, n) float64 on U's device; returns the
+        drawn output modes (samples, n) int32 in draw order."""
+        U, ldu = _as_matrix(U)
+        m = U.shape[0]
+        order = order.to(device=U.device, dtype=torch.int32).contiguous()
+        uniforms = uniforms.to(device=U.device, dtype=torch.float64).contiguous()
+        if order.dim() != 2 or uniforms.shape != order.shape:
+            raise ValueError("order and uniforms need the same (samples, n) shape")
+        samples, n = order.shape
+        out = torch.empty((samples, n), dtype=torch.int32, device=U.device)
+        st = self._lib.pq_sample_chain(self._ctx, U.data_ptr(), ldu, m, n, samples, order.data_ptr(),
+                                       uniforms.data_ptr(), out.data_ptr(), _stream_handle(U.device))
+        _check(st, self._ctx)
+        return out
+
     def perm_many(self, U: torch.Tensor, jobs: Sequence[dict], n_out: int | None = None, with_amp: bool = True):
         """Jobs {op, rows: [(mode, mult)], cols: [(mode, mult)], out} through the
         statically scheduled many-pattern path (pq_perm_many).  PERM jobs write
