@@ -213,6 +213,24 @@ int pq_perm_all_outputs(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m, c
 int pq_sample_chain(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m, int32_t n, int32_t samples,
                     const int32_t* order, const double* uniforms, int32_t* out, void* stream);
 
+/*
+ * pq_loss_dilation -- lossy interferometers (the pure-loss channel of the
+ * Boson Sampling section: mode i meets an inaccessible mode at a beamsplitter
+ * with transmissivity eta_i, after the interferometer U; the beamsplitter is
+ * the paper's [[t, -r*], [r, t]] on (i, m + i) with t = sqrt(eta_i),
+ * r = sqrt(1 - eta_i)).  Writes the 2m x 2m unitary
+ *     Ud = [[D U, -E], [E U, D]],  D = diag(sqrt(eta)), E = diag(sqrt(1 - eta)),
+ * whose top-left block is the lossy transfer matrix A = D U (A A^dagger <= I).
+ * Photons entering modes 0..m-1 and leaving through modes m..2m-1 are the
+ * lost ones, so pq_sample_chain and pq_perm_all_outputs on Ud (inputs in
+ * modes 0..m-1) sample and evaluate the lossy output distribution.
+ *   U     device, m x m, leading dimension ldu >= m.
+ *   eta   host double[m] in [0, 1] (PQ_EINVAL otherwise).
+ *   Ud    device, 2m x 2m, leading dimension ldd >= 2m, written.
+ */
+int pq_loss_dilation(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m, const double* eta, pq_c128* Ud,
+                     int64_t ldd, void* stream);
+
 /* Number of occupation vectors with n photons on m modes, C(n+m-1, n);
  * -1 for m < 1, n < 0, or a count above 2^62 (host, no GPU work). */
 int64_t pq_fock_count(int32_t m, int32_t n);

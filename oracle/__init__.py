@@ -23,6 +23,11 @@ What it computes (each function cites the passage it follows):
 * ``chain_rule_sample(U, order, uniforms)`` -- one chain-rule draw sequence
                              with given input order and uniforms (CDF
                              inversion over the extend-row weights).
+* ``loss_dilation(U, eta)``, ``lossy_probability(U, eta, S, T)`` -- per-mode
+                             pure-loss channels after U as beamsplitters to
+                             environment modes (Boson Sampling section), and
+                             the detection probability of T marginalised over
+                             the environment.
 * ``beamsplitter(theta, phi)``, ``mesh_unitary(angles)`` -- the beamsplitter
                              matrix of the "Beamsplitter gate" section and a
                              rectangular mesh of such cells.
@@ -335,6 +340,51 @@ def chain_rule_sample(U, order, uniforms):
         rows.append(r)
         margins.append(float(np.min(np.abs(cdf - target))) / cdf[-1])
     return rows, margins
+
+
+def loss_dilation(U, eta) -> np.ndarray:
+    """2m-mode unitary of U followed, on every output mode i, by a beamsplitter
+    with transmissivity eta_i to an environment mode m + i (Boson Sampling
+    section: t = sqrt(eta), r = sqrt(1 - eta)).  Built as the product of the
+    beamsplitter layer and U acting on the system modes:
+        [[t, -r], [r, t]]  on (i, m + i),   then  U (+) I  before it."""
+    U = np.asarray(U, dtype=np.complex128)
+    m = U.shape[0]
+    big = np.eye(2 * m, dtype=np.complex128)
+    big[:m, :m] = U
+    layer = np.eye(2 * m, dtype=np.complex128)
+    for i in range(m):
+        t, r = math.sqrt(eta[i]), math.sqrt(1.0 - eta[i])
+        layer[i, i], layer[i, m + i] = t, -r
+        layer[m + i, i], layer[m + i, m + i] = r, t
+    return layer @ big
+
+
+def lossy_probability(U, eta, S, T) -> float:
+    """Probability of detecting T (sum T <= sum S) on the system modes after
+    U and the losses: the sum over environment patterns E of the ideal
+    probability of (T, E) on the dilation, inputs in the system modes."""
+    m = len(S)
+    n = int(np.sum(S))
+    k = n - int(np.sum(T))
+    if k < 0:
+        return 0.0
+    Ud = loss_dilation(U, eta)
+    S2 = np.concatenate([np.asarray(S, np.int32), np.zeros(m, np.int32)])
+    total = 0.0
+    for E in _compositions(m, k):
+        T2 = np.concatenate([np.asarray(T, np.int32), np.asarray(E, np.int32)])
+        total += probability(Ud, S2, T2)
+    return total
+
+
+def _compositions(m: int, k: int):
+    if m == 1:
+        yield [k]
+        return
+    for v in range(k + 1):
+        for rest in _compositions(m - 1, k - v):
+            yield [v] + rest
 
 
 def beamsplitter_derivatives(theta: float, phi: float) -> tuple:

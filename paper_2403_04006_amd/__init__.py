@@ -231,6 +231,28 @@ class Engine:
         _check(st, self._ctx)
         return out
 
+    def loss_dilation(self, U: torch.Tensor, eta: Sequence[float]) -> torch.Tensor:
+        """2m x 2m unitary dilation of U followed by per-mode losses with
+        transmissivities eta (pq_loss_dilation)."""
+        U, ldu = _as_matrix(U)
+        m = U.shape[0]
+        if len(eta) != m:
+            raise ValueError("eta needs one entry per mode")
+        Ud = torch.empty((2 * m, 2 * m), dtype=torch.complex128, device=U.device)
+        arr = (ctypes.c_double * m)(*[float(x) for x in eta])
+        st = self._lib.pq_loss_dilation(self._ctx, U.data_ptr(), ldu, m, arr, Ud.data_ptr(), 2 * m,
+                                        _stream_handle(U.device))
+        _check(st, self._ctx)
+        return Ud
+
+    def sample_chain_lossy(self, U: torch.Tensor, eta: Sequence[float], order: torch.Tensor,
+                           uniforms: torch.Tensor) -> torch.Tensor:
+        """Chain-rule samples through U followed by per-mode losses: the draws
+        on the loss dilation, with lost photons (modes >= m) reported as -1."""
+        m = U.shape[0]
+        out = self.sample_chain(self.loss_dilation(U, eta), order, uniforms)
+        return torch.where(out >= m, torch.full_like(out, -1), out)
+
     def perm_many(self, U: torch.Tensor, jobs: Sequence[dict], n_out: int | None = None, with_amp: bool = True):
         """Jobs {op, rows: [(mode, mult)], cols: [(mode, mult)], out} through the
         statically scheduled many-pattern path (pq_perm_many).  PERM jobs write

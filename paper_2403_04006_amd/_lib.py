@@ -83,6 +83,8 @@ _SIGNATURES = {
     "pq_profile_read": ([_VP, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "pq_perm_all_outputs": ([_VP, _VP, ctypes.c_int64, ctypes.c_int32, _I32P, _VP, _VP, _VP], ctypes.c_int),
     "pq_fock_count": ([ctypes.c_int32, ctypes.c_int32], ctypes.c_int64),
+    "pq_loss_dilation": ([_VP, _VP, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), _VP,
+                          ctypes.c_int64, _VP], ctypes.c_int),
     "pq_sample_chain": ([_VP, _VP, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _VP, _VP, _VP,
                          _VP], ctypes.c_int),
     "pq_fock_unrank": ([ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, _I32P], ctypes.c_int),

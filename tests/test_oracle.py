@@ -396,3 +396,49 @@ def test_chain_rule_sample_inverts_the_cdf():
     w0 = oracle.chain_rule_distribution(U, order, [])
     assert rows[0] == int(np.argmax(w0 > 0))          # u = 0 picks the first mode with weight
     assert len(rows) == 3 and all(0 <= r < 5 for r in rows) and len(margins) == 3
+
+
+# ------------------------------------------------------------------ losses
+def _detected(m, n):
+    for k in range(n + 1):
+        for T in workloads.fock_outputs(m, k):
+            yield T
+
+
+def test_lossy_distribution_is_normalised_and_binomial_for_uniform_loss():
+    # uniform transmissivity: every photon survives independently, so the
+    # detected photon number is Binomial(n, eta)
+    m, eta = 4, 0.7
+    U = workloads.haar(m, 31)
+    S = np.array([1, 1, 0, 1], np.int32)
+    n = 3
+    by_k = np.zeros(n + 1)
+    for T in _detected(m, n):
+        by_k[int(T.sum())] += oracle.lossy_probability(U, [eta] * m, S, T)
+    for k in range(n + 1):
+        assert abs(by_k[k] - math.comb(n, k) * eta ** k * (1 - eta) ** (n - k)) < 1e-12
+    assert abs(by_k.sum() - 1.0) < 1e-12
+
+
+def test_lossy_mean_occupation():
+    # <n_i> = eta_i sum_j |U_ij|^2 s_j for Fock inputs through a linear
+    # interferometer followed by loss on mode i
+    m = 4
+    U = workloads.haar(m, 32)
+    eta = [0.9, 0.5, 0.25, 1.0]
+    S = np.array([2, 0, 1, 1], np.int32)
+    mean = np.zeros(m)
+    for T in _detected(m, 4):
+        mean += T * oracle.lossy_probability(U, eta, S, T)
+    want = np.array(eta) * (np.abs(U) ** 2 @ S)
+    assert np.max(np.abs(mean - want)) < 1e-12
+
+
+def test_no_loss_reduces_to_ideal_and_dilation_is_unitary():
+    m = 3
+    U = workloads.haar(m, 33)
+    S = np.array([1, 2, 0], np.int32)
+    for T in workloads.fock_outputs(m, 3):
+        assert abs(oracle.lossy_probability(U, [1.0] * m, S, T) - oracle.probability(U, S, T)) < 1e-14
+    Ud = oracle.loss_dilation(U, [0.3, 0.6, 0.9])
+    assert np.max(np.abs(Ud @ Ud.conj().T - np.eye(6))) < 1e-14
