@@ -178,13 +178,19 @@ def main() -> int:
             onesk = np.ones(nk, np.int32)
             pk = pq.PatternSet([onesk], [onesk], nk)
             gk = torch.ones(1, dtype=torch.complex128, device=dev)
-            # sustained load first (the clock ramps up under load), then the
-            # forward and reverse sweeps back to back, each over ~0.1 s or more
-            reps_f = max(10, int(0.1 / (2.9e-3 * 2.0 ** (nk - 30))))
+            # one call each sizes the loops (~0.1 s of forward sweeps, at
+            # most 2000 calls); sustained load first (the clock ramps up under
+            # load), then the forward and reverse sweeps back to back
+            eng.grad_patterns(Uk, pk, gk)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            eng.perm(Uk, onesk, onesk)
+            torch.cuda.synchronize()
+            t_one = time.perf_counter() - t0
+            reps_f = min(2000, max(10, int(0.1 / t_one)))
             reps_b = max(4, reps_f // 4)
             for _ in range(reps_f):
                 eng.perm(Uk, onesk, onesk)
-            eng.grad_patterns(Uk, pk, gk)
             torch.cuda.synchronize()
             eng.profile(True)
             eng.profile_read()
@@ -192,13 +198,20 @@ def main() -> int:
                 eng.perm(Uk, onesk, onesk)
             torch.cuda.synchronize()
             nf, msf = eng.profile_read()
+            # whole reverse call (sweep, derivative reductions, scatter into
+            # dU) bracketed by events on the stream the library launches on
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record()
             for _ in range(reps_b):
                 eng.grad_patterns(Uk, pk, gk)
+            ev1.record()
             torch.cuda.synchronize()
             nb, msb = eng.profile_read()
             eng.profile(False)
+            full_b = ev0.elapsed_time(ev1) / reps_b
             grad_kernel.append({"n": nk, "forward_sweep_ms": msf / nf, "reverse_sweep_ms": msb / nb,
-                                "ratio": (msb / nb) / (msf / nf)})
+                                "ratio": (msb / nb) / (msf / nf), "reverse_call_ms": full_b,
+                                "call_ratio": full_b / (msf / nf)})
         print(f"# reverse/forward sweeps: {grad_kernel}", file=sys.stderr, flush=True)
 
     # batched workloads through pq_perm_many (sweep kernels timed with HIP

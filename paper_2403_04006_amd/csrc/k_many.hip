@@ -36,19 +36,8 @@ __global__ __launch_bounds__(64) void many_final_kernel(const ManyFinalArgs a) {
             if (a.perm) a.perm[J.out_offset] = cplx{re, im};
             if (a.amp) a.amp[J.out_offset] = cplx{re * J.norm, im * J.norm};
         }
-        if (a.adjoint) {
-            const int nent = J.r * J.nc;
-            cplx* D = a.dpat + a.dpat_off[p];
-            for (int e = t; e < nent; e += 64) {
-                double re = 0.0, im = 0.0;
-                for (int k = 0; k < J.nchunks; ++k) {
-                    const double* q = base + (size_t)k * sd + 4 + 2 * e;
-                    re += q[0];
-                    im += q[1];
-                }
-                D[e] = cplx{re * J.scale, im * J.scale};
-            }
-        }
+        // (reverse sweeps: the derivative part of the slots is reduced by
+        // the two dred stages)
     } else {
         // Laplace expansion: L_j from the chunk sums, then out[l] = sum_j U[l, C_j] L_j
         __shared__ cplx L[kMaxExtendCols];
@@ -75,6 +64,47 @@ __global__ __launch_bounds__(64) void many_final_kernel(const ManyFinalArgs a) {
             if (a.perm) a.perm[J.out_offset + l] = cplx{re, im};
         }
     }
+}
+
+__global__ __launch_bounds__(64) void dred1_kernel(const DRedArgs a) {
+    const DRedItem it = a.items[blockIdx.x];
+    const BJob& J = a.jobs[it.pat];
+    const int nent = J.r * J.nc;
+    const int e = it.eb * 64 + (int)threadIdx.x;
+    if (e >= nent) return;
+    const int cls = a.pat_class[it.pat];
+    const int sd = a.class_sd[cls];
+    const double* base = a.partials + a.class_off[cls] + (size_t)a.pat_slot[it.pat] * sd + 4 + 2 * e;
+    const int k0 = it.cb * 64;
+    const int k1 = J.nchunks < k0 + 64 ? J.nchunks : k0 + 64;
+    double re = 0.0, im = 0.0;
+    for (int k = k0; k < k1; ++k) {
+        re += base[(size_t)k * sd];
+        im += base[(size_t)k * sd + 1];
+    }
+    a.part[it.part_off + (int64_t)it.cb * nent + e] = cplx{re, im};
+}
+
+__global__ __launch_bounds__(64) void dred2_kernel(const DRedArgs a) {
+    const DRedItem it = a.items[blockIdx.x];
+    const BJob& J = a.jobs[it.pat];
+    const int nent = J.r * J.nc;
+    const int e = it.eb * 64 + (int)threadIdx.x;
+    if (e >= nent) return;
+    double re = 0.0, im = 0.0;
+    for (int cb = 0; cb < it.ncb; ++cb) {
+        const cplx v = a.part[it.part_off + (int64_t)cb * nent + e];
+        re += v.re;
+        im += v.im;
+    }
+    a.dpat[a.dpat_off[it.pat] + e] = cplx{re * J.scale, im * J.scale};
+}
+
+hipError_t launch_dred(int stage, const DRedArgs& a, int nitems, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    if (stage == 1) hipLaunchKernelGGL(dred1_kernel, dim3(nitems), dim3(64), 0, s, a);
+    else hipLaunchKernelGGL(dred2_kernel, dim3(nitems), dim3(64), 0, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_many_final(const ManyFinalArgs& a, hipStream_t s) {

@@ -61,6 +61,10 @@ struct ManyEntry {
     cplx* d_dpat = nullptr;
     int32_t* d_sc_off = nullptr;     // adjoint: scatter lists (CSR over dU entries)
     int32_t* d_sc_items = nullptr;
+    DRedItem* d_red1 = nullptr;      // adjoint: derivative reduction items
+    DRedItem* d_red2 = nullptr;
+    cplx* d_red_part = nullptr;
+    int nred1 = 0, nred2 = 0;
     uint64_t last_use = 0;
     ~ManyEntry() {
         if (dmem) hipFree(dmem);
@@ -255,6 +259,26 @@ int build_many(pq_ctx* ctx, int mode, int32_t m, const std::vector<PatternSpec>&
         class_sd.push_back(C.slot_doubles);
     }
 
+    // adjoint: reduction items of the derivative slots (see DRedItem)
+    std::vector<DRedItem> red1, red2;
+    size_t red_part = 0;
+    if (adj) {
+        for (size_t k = 0; k < pats.size(); ++k) {
+            if (pat_class[k] < 0) continue;
+            const BJob& b = hj[k];
+            const int nent = b.r * b.nc;
+            if (nent == 0) continue;
+            const int neb = (nent + 63) / 64, ncb = (b.nchunks + 63) / 64;
+            for (int eb = 0; eb < neb; ++eb) {
+                for (int cb = 0; cb < ncb; ++cb) red1.push_back(DRedItem{(int32_t)k, eb, cb, ncb, (int64_t)red_part});
+                red2.push_back(DRedItem{(int32_t)k, eb, 0, ncb, (int64_t)red_part});
+            }
+            red_part += (size_t)ncb * nent;
+        }
+    }
+    E.nred1 = (int)red1.size();
+    E.nred2 = (int)red2.size();
+
     // adjoint: for every dU entry, the (pattern, D index) pairs touching it,
     // in pattern order (a counting sort by entry)
     std::vector<int32_t> sc_off, sc_items;
@@ -306,11 +330,14 @@ int build_many(pq_ctx* ctx, int mode, int32_t m, const std::vector<PatternSpec>&
     const size_t oDo = cv.take(sizeof(int64_t) * sz(dpat_off.size()));
     const size_t oSo = cv.take(sizeof(int32_t) * sz(sc_off.size()));
     const size_t oSi = cv.take(sizeof(int32_t) * sz(sc_items.size()));
+    const size_t oR1 = cv.take(sizeof(DRedItem) * sz(red1.size()));
+    const size_t oR2 = cv.take(sizeof(DRedItem) * sz(red2.size()));
     const size_t upload_bytes = cv.off;
     const size_t oMat = cv.take(sizeof(cplx) * sz(mat_elems));
     const size_t oTab = cv.take(sizeof(StepEntry) * 2 * kMaxInner * sz(sigs.size()));
     const size_t oPart = cv.take(sizeof(double) * sz(partial_doubles));
     const size_t oDp = cv.take(sizeof(cplx) * sz(dpat_elems));
+    const size_t oRp = cv.take(sizeof(cplx) * sz(red_part));
     if (hipMalloc((void**)&E.dmem, cv.off) != hipSuccess) {
         E.dmem = nullptr;
         return ctx->fail(PQ_ENOMEM, "many: hipMalloc(%zu) failed", cv.off);
@@ -327,6 +354,9 @@ int build_many(pq_ctx* ctx, int mode, int32_t m, const std::vector<PatternSpec>&
     E.d_dpat_off = (int64_t*)(E.dmem + oDo);
     E.d_sc_off = (int32_t*)(E.dmem + oSo);
     E.d_sc_items = (int32_t*)(E.dmem + oSi);
+    E.d_red1 = (DRedItem*)(E.dmem + oR1);
+    E.d_red2 = (DRedItem*)(E.dmem + oR2);
+    E.d_red_part = (cplx*)(E.dmem + oRp);
     E.d_mat = (cplx*)(E.dmem + oMat);
     E.d_tabs = (StepEntry*)(E.dmem + oTab);
     E.d_partials = (double*)(E.dmem + oPart);
@@ -347,6 +377,8 @@ int build_many(pq_ctx* ctx, int mode, int32_t m, const std::vector<PatternSpec>&
     put(oDo, dpat_off.data(), sizeof(int64_t) * dpat_off.size());
     put(oSo, sc_off.data(), sizeof(int32_t) * sc_off.size());
     put(oSi, sc_items.data(), sizeof(int32_t) * sc_items.size());
+    put(oR1, red1.data(), sizeof(DRedItem) * red1.size());
+    put(oR2, red2.data(), sizeof(DRedItem) * red2.size());
     return ctx->upload(E.dmem, stage, upload_bytes, st);
 }
 
@@ -410,6 +442,22 @@ int run_many(pq_ctx* ctx, ManyEntry& E, const cplx* U, int64_t ldu, int32_t m, c
     rc = ctx->check(launch_many_final(fa, st), "many final");
     if (rc) return rc;
     if (E.mode == kModeAdj) {
+        DRedArgs ra;
+        ra.jobs = E.d_jobs;
+        ra.pat_slot = E.d_pat_slot;
+        ra.pat_class = E.d_pat_class;
+        ra.class_off = E.d_class_off;
+        ra.class_sd = E.d_class_sd;
+        ra.partials = E.d_partials;
+        ra.dpat_off = E.d_dpat_off;
+        ra.part = E.d_red_part;
+        ra.dpat = E.d_dpat;
+        ra.items = E.d_red1;
+        rc = ctx->check(launch_dred(1, ra, E.nred1, st), "derivative reduction");
+        if (rc) return rc;
+        ra.items = E.d_red2;
+        rc = ctx->check(launch_dred(2, ra, E.nred2, st), "derivative reduction");
+        if (rc) return rc;
         GradScatterArgs ga;
         ga.offsets = E.d_sc_off;
         ga.items = E.d_sc_items;

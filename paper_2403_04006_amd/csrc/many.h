@@ -72,6 +72,29 @@ struct ManyFinalArgs {
     cplx* dpat;                // adjoint: per pattern r x nc complex d perm / d B (scaled)
 };
 
+// Reduction of the reverse sweeps' derivative slots in two fixed-order
+// stages: stage 1 adds up to 64 consecutive slots of a pattern for 64
+// consecutive entries, stage 2 adds a pattern's stage-1 partials and scales.
+// Item (pat, eb, cb): entries [64 eb, 64 eb + 64), slots [64 cb, 64 cb + 64);
+// stage-2 items have cb = 0 and read ncb partial rows.
+struct DRedItem {
+    int32_t pat, eb, cb, ncb;
+    int64_t part_off;       // complex offset of the pattern's [ncb][r * nc] partials
+};
+
+struct DRedArgs {
+    const DRedItem* items;
+    const BJob* jobs;
+    const int32_t* pat_slot;
+    const int32_t* pat_class;
+    const int64_t* class_off;
+    const int32_t* class_sd;
+    const double* partials;
+    const int64_t* dpat_off;
+    cplx* part;
+    cplx* dpat;
+};
+
 // Scatter of the per-pattern derivatives into dU (conjugate-Wirtinger VJP).
 // For every entry e = a*m + b of dU, items[offsets[e] .. offsets[e+1]) list
 // the (pattern, index into dpat) pairs that touch it, in pattern order.

@@ -25,6 +25,7 @@ PQ_WCLASS(PQ_WDECL)
 
 hipError_t launch_many(int mode, int ncmax, int var, const ManyArgs& a, hipStream_t s);
 hipError_t launch_many_final(const ManyFinalArgs& a, hipStream_t s);
+hipError_t launch_dred(int stage, const DRedArgs& a, int nitems, hipStream_t s);
 hipError_t launch_grad_scatter(const GradScatterArgs& a, hipStream_t s);
 
 }  // namespace pq
