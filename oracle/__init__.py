@@ -31,6 +31,13 @@ What it computes (each function cites the passage it follows):
 * ``beamsplitter(theta, phi)``, ``mesh_unitary(angles)`` -- the beamsplitter
                              matrix of the "Beamsplitter gate" section and a
                              rectangular mesh of such cells.
+* ``lhaf_bruteforce(B)``  -- Eq. loop_hafnian (Eq. haf_def with loops off):
+                             the sum over single-pair matchings of an
+                             explicit matrix, lowest vertex matched first.
+* ``lhaf_rep(A, gamma, reps)`` -- the loop hafnian of filldiag(A_r, gamma_r),
+                             mode i repeated r_i times (the GBS detection
+                             probability's matrix function), x87 extended
+                             precision; gamma None gives the hafnian.
 * ``two_mode_amplitude``   -- the two-mode Fock expansion of the beamsplitter
                              ("States and their evolution"), with the ket
                              normalisation the printed coefficient omits.
@@ -75,8 +82,9 @@ def _lib():
     lib.orc_perm_ryser_mult.argtypes = [dptr, ctypes.c_int64, ctypes.c_int, iptr, iptr, ldptr]
     lib.orc_perm_grad.argtypes = [dptr, ctypes.c_int64, ctypes.c_int, iptr, iptr, ldptr]
     lib.orc_perm_ryser_mult_q.argtypes = [dptr, ctypes.c_int64, ctypes.c_int, iptr, iptr, dptr]
+    lib.orc_lhaf_rep.argtypes = [dptr, ctypes.c_int64, ctypes.c_int, dptr, iptr, ldptr]
     for f in ("orc_perm_bruteforce", "orc_perm_ryser", "orc_perm_ryser_mult", "orc_perm_grad",
-              "orc_perm_ryser_mult_q"):
+              "orc_perm_ryser_mult_q", "orc_lhaf_rep"):
         getattr(lib, f).restype = ctypes.c_int
     lib.orc_num_threads.restype = ctypes.c_int
     lib.orc_long_double_mantissa_bits.restype = ctypes.c_int
@@ -435,3 +443,67 @@ def mesh_loss_grad(angles, cells, modes: int, S, patterns) -> np.ndarray:
         dp = np.einsum("ab,qkab->qk", G, J)
         total += np.real(dp / p)
     return -2.0 * total / len(patterns)
+
+
+# ------------------------------------------------------------ loop hafnians
+def lhaf_bruteforce(B, loops: bool = True):
+    """Eq. loop_hafnian (Eq. haf_def when ``loops`` is False): the sum over
+    every single-pair matching of the vertices 0..N-1 of the product of its
+    edge weights B[i][j] (i < j) and loop weights B[i][i].  Each matching is
+    listed once by matching the lowest remaining vertex first (the ordering
+    condition under Eq. haf_def).  Works on any element type (Python ints
+    give exact integers); N <= 12."""
+    B = [list(row) for row in B]
+    n = len(B)
+    if any(len(row) != n for row in B) or n > 12:
+        raise ValueError("square matrix with N <= 12 expected")
+
+    def rec(rem):
+        if not rem:
+            return 1
+        v, rest = rem[0], rem[1:]
+        total = B[v][v] * rec(rest) if loops else 0
+        for k, u in enumerate(rest):
+            total = total + B[v][u] * rec(rest[:k] + rest[k + 1:])
+        return total
+
+    return rec(tuple(range(n)))
+
+
+def expand_lhaf(A, gamma, reps) -> np.ndarray:
+    """filldiag(A_r, gamma_r): mode i repeated r_i times; the diagonal holds
+    gamma (zeros when gamma is None)."""
+    A = _cplx(A)
+    reps = [int(v) for v in reps]
+    idx = [i for i, r in enumerate(reps) for _ in range(r)]
+    B = A[np.ix_(idx, idx)].copy()
+    np.fill_diagonal(B, 0.0 if gamma is None else np.asarray(gamma, np.complex128)[idx])
+    return B
+
+
+def lhaf_rep_ld(A, gamma, reps) -> tuple:
+    A = _cplx(A)
+    d = A.shape[0]
+    if A.shape != (d, d):
+        raise ValueError("square matrix expected")
+    r = _occ(reps, d)
+    g = None
+    if gamma is not None:
+        g = np.ascontiguousarray(np.asarray(gamma, dtype=np.complex128))
+        if g.shape != (d,):
+            raise ValueError("gamma must have length d")
+    out = (ctypes.c_longdouble * 2)()
+    st = _lib().orc_lhaf_rep(_dp(A), d, d, _dp(g) if g is not None else None,
+                             r.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), out)
+    if st:
+        raise RuntimeError(f"oracle error {st}")
+    return out[0], out[1]
+
+
+def lhaf_rep(A, gamma, reps) -> complex:
+    """Loop hafnian of filldiag(A_r, gamma_r) (Eq. loop_hafnian; Appendix,
+    GBS detection probability); gamma None: the hafnian (Eq. haf_def).  Reads
+    the upper triangle of A."""
+    re, im = lhaf_rep_ld(A, gamma, reps)
+    return complex(float(re), float(im))
+

@@ -24,6 +24,10 @@
  *                           the alternating sum cancels beyond what 64 bits
  *                           of mantissa can hold.
  *   orc_perm_grad        -- d perm(U_{T,S}) / d U_ij = t_i s_j perm(U_{T-e_i,S-e_j}).
+ *   orc_lhaf_rep         -- the loop hafnian (Appendix, Eq. loop_hafnian) of the
+ *                           matrix with mode i repeated r_i times (the filldiag
+ *                           form of the GBS detection probability); without
+ *                           loops, the hafnian (Eq. haf_def).
  *
  * Complex matrices are interleaved (re, im) doubles, row-major with a leading
  * dimension counted in complex elements.  Results are returned as long double
@@ -362,3 +366,74 @@ int orc_perm_grad(const double* U, int64_t ldu, int m,
 }
 
 int orc_num_threads(void) { return omp_get_max_threads(); }
+
+/* ---------------------------------------------------------------------------
+ * Loop hafnian with repeated modes (Appendix, Eq. loop_hafnian; Eq. haf_def
+ * when loops are off).  The matrix is filldiag(A_r, gamma_r): vertex copies
+ * of mode i and mode k are joined by an edge of weight A[i][k] (i < k, the
+ * upper triangle), two copies of mode i by A[i][i], and every copy of mode i
+ * carries a loop of weight gamma[i].
+ *
+ * Every single-pair matching is listed once by matching the lowest remaining
+ * vertex first (the ordering condition under Eq. haf_def).  With copies of a
+ * mode interchangeable, the lowest vertex is a copy of the first mode i with
+ * o_i > 0, and it takes
+ *   a loop                                  gamma_i   f(o - e_i)
+ *   one of the other o_i - 1 copies of i    A_ii      f(o - 2 e_i)
+ *   one of the o_k copies of a later mode k A_ik      f(o - e_i - e_k)
+ * so lhaf over occupation o follows from smaller occupations; f(0) = 1.  The
+ * table runs over every o <= r in mixed-radix order (every term it reads has
+ * a smaller index).  gamma == NULL: no loops (the hafnian).
+ * ------------------------------------------------------------------------- */
+int orc_lhaf_rep(const double* A, int64_t lda, int d, const double* gamma,
+                 const int32_t* reps, long double out[2]) {
+    if (d < 0 || lda < d || !reps) return 1;
+    int mode[64], r[64], k = 0;
+    for (int i = 0; i < d; ++i) {
+        if (reps[i] < 0) return 1;
+        if (reps[i] == 0) continue;
+        if (k == 64) return 2;
+        mode[k] = i;
+        r[k] = reps[i];
+        ++k;
+    }
+    int64_t stride[65];
+    stride[0] = 1;
+    for (int i = 0; i < k; ++i) {
+        stride[i + 1] = stride[i] * (int64_t)(r[i] + 1);
+        if (stride[i + 1] > ((int64_t)1 << 23)) return 2;
+    }
+    const int64_t total = stride[k];
+    cld* f = (cld*)malloc(sizeof(cld) * (size_t)total);
+    if (!f) return 3;
+    f[0] = cld_make(1.0L, 0.0L);
+    int o[64];
+    for (int64_t idx = 1; idx < total; ++idx) {
+        int64_t rest = idx;
+        for (int i = 0; i < k; ++i) {
+            o[i] = (int)(rest % (r[i] + 1));
+            rest /= (r[i] + 1);
+        }
+        int i = 0;
+        while (o[i] == 0) ++i;
+        cld acc = cld_make(0.0L, 0.0L);
+        if (gamma) {
+            const cld g = cld_make((long double)gamma[2 * mode[i]], (long double)gamma[2 * mode[i] + 1]);
+            acc = cld_add(acc, cld_mul(g, f[idx - stride[i]]));
+        }
+        if (o[i] >= 2) {
+            const cld a = ld_elem(A, lda, mode[i], mode[i]);
+            acc = cld_add(acc, cld_scale(cld_mul(a, f[idx - 2 * stride[i]]), (long double)(o[i] - 1)));
+        }
+        for (int j = i + 1; j < k; ++j) {
+            if (o[j] == 0) continue;
+            const cld a = ld_elem(A, lda, mode[i], mode[j]);
+            acc = cld_add(acc, cld_scale(cld_mul(a, f[idx - stride[i] - stride[j]]), (long double)o[j]));
+        }
+        f[idx] = acc;
+    }
+    out[0] = f[total - 1].re;
+    out[1] = f[total - 1].im;
+    free(f);
+    return 0;
+}

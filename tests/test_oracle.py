@@ -442,3 +442,128 @@ def test_no_loss_reduces_to_ideal_and_dilation_is_unitary():
         assert abs(oracle.lossy_probability(U, [1.0] * m, S, T) - oracle.probability(U, S, T)) < 1e-14
     Ud = oracle.loss_dilation(U, [0.3, 0.6, 0.9])
     assert np.max(np.abs(Ud @ Ud.conj().T - np.eye(6))) < 1e-14
+
+
+# -------------------------------------------------------------- loop hafnian
+def involutions(n):
+    # number of single-pair matchings of n vertices: T(n) = T(n-1) + (n-1) T(n-2)
+    t = [1, 1]
+    for k in range(2, n + 1):
+        t.append(t[-1] + (k - 1) * t[-2])
+    return t[n]
+
+
+def odd_double_factorial(n):
+    # (n - 1)!! perfect matchings of n (even) vertices
+    return math.prod(range(n - 1, 0, -2)) if n % 2 == 0 else 0
+
+
+@pytest.mark.parametrize("n", range(0, 11))
+def test_lhaf_bruteforce_counts_matchings(n):
+    J = [[1] * n for _ in range(n)]
+    assert oracle.lhaf_bruteforce(J, loops=False) == odd_double_factorial(n)
+    assert oracle.lhaf_bruteforce(J) == involutions(n)
+
+
+def test_lhaf_bruteforce_small_closed_forms():
+    rng = np.random.default_rng(3)
+    a = rng.integers(-9, 10, (4, 4)).tolist()
+    assert oracle.lhaf_bruteforce([]) == 1
+    assert oracle.lhaf_bruteforce([[a[0][0]]]) == a[0][0]
+    assert oracle.lhaf_bruteforce([r[:2] for r in a[:2]]) == a[0][1] + a[0][0] * a[1][1]
+    three = [r[:3] for r in a[:3]]
+    assert oracle.lhaf_bruteforce(three) == (a[0][0] * a[1][1] * a[2][2] + a[0][0] * a[1][2]
+                                              + a[1][1] * a[0][2] + a[2][2] * a[0][1])
+    assert oracle.lhaf_bruteforce(three, loops=False) == 0
+    assert oracle.lhaf_bruteforce(a, loops=False) == a[0][1] * a[2][3] + a[0][2] * a[1][3] + a[0][3] * a[1][2]
+
+
+@pytest.mark.parametrize("k", range(1, 6))
+def test_haf_complete_bipartite_is_factorial(k):
+    # perfect matchings of K_{k,k}: k!
+    n = 2 * k
+    B = [[1 if (i < k) != (j < k) else 0 for j in range(n)] for i in range(n)]
+    assert oracle.lhaf_bruteforce(B, loops=False) == math.factorial(k)
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_lhaf_rep_matches_bruteforce_on_expanded_matrix(seed):
+    # upper triangle only: a non-symmetric A would expose a transposed read
+    rng = np.random.default_rng(seed)
+    d = int(rng.integers(1, 6))
+    reps = rng.integers(0, 4, d)
+    while reps.sum() > 10:
+        reps[int(rng.integers(0, d))] = 0
+    A = rng.standard_normal((d, d)) + 1j * rng.standard_normal((d, d))
+    g = rng.standard_normal(d) + 1j * rng.standard_normal(d)
+    B = oracle.expand_lhaf(A, g, reps)
+    for gamma, loops in ((g, True), (None, False)):
+        want = complex(oracle.lhaf_bruteforce(B, loops=loops))
+        got = oracle.lhaf_rep(A, gamma, reps)
+        assert abs(got - want) <= 1e-12 * max(1.0, abs(want)), (reps, loops)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_haf_rep_block_matrix_is_repeated_permanent(seed):
+    # haf([[0, B], [B^T, 0]]) with repetitions (t, s) pairs row copies with
+    # column copies only: perm(B_{t,s}) (ties the hafnian table to Ryser)
+    rng = np.random.default_rng(100 + seed)
+    k = int(rng.integers(2, 9))
+    B = workloads.gaussian_matrix(k, seed)
+    t = rng.integers(0, 4, k)
+    s = np.zeros(k, np.int64)
+    for _ in range(int(t.sum())):
+        s[int(rng.integers(0, k))] += 1
+    while np.prod(t + 1) * np.prod(s + 1) > (1 << 22):
+        t[int(np.argmax(t))] -= 1
+        s[int(np.argmax(s))] -= 1
+    M = np.zeros((2 * k, 2 * k), np.complex128)
+    M[:k, k:] = B
+    M[k:, :k] = B.T
+    got = oracle.lhaf_rep(M, None, np.concatenate([t, s]))
+    want = oracle.perm_mult(B, s, t)
+    assert rel(got, want) <= 1e-13
+    # loops of weight zero change nothing
+    assert rel(oracle.lhaf_rep(M, np.zeros(2 * k), np.concatenate([t, s])), want) <= 1e-13
+
+
+@pytest.mark.parametrize("reps", [[3], [2, 2], [1, 2, 3], [5, 0, 4], [2] * 6, [10, 10, 10], [1] * 12])
+def test_lhaf_rep_constant_matrix_hermite_form(reps):
+    # A = a J, gamma = g 1: every matching of N vertices with j pairs counts
+    # a^j g^(N-2j); there are N! / (j! (N-2j)! 2^j) of them
+    a, g = 0.75 - 0.5j, 0.5 + 0.25j
+    d = len(reps)
+    N = sum(reps)
+    want = sum(math.factorial(N) / (math.factorial(j) * math.factorial(N - 2 * j) * 2 ** j) * a ** j * g ** (N - 2 * j)
+               for j in range(N // 2 + 1))
+    got = oracle.lhaf_rep(np.full((d, d), a), np.full(d, g), reps)
+    assert rel(got, want) <= 1e-14
+    want_haf = (math.factorial(N) / (math.factorial(N // 2) * 2 ** (N // 2)) * a ** (N // 2)) if N % 2 == 0 else 0
+    assert abs(oracle.lhaf_rep(np.full((d, d), a), None, reps) - want_haf) <= 1e-14 * max(1, abs(want_haf))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_lhaf_rep_diagonal_scaling_and_mode_permutation(seed):
+    rng = np.random.default_rng(200 + seed)
+    d = 6
+    A = workloads.symmetric_gaussian(d, seed)
+    g = workloads.loop_vector(d, seed)
+    reps = rng.integers(0, 4, d)
+    base = oracle.lhaf_rep(A, g, reps)
+    D = rng.standard_normal(d) + 1j * rng.standard_normal(d)
+    scaled = oracle.lhaf_rep(D[:, None] * A * D[None, :], D * g, reps)
+    assert rel(scaled, np.prod(D ** reps) * base) <= 1e-13
+    p = rng.permutation(d)
+    assert rel(oracle.lhaf_rep(A[np.ix_(p, p)], g[p], reps[p]), base) <= 1e-13
+
+
+def test_lhaf_rep_loops_only_and_no_loops():
+    rng = np.random.default_rng(7)
+    d = 5
+    g = rng.standard_normal(d) + 1j * rng.standard_normal(d)
+    reps = np.array([2, 0, 3, 1, 1])
+    assert rel(oracle.lhaf_rep(np.zeros((d, d)), g, reps), np.prod(g ** reps)) <= 1e-15
+    A = workloads.gbs_matrix(d, 1)
+    assert oracle.lhaf_rep(A, np.zeros(d), reps) == oracle.lhaf_rep(A, None, reps)
+    assert oracle.lhaf_rep(A, None, [1, 0, 0, 0, 0]) == 0
+    assert oracle.lhaf_rep(A, g, [0] * d) == 1

@@ -19,6 +19,10 @@ Workload recipes (all seeded, all synthetic):
 * differentiation: a 12-mode rectangular beamsplitter mesh with angles uniform
   in [0, 2 pi) and collision-free 8-photon output patterns drawn with
   replacement.
+* loop hafnians: the symmetric matrix U diag(tanh r) U^T of d single-mode
+  squeezers (r = arcsinh 1, the paper's GBS benchmark squeezing) followed by a
+  Haar interferometer U, with a seeded complex loop vector for displacement;
+  repetitions (2, ..., 2) as in the paper's hafnian benchmarks.
 """
 from __future__ import annotations
 
@@ -31,6 +35,7 @@ __all__ = [
     "haar", "gaussian_matrix", "collision_free_block", "bounded_compositions",
     "repeated_patterns", "fock_outputs", "sampling_jobs", "mesh_angles",
     "mesh_patterns", "random_occupations", "MESH_MODES", "MESH_CELLS",
+    "gbs_matrix", "loop_vector", "symmetric_gaussian",
 ]
 
 
@@ -49,6 +54,25 @@ def gaussian_matrix(n: int, seed: int, scale: float | None = None) -> np.ndarray
     s = (1.0 / np.sqrt(n)) if scale is None else scale
     z = (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) * (s / np.sqrt(2.0))
     return np.ascontiguousarray(z)
+
+
+def gbs_matrix(d: int, seed: int, r: float = float(np.arcsinh(1.0))) -> np.ndarray:
+    """Symmetric d x d matrix U diag(tanh r) U^T with U = haar(d, seed)."""
+    U = haar(d, seed)
+    return np.ascontiguousarray((U * np.tanh(r)) @ U.T)
+
+
+def loop_vector(d: int, seed: int, scale: float = 0.5) -> np.ndarray:
+    """Complex loop weights ~ CN(0, scale^2), seeded apart from the matrix."""
+    rng = np.random.default_rng(10_000 + seed)
+    z = (rng.standard_normal(d) + 1j * rng.standard_normal(d)) * (scale / np.sqrt(2.0))
+    return np.ascontiguousarray(z)
+
+
+def symmetric_gaussian(d: int, seed: int, scale: float = 1.0) -> np.ndarray:
+    """(Z + Z^T) / 2 with Z ~ CN(0, scale^2) entries."""
+    z = gaussian_matrix(d, seed, scale)
+    return np.ascontiguousarray((z + z.T) / 2.0)
 
 
 def collision_free_block(n: int, seed: int) -> np.ndarray:
