@@ -73,6 +73,7 @@ def main() -> int:
     ap.add_argument("--cpu-sample-n", type=int, default=28)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
+    ap.add_argument("--no-haf", action="store_true", help="skip the loop hafnian workloads")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the repeated-pattern and sampling-replay batches")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -304,6 +305,33 @@ def main() -> int:
             "completeness_error": abs(float(torch.sum(torch.abs(amp16) ** 2)) - 1.0)}
         print(f"# batched: {batched}", file=sys.stderr, flush=True)
 
+    # loop hafnians with the paper's (2, ..., 2) repetitions on 20 modes (40
+    # vertices, 2 * 3^19 Gray terms), GBS-shaped matrix U diag(tanh r) U^T,
+    # without and with loops; the sweep timed with the sweep events
+    hafnian = None
+    if not args.no_haf:
+        hafnian = {}
+        dh = 20
+        Ah = torch.from_numpy(workloads.gbs_matrix(dh, 0)).to(dev)
+        gh = torch.from_numpy(workloads.loop_vector(dh, 0)).to(dev)
+        hterms = 2 * 3 ** (dh - 1)
+        for name, gam in (("haf_2x20", None), ("lhaf_2x20", gh)):
+            eng.lhaf(Ah, gam, [2] * dh)
+            torch.cuda.synchronize()
+            eng.profile(True)
+            eng.profile_read()
+            tw = time.perf_counter()
+            for _ in range(3):
+                eng.lhaf(Ah, gam, [2] * dh)
+            torch.cuda.synchronize()
+            tw = (time.perf_counter() - tw) / 3
+            nl_, ms = eng.profile_read()
+            eng.profile(False)
+            hafnian[name] = {"modes": dh, "repetitions": 2, "vertices": 2 * dh, "loops": gam is not None,
+                             "gray_terms": hterms, "sweep_ms": ms / nl_, "wall_ms": tw * 1e3,
+                             "terms_per_s": hterms / (ms / nl_ / 1e3)}
+        print(f"# hafnian: {hafnian}", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -356,6 +384,7 @@ def main() -> int:
         "grad_forward": grad_ratio,
         "grad_kernel": grad_kernel,
         "batched": batched,
+        "hafnian": hafnian,
     }
     print(json.dumps(line), flush=True)
     eng.close()

@@ -231,6 +231,29 @@ int pq_sample_chain(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m, int32
 int pq_loss_dilation(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m, const double* eta, pq_c128* Ud,
                      int64_t ldd, void* stream);
 
+/*
+ * pq_lhaf -- loop hafnian with repeated modes (Appendix, Eq. loop_hafnian;
+ * with gamma NULL the hafnian, Eq. haf_def), the matrix function of the
+ * Gaussian Boson Sampling detection probability: lhaf(filldiag(A_r, gamma_r)),
+ * where mode i is repeated reps[i] times, two copies of modes i < k are
+ * joined by an edge of weight A[i][k], two copies of mode i by A[i][i], and
+ * every copy of mode i carries a loop of weight gamma[i].  Only the upper
+ * triangle (i <= k) of A is read.  Evaluated by a Glynn-type Gray-code sum
+ * over vertex signs with repetition digits and halving (the Gaussian Boson
+ * Sampling section), complex FP64, double-double reduction.
+ *   A      device, d x d row-major, leading dimension lda >= d.
+ *   gamma  device, d complex, or NULL (no loops: the hafnian).
+ *   reps   host int32[d], >= 0; N = sum reps.
+ *   out    device, 1 complex, written.
+ * N == 0 writes 1; without loops an odd N writes 0.  Limits (PQ_ERANGE):
+ * N <= 64, at most 48 modes with reps > 0, at most 32 of them beyond the
+ * lane digits (for (2, ..., 2) repetitions: 36 modes), at most 2^52 time
+ * states.  Negative reps, NULL out/reps, or NULL A / lda < d with N > 0 give
+ * PQ_EINVAL.
+ */
+int pq_lhaf(pq_ctx* ctx, const pq_c128* A, int64_t lda, int32_t d, const pq_c128* gamma,
+            const int32_t* reps, pq_c128* out, void* stream);
+
 /* Number of occupation vectors with n photons on m modes, C(n+m-1, n);
  * -1 for m < 1, n < 0, or a count above 2^62 (host, no GPU work). */
 int64_t pq_fock_count(int32_t m, int32_t n);

@@ -245,6 +245,28 @@ class Engine:
         _check(st, self._ctx)
         return Ud
 
+    def lhaf(self, A: torch.Tensor, gamma: torch.Tensor | None, reps: Sequence[int]) -> torch.Tensor:
+        """Loop hafnian of filldiag(A_r, gamma_r) with mode i repeated reps[i]
+        times (pq_lhaf); gamma None gives the hafnian.  Returns a 1-element
+        complex128 tensor on A's device."""
+        A, lda = _as_matrix(A)
+        d = A.shape[0]
+        r = np.ascontiguousarray(np.asarray(reps, dtype=np.int32))
+        if r.shape != (d,):
+            raise ValueError("reps needs one entry per mode")
+        g_ptr = None
+        if gamma is not None:
+            if gamma.dtype != torch.complex128 or gamma.device != A.device or tuple(gamma.shape) != (d,):
+                raise ValueError("gamma must be a complex128 vector of length d on A's device")
+            gamma = gamma.contiguous()
+            g_ptr = gamma.data_ptr()
+        out = torch.empty(1, dtype=torch.complex128, device=A.device)
+        st = self._lib.pq_lhaf(self._ctx, A.data_ptr(), lda, d, g_ptr,
+                               r.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), out.data_ptr(),
+                               _stream_handle(A.device))
+        _check(st, self._ctx)
+        return out
+
     def sample_chain_lossy(self, U: torch.Tensor, eta: Sequence[float], order: torch.Tensor,
                            uniforms: torch.Tensor) -> torch.Tensor:
         """Chain-rule samples through U followed by per-mode losses: the draws

@@ -88,6 +88,7 @@ _SIGNATURES = {
     "pq_sample_chain": ([_VP, _VP, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _VP, _VP, _VP,
                          _VP], ctypes.c_int),
     "pq_fock_unrank": ([ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, _I32P], ctypes.c_int),
+    "pq_lhaf": ([_VP, _VP, ctypes.c_int64, ctypes.c_int32, _VP, _I32P, _VP, _VP], ctypes.c_int),
 }
 
 _lib = None

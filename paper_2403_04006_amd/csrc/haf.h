@@ -1,0 +1,87 @@
+// Loop hafnian with repeated modes (Eq. loop_hafnian; Eq. haf_def without
+// loops): lhaf(filldiag(A_r, gamma_r)), mode i repeated r_i times, N = sum r.
+//
+// Glynn-type polarisation over vertices (the Gaussian Boson Sampling section
+// names Glynn-type hafnian sums with halving).  lhaf is the multilinear
+// coefficient of exp(x^T A x / 2 + gamma^T x) in the N vertex variables;
+// averaging prod_v x_v times that polynomial over x in {+1, -1}^N picks it out,
+// and the copies of a mode collapse to X_i = r_i - 2 d_i (d_i minus signs,
+// C(r_i, d_i) ways).  Pinning one copy of the fixed mode f (the smallest r) to
+// +1 halves the sum ("halving"):
+//
+//   lhaf = 2^{-(N-1)} sum_d prod_i (-1)^{d_i} C(rho_i - 1, d_i) P_N(q, l),
+//   q = X^T A X,  l = gamma^T X,
+//   P_N(q, l) = sum_{j=0}^{floor(N/2)} (q/2)^j l^{N-2j} / (j! (N-2j)!),
+//
+// with radix rho_f = r_f (d_f = 0..r_f - 1) and rho_i = r_i + 1 otherwise --
+// the digit structure of the generalised permanent sum.  Without loops
+// P_N = (q/2)^{N/2} / (N/2)! (zero for odd N).
+//
+// Work split: lane digits (product of radices <= 64) are fixed per lane; the
+// other ("time") digits walk a reflected Gray code shared by the wavefront.
+// When time digit t moves by dX = -+2 (d_t up / down), with v = A X before
+// the move,
+//   q += 2 dX v_t + dX^2 A_tt,   l += dX gamma_t,   v += dX A[:, t].
+// Only v_t of the moving digit is used: v_t = L_t + T_t, where L_t = sum over
+// lane digits j of A_tj X_j (per lane, from the uniform row) and T_t = sum
+// over time digits s of A_ts X_s (the same in every lane); lane s of the
+// wavefront keeps T_s.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pq_common.h"
+
+namespace pq {
+
+constexpr int kHafMaxModes = 48;   // distinct occupied modes
+constexpr int kHafMaxTime = 32;    // time digits
+constexpr int kHafMaxLane = 7;     // lane digits (six of radix >= 2 and a radix-1 fixed mode)
+constexpr int kHafMaxN = 64;       // vertices (photons)
+constexpr int kHafInner = 2048;    // inner (table-driven) Gray block
+constexpr uint64_t kHafMinChunk = 256;   // time states per wavefront, at least
+
+// One step of the inner Gray block: entry p (p >= 1) moves time digit t by
+// dx (-2 when its digit value rises, +2 when it falls) from position p - 1 to
+// p; w is the signed binomial weight of the inner digits at position p.
+struct HafStep {
+    int32_t t;
+    int32_t dx;
+    double w;
+};
+
+// Compact symmetric matrix and loop weights in digit order (lane digits
+// first, then time digits, inner ones first), from the upper triangle of A.
+struct HafPrepArgs {
+    const cplx* A;
+    int64_t lda;
+    const cplx* gamma;                // may be null (no loops)
+    int32_t k;
+    int32_t mode[kHafMaxModes];       // digit order -> mode of A
+    cplx* Ac;                         // [k][k]
+    cplx* gc;                         // [k]
+};
+
+struct HafArgs {
+    const cplx* Ac;                   // [k][k]
+    const cplx* gc;                   // [k]
+    const HafStep* tab;               // [2][M]: forward block, reflected block
+    double* partials;                 // [waves][4] double-double per wavefront
+    uint64_t time_states;
+    uint32_t waves;
+    int32_t k, nl, nt, n_in;          // modes, lane digits, time digits, inner time digits
+    int32_t lane_states;
+    int32_t M;                        // inner block length
+    int32_t N;
+    int32_t kpow;                     // N / 2 (no loops)
+    int8_t rad[kHafMaxModes];         // radix per digit
+    int8_t rep[kHafMaxModes];         // r per digit
+    double coef[kHafMaxN / 2 + 1];    // 1 / (j! (N - 2j)!) (loops)
+};
+
+hipError_t launch_haf_prep(const HafPrepArgs& a, hipStream_t s);
+// loops: P_N with gamma; otherwise (q/2)^{N/2}.  nl in 1..kHafMaxLane.
+hipError_t launch_haf(bool loops, int nl, const HafArgs& a, int grid, hipStream_t s);
+int occupancy_haf(bool loops, int nl);
+
+}  // namespace pq

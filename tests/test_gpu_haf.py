@@ -1,0 +1,179 @@
+"""Loop hafnian (pq_lhaf) on the GPU against the oracle: random repetition
+patterns at sizes the oracle's occupation table finishes in seconds, the
+paper's (2, ..., 2) repetitions up to 28 vertices, and at 40 vertices (the
+benchmark size) identities that hold at any size: the block-matrix hafnian
+equals a repeated permanent (oracle Ryser), the constant-matrix Hermite form,
+diagonal scaling and mode permutation."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def eng():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2403_04006_amd as pq
+    return pq.Engine(0)
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.complex128)).cuda()
+
+
+def tol(N):
+    # relative error bound of the FP64 sum (see the design notes): 1e-10 up
+    # to 20 vertices, 1e-8 up to 40
+    return 1e-10 if N <= 20 else 1e-8
+
+
+def rel(a, b):
+    return abs(a - b) / max(abs(b), 1e-300)
+
+
+def gpu_lhaf(eng, A, g, reps):
+    out = eng.lhaf(dev(A), None if g is None else dev(g), list(reps))
+    torch.cuda.synchronize()
+    return complex(out.cpu().numpy()[0])
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_lhaf_random_patterns_match_oracle(eng, seed):
+    rng = np.random.default_rng(500 + seed)
+    d = int(rng.integers(1, 13))
+    reps = rng.integers(0, 4, d)
+    while np.prod(reps + 1) > (1 << 21) or reps.sum() > 24:
+        reps[int(np.argmax(reps))] -= 1
+    A = workloads.symmetric_gaussian(d, seed) if seed % 2 else workloads.gbs_matrix(d, seed)
+    g = workloads.loop_vector(d, seed)
+    N = int(reps.sum())
+    for gamma in (g, None):
+        want = oracle.lhaf_rep(A, gamma, reps)
+        got = gpu_lhaf(eng, A, gamma, reps)
+        if gamma is None and N % 2:
+            assert got == 0
+            continue
+        assert rel(got, want) <= tol(N), (seed, list(reps), gamma is None)
+
+
+@pytest.mark.parametrize("d", [4, 8, 11, 12, 14])
+def test_repetitions_two_match_oracle(eng, d):
+    # the paper's (2, ..., 2) repetitions; d = 14 spans many wavefronts, inner
+    # blocks and reflected segments
+    A = workloads.gbs_matrix(d, d)
+    g = workloads.loop_vector(d, d)
+    reps = [2] * d
+    for gamma in (g, None):
+        want = oracle.lhaf_rep(A, gamma, reps)
+        got = gpu_lhaf(eng, A, gamma, reps)
+        assert rel(got, want) <= tol(2 * d), (d, gamma is None)
+
+
+@pytest.mark.parametrize("n", [1, 7, 12, 16, 20])
+def test_unit_repetitions_match_oracle(eng, n):
+    A = workloads.symmetric_gaussian(n, 40 + n)
+    g = workloads.loop_vector(n, 40 + n)
+    want = oracle.lhaf_rep(A, g, [1] * n)
+    assert rel(gpu_lhaf(eng, A, g, [1] * n), want) <= tol(n)
+
+
+def test_reads_upper_triangle_and_leading_dimension(eng):
+    # a non-symmetric matrix inside a wider buffer: the definition reads the
+    # pairs i <= k only
+    rng = np.random.default_rng(3)
+    d, D = 7, 11
+    big = rng.standard_normal((D, D)) + 1j * rng.standard_normal((D, D))
+    g = workloads.loop_vector(d, 3)
+    reps = [2, 0, 1, 3, 1, 2, 1]
+    want = oracle.lhaf_rep(big[:d, :d], g, reps)
+    out = eng.lhaf(dev(big)[:d, :d], dev(g), reps)
+    torch.cuda.synchronize()
+    assert rel(complex(out.cpu().numpy()[0]), want) <= 1e-10
+
+
+def test_block_matrix_is_repeated_permanent_at_40_vertices(eng):
+    # haf([[0, B], [B^T, 0]]) with repetitions (2, ..., 2): perm(B_{t,s}), t =
+    # s = (2, ..., 2) on a 10 x 10 block, by the oracle's Ryser sum and by the
+    # permanent engine
+    B = workloads.collision_free_block(10, 5) * 3.0
+    M = np.zeros((20, 20), np.complex128)
+    M[:10, 10:] = B
+    M[10:, :10] = B.T
+    s = np.full(10, 2, np.int32)
+    want = oracle.perm_mult(B, s, s)
+    got = gpu_lhaf(eng, M, None, [2] * 20)
+    assert rel(got, want) <= tol(40)
+    # zero loops take the loop path and change nothing
+    assert rel(gpu_lhaf(eng, M, np.zeros(20), [2] * 20), want) <= tol(40)
+    p, _ = eng.perm(dev(B), s, s)
+    torch.cuda.synchronize()
+    assert rel(got, complex(p.cpu().item())) <= tol(40)
+
+
+def test_constant_matrix_hermite_form_at_40_vertices(eng):
+    a, gv = 0.05 - 0.02j, 0.3 + 0.1j
+    d = 20
+    N = 2 * d
+    want = sum(math.factorial(N) / (math.factorial(j) * math.factorial(N - 2 * j) * 2 ** j) * a ** j * gv ** (N - 2 * j)
+               for j in range(N // 2 + 1))
+    got = gpu_lhaf(eng, np.full((d, d), a), np.full(d, gv), [2] * d)
+    assert rel(got, want) <= tol(N)
+    want_haf = math.factorial(N) / (math.factorial(N // 2) * 2 ** (N // 2)) * a ** (N // 2)
+    assert rel(gpu_lhaf(eng, np.full((d, d), a), None, [2] * d), want_haf) <= tol(N)
+
+
+@pytest.mark.parametrize("d", [16, 20])
+def test_scaling_and_permutation_at_full_size(eng, d):
+    rng = np.random.default_rng(d)
+    A = workloads.gbs_matrix(d, 7)
+    g = workloads.loop_vector(d, 7)
+    reps = np.full(d, 2)
+    base = gpu_lhaf(eng, A, g, reps)
+    D = np.exp(1j * rng.uniform(0, 2 * np.pi, d)) * rng.uniform(0.8, 1.25, d)
+    scaled = gpu_lhaf(eng, D[:, None] * A * D[None, :], D * g, reps)
+    assert rel(scaled, np.prod(D ** reps) * base) <= tol(2 * d)
+    p = rng.permutation(d)
+    assert rel(gpu_lhaf(eng, A[np.ix_(p, p)], g[p], reps[p]), base) <= tol(2 * d)
+
+
+def test_special_cases(eng):
+    A = workloads.gbs_matrix(5, 1)
+    g = workloads.loop_vector(5, 1)
+    assert gpu_lhaf(eng, A, g, [0] * 5) == 1
+    assert gpu_lhaf(eng, A, None, [0, 1, 0, 2, 0]) == 0
+    assert rel(gpu_lhaf(eng, A, g, [0, 0, 1, 0, 0]), g[2]) <= 1e-15
+    assert rel(gpu_lhaf(eng, A, None, [0, 0, 0, 2, 0]), A[3, 3]) <= 1e-15
+    assert rel(gpu_lhaf(eng, A, g, [1, 1, 0, 0, 0]), A[0, 1] + g[0] * g[1]) <= 1e-15
+
+
+def test_deterministic(eng):
+    A = workloads.gbs_matrix(16, 2)
+    g = workloads.loop_vector(16, 2)
+    a = eng.lhaf(dev(A), dev(g), [2] * 16)
+    b = eng.lhaf(dev(A), dev(g), [2] * 16)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_argument_errors(eng):
+    import paper_2403_04006_amd as pq
+    A = dev(workloads.gbs_matrix(4, 0))
+    with pytest.raises(pq.PqError):
+        eng.lhaf(A, None, [1, -1, 0, 0])
+    with pytest.raises(pq.PqError):
+        eng.lhaf(A, None, [30, 30, 4, 2])          # N > 64
+    big = dev(workloads.gbs_matrix(50, 0))
+    with pytest.raises(pq.PqError):
+        eng.lhaf(big, None, [1] * 50)              # more than 48 occupied modes
+    with pytest.raises(pq.PqError):
+        eng.lhaf(big, None, [1] * 40 + [0] * 10)   # 33 Gray-walked modes
+    with pytest.raises(ValueError):
+        eng.lhaf(A, None, [1, 1])
