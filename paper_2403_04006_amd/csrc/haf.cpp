@@ -201,7 +201,22 @@ int pq_lhaf(pq_ctx* ctx, const pq_c128* A, int64_t lda, int32_t d, const pq_c128
     a.lane_states = p.lane_states;
     a.M = p.M;
     a.N = N;
-    a.kpow = N / 2;
+    {
+        // square-and-multiply schedule of x^{N/2}
+        const int K = N / 2;
+        int top = 0;
+        while ((K >> (top + 1)) > 0) ++top;
+        int z = 0;
+        a.pw_nseg = 0;
+        for (int b = top - 1; b >= 0; --b) {
+            ++z;
+            if ((K >> b) & 1) {
+                a.pw_z[a.pw_nseg++] = z;
+                z = 0;
+            }
+        }
+        a.pw_tail = z;
+    }
     for (int i = 0; i < p.k; ++i) {
         a.rad[i] = (int8_t)p.rad[i];
         a.rep[i] = (int8_t)p.rep[i];

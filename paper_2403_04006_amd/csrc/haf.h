@@ -73,7 +73,11 @@ struct HafArgs {
     int32_t lane_states;
     int32_t M;                        // inner block length
     int32_t N;
-    int32_t kpow;                     // N / 2 (no loops)
+    // x^{N/2} (no loops): for each set bit of N/2 below the top one, pw_z[i]
+    // squarings then a multiply by x; pw_tail squarings at the end
+    int32_t pw_nseg;
+    int32_t pw_tail;
+    int32_t pw_z[8];
     int8_t rad[kHafMaxModes];         // radix per digit
     int8_t rep[kHafMaxModes];         // r per digit
     double coef[kHafMaxN / 2 + 1];    // 1 / (j! (N - 2j)!) (loops)

@@ -91,30 +91,41 @@ __global__ __launch_bounds__(kBlock) void haf_kernel(const HafArgs a) {
 
     const int N = a.N;
     const int J = N >> 1;
-    const int K = a.kpow;
-    const int hb = K > 0 ? 31 - __builtin_clz((unsigned)K) : 0;
     cplx acc{0.0, 0.0};
     // acc += w P_N(x, l), x = q / 2 (the 1 / (N/2)! of the loop-free case is
     // applied once at the end)
     auto term = [&](const cplx& x, const cplx& l, double w) {
         cplx p;
         if constexpr (LOOP) {
+            // s_j = s_{j-1} y + c_j x^j = sum_{i<=j} c_i x^i y^{j-i}, y = l^2;
+            // two steps per trip, x^j always advanced (no selects)
             const cplx y = cmul(l, l);
             cplx s{a.coef[0], 0.0};
             cplx xp = x;
-            for (int j = 1; j <= J; ++j) {
+            int j = 1;
+            for (; j < J; j += 2) {
                 s = cmul(s, y);
                 cfma_to(s, a.coef[j], xp);
-                if (j < J) xp = cmul(xp, x);
+                xp = cmul(xp, x);
+                s = cmul(s, y);
+                cfma_to(s, a.coef[j + 1], xp);
+                xp = cmul(xp, x);
+            }
+            if (j == J) {
+                s = cmul(s, y);
+                cfma_to(s, a.coef[j], xp);
             }
             if (N & 1) s = cmul(s, l);
             p = s;
         } else {
+            // x^K by uniform loops: per set bit below the top one, z squarings
+            // then one multiply by x; the trailing squarings last
             p = x;
-            for (int b = hb - 1; b >= 0; --b) {
-                p = cmul(p, p);
-                if ((K >> b) & 1) p = cmul(p, x);
+            for (int i = 0; i < a.pw_nseg; ++i) {
+                for (int z = 0; z < a.pw_z[i]; ++z) p = cmul(p, p);
+                p = cmul(p, x);
             }
+            for (int z = 0; z < a.pw_tail; ++z) p = cmul(p, p);
         }
         cfma_to(acc, w, p);
     };
