@@ -567,3 +567,37 @@ def test_lhaf_rep_loops_only_and_no_loops():
     assert oracle.lhaf_rep(A, np.zeros(d), reps) == oracle.lhaf_rep(A, None, reps)
     assert oracle.lhaf_rep(A, None, [1, 0, 0, 0, 0]) == 0
     assert oracle.lhaf_rep(A, g, [0] * d) == 1
+
+
+def squeezed_shells(r, nmax):
+    # total photon number of independent squeezed vacua: mode i holds 2k
+    # photons with probability (2k)! / (2^k k!)^2 tanh^(2k) r_i / cosh r_i; a
+    # passive interferometer keeps the total
+    dist = np.zeros(nmax + 1)
+    dist[0] = 1.0
+    for ri in r:
+        single = np.zeros(nmax + 1)
+        for k in range(nmax // 2 + 1):
+            single[2 * k] = math.factorial(2 * k) / (2 ** k * math.factorial(k)) ** 2 * np.tanh(ri) ** (2 * k) / np.cosh(ri)
+        dist = np.convolve(dist, single)[:nmax + 1]
+    return dist
+
+
+def test_gbs_photon_shells_match_squeezed_statistics():
+    # squeezed vacua through a Haar interferometer: p(t) = |haf(B_t)|^2 /
+    # (prod t! prod cosh r) with B = U diag(tanh r) U^T (Gaussian Boson
+    # Sampling appendix, pure state, no displacement); every output with two
+    # photons in one mode needs the pair weight B_ii between its copies
+    import itertools
+    d = 3
+    r = np.array([0.5, 0.3, 0.4])
+    U = workloads.haar(d, 3)
+    B = (U * np.tanh(r)) @ U.T
+    want = squeezed_shells(r, 12)
+    for N in range(0, 13):
+        shell = 0.0
+        for t in itertools.product(range(N + 1), repeat=d):
+            if sum(t) == N:
+                h = oracle.lhaf_rep(B, None, list(t))
+                shell += abs(h) ** 2 / (math.prod(math.factorial(x) for x in t) * np.prod(np.cosh(r)))
+        assert abs(shell - want[N]) <= 1e-15 + 1e-13 * want[N], N
