@@ -247,8 +247,8 @@ int pq_loss_dilation(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m, cons
  *   out    device, 1 complex, written.
  * N == 0 writes 1; without loops an odd N writes 0.  Limits (PQ_ERANGE):
  * N <= 64, at most 48 modes with reps > 0, at most 32 of them beyond the
- * lane digits (for (2, ..., 2) repetitions: 36 modes), at most 2^52 time
- * states.  Negative reps, NULL out/reps, or NULL A / lda < d with N > 0 give
+ * lane digits and the one register digit (for (2, ..., 2) repetitions: 37
+ * modes), at most 2^52 time states.  Negative reps, NULL out/reps, or NULL A / lda < d with N > 0 give
  * PQ_EINVAL.
  */
 int pq_lhaf(pq_ctx* ctx, const pq_c128* A, int64_t lda, int32_t d, const pq_c128* gamma,

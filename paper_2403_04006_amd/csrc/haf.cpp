@@ -18,6 +18,7 @@ namespace {
 
 struct HafPlan {
     int k = 0, nl = 0, nt = 0, n_in = 0, N = 0;
+    int rr = 1, to = 0;   // register digit radix (1: none); first time digit
     int lane_states = 1, M = 1;
     uint64_t time_states = 1;
     int mode[kHafMaxModes];
@@ -27,9 +28,11 @@ struct HafPlan {
 
 // Digits: the fixed mode (smallest r, first of equals) has radix r, every
 // other occupied mode r + 1.  Lane digits: radix-1 digits, then the largest
-// radices while the product stays <= 64 (at most six of radix >= 2); time
-// digits: the rest in mode order, the inner block the leading ones whose
-// product stays <= kHafInner.
+// radices while the product stays <= 64 (at most six of radix >= 2).  The
+// register digit: the first remaining digit of radix 3, else of radix 2.
+// Time digits: the rest in mode order, the inner block the leading ones
+// whose product stays <= kHafInner.  Digit order: lane digits, the register
+// digit, time digits.
 int plan_haf(const int32_t* reps, int d, HafPlan& p, const char** why) {
     int modes[kHafMaxModes], r[kHafMaxModes], k = 0, N = 0;
     for (int i = 0; i < d; ++i) {
@@ -69,24 +72,31 @@ int plan_haf(const int32_t* reps, int d, HafPlan& p, const char** why) {
         }
     }
     if (nl > kHafMaxLane) { *why = "lane digits"; return PQ_ERANGE; }
+    int reg = -1;
+    for (int want = 3; want >= 2 && reg < 0; --want)
+        for (int i = 0; i < k && reg < 0; ++i)
+            if (!is_lane[i] && rho[i] == want) reg = i;
     int q = 0;
     for (int i = 0; i < k; ++i)
         if (is_lane[i]) { p.mode[q] = modes[i]; p.rad[q] = rho[i]; p.rep[q] = r[i]; ++q; }
+    if (reg >= 0) { p.mode[q] = modes[reg]; p.rad[q] = rho[reg]; p.rep[q] = r[reg]; ++q; }
     for (int i = 0; i < k; ++i)
-        if (!is_lane[i]) { p.mode[q] = modes[i]; p.rad[q] = rho[i]; p.rep[q] = r[i]; ++q; }
+        if (!is_lane[i] && i != reg) { p.mode[q] = modes[i]; p.rad[q] = rho[i]; p.rep[q] = r[i]; ++q; }
     p.nl = nl;
-    p.nt = k - nl;
+    p.rr = reg >= 0 ? rho[reg] : 1;
+    p.to = nl + (reg >= 0 ? 1 : 0);
+    p.nt = k - p.to;
     if (p.nt > kHafMaxTime) { *why = "more than 32 Gray-walked modes"; return PQ_ERANGE; }
     p.lane_states = lane_prod;
     uint64_t ts = 1;
     for (int t = 0; t < p.nt; ++t) {
-        const uint64_t rr = (uint64_t)p.rad[nl + t];
+        const uint64_t rr = (uint64_t)p.rad[p.to + t];
         if (ts > ((uint64_t)1 << 52) / rr) { *why = "more than 2^52 Gray terms"; return PQ_ERANGE; }
         ts *= rr;
     }
     p.time_states = ts;
     int M = 1, n_in = 0;
-    while (n_in < p.nt && M * p.rad[nl + n_in] <= kHafInner) M *= p.rad[nl + n_in++];
+    while (n_in < p.nt && M * p.rad[p.to + n_in] <= kHafInner) M *= p.rad[p.to + n_in++];
     p.M = M;
     p.n_in = n_in;
     return PQ_OK;
@@ -96,7 +106,7 @@ int plan_haf(const int32_t* reps, int d, HafPlan& p, const char** why) {
 // reflected positions are ranks M-1..0.
 void haf_tables(const HafPlan& p, std::vector<HafStep>& tab) {
     const int M = p.M, n_in = p.n_in;
-    auto rad = [&](int i) { return p.rad[p.nl + i]; };
+    auto rad = [&](int i) { return p.rad[p.to + i]; };
     std::vector<int> prev(n_in > 0 ? n_in : 1, 0), cur(n_in > 0 ? n_in : 1, 0);
     tab.assign((size_t)2 * M, HafStep{0, 0, 0.0});
     for (int r = 0; r < M; ++r) {
@@ -137,6 +147,7 @@ int pq_lhaf(pq_ctx* ctx, const pq_c128* A, int64_t lda, int32_t d, const pq_c128
     int N = 0;
     for (int i = 0; i < d; ++i) {
         if (reps[i] < 0) return ctx->fail(PQ_EINVAL, "pq_lhaf: negative repetition");
+        if (reps[i] > kHafMaxN) return ctx->fail(PQ_ERANGE, "pq_lhaf: more than %d vertices", kHafMaxN);
         N += reps[i];
         if (N > kHafMaxN) return ctx->fail(PQ_ERANGE, "pq_lhaf: more than %d vertices", kHafMaxN);
     }
@@ -153,7 +164,7 @@ int pq_lhaf(pq_ctx* ctx, const pq_c128* A, int64_t lda, int32_t d, const pq_c128
     std::vector<HafStep> tab;
     haf_tables(p, tab);
 
-    const int occ = occupancy_haf(loops, p.nl);
+    const int occ = occupancy_haf(loops, p.nl, p.rr);
     if (occ <= 0) return ctx->fail(PQ_EDEVICE, "pq_lhaf: occupancy query failed");
     const uint64_t max_waves = (uint64_t)ctx->num_cu * (uint64_t)occ * kWavesPerBlock;
     uint64_t waves = (p.time_states + kHafMinChunk - 1) / kHafMinChunk;
@@ -196,6 +207,7 @@ int pq_lhaf(pq_ctx* ctx, const pq_c128* A, int64_t lda, int32_t d, const pq_c128
     a.waves = (uint32_t)waves;
     a.k = p.k;
     a.nl = p.nl;
+    a.rr = p.rr;
     a.nt = p.nt;
     a.n_in = p.n_in;
     a.lane_states = p.lane_states;
@@ -208,10 +220,11 @@ int pq_lhaf(pq_ctx* ctx, const pq_c128* A, int64_t lda, int32_t d, const pq_c128
         while ((K >> (top + 1)) > 0) ++top;
         int z = 0;
         a.pw_nseg = 0;
+        a.pw_pack = 0;
         for (int b = top - 1; b >= 0; --b) {
             ++z;
             if ((K >> b) & 1) {
-                a.pw_z[a.pw_nseg++] = z;
+                a.pw_pack |= (uint32_t)z << (4 * a.pw_nseg++);
                 z = 0;
             }
         }
@@ -234,7 +247,7 @@ int pq_lhaf(pq_ctx* ctx, const pq_c128* A, int64_t lda, int32_t d, const pq_c128
         rc = ctx->check(hipEventRecord(e0, st), "profile: record");
         if (rc) return rc;
     }
-    rc = ctx->check(launch_haf(loops, p.nl, a, grid, st), "hafnian sweep");
+    rc = ctx->check(launch_haf(loops, p.nl, p.rr, a, grid, st), "hafnian sweep");
     if (rc) return rc;
     if (ctx->profiling) {
         rc = ctx->check(hipEventRecord(e1, st), "profile: record");

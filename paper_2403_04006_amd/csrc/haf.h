@@ -17,8 +17,10 @@
 // the digit structure of the generalised permanent sum.  Without loops
 // P_N = (q/2)^{N/2} / (N/2)! (zero for odd N).
 //
-// Work split: lane digits (product of radices <= 64) are fixed per lane; the
-// other ("time") digits walk a reflected Gray code shared by the wavefront.
+// Work split: lane digits (product of radices <= 64) are fixed per lane; a
+// register digit of radix 2 or 3 (if one is left) is evaluated at all its
+// values in every lane at every step; the other ("time") digits walk a
+// reflected Gray code shared by the wavefront.
 // When time digit t moves by dX = -+2 (d_t up / down), with v = A X before
 // the move,
 //   q += 2 dX v_t + dX^2 A_tt,   l += dX gamma_t,   v += dX A[:, t].
@@ -70,22 +72,25 @@ struct HafArgs {
     uint64_t time_states;
     uint32_t waves;
     int32_t k, nl, nt, n_in;          // modes, lane digits, time digits, inner time digits
+    int32_t rr;                       // radix of the register digit (digit nl), 1: none
     int32_t lane_states;
     int32_t M;                        // inner block length
     int32_t N;
-    // x^{N/2} (no loops): for each set bit of N/2 below the top one, pw_z[i]
-    // squarings then a multiply by x; pw_tail squarings at the end
+    // x^{N/2} (no loops): for each set bit of N/2 below the top one (pw_nseg
+    // of them), bits 4i..4i+3 of pw_pack squarings then a multiply by x;
+    // pw_tail squarings at the end
     int32_t pw_nseg;
     int32_t pw_tail;
-    int32_t pw_z[8];
+    uint32_t pw_pack;
     int8_t rad[kHafMaxModes];         // radix per digit
     int8_t rep[kHafMaxModes];         // r per digit
     double coef[kHafMaxN / 2 + 1];    // 1 / (j! (N - 2j)!) (loops)
 };
 
 hipError_t launch_haf_prep(const HafPrepArgs& a, hipStream_t s);
-// loops: P_N with gamma; otherwise (q/2)^{N/2}.  nl in 1..kHafMaxLane.
-hipError_t launch_haf(bool loops, int nl, const HafArgs& a, int grid, hipStream_t s);
-int occupancy_haf(bool loops, int nl);
+// loops: P_N with gamma; otherwise (q/2)^{N/2}.  nl in 1..kHafMaxLane,
+// rr in 1..3.
+hipError_t launch_haf(bool loops, int nl, int rr, const HafArgs& a, int grid, hipStream_t s);
+int occupancy_haf(bool loops, int nl, int rr);
 
 }  // namespace pq

@@ -34,10 +34,20 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+// (a + ib)^2 in place: 4 FP64 instructions, no copies
+__device__ __forceinline__ void csqr(cplx& p) {
+    const double t = p.im * p.im;
+    const double s = p.re + p.re;
+    p.im = s * p.im;
+    p.re = __builtin_fma(p.re, p.re, -t);
+}
+
 // One wavefront sweeps [start, start + count) of the time states; lanes hold
-// the lane digits.  NL: lane digits; LOOP: loop weights present.
-template <int NL, bool LOOP>
+// the lane digits.  NL: lane digits; RR: radix of the register digit (1: none)
+// whose RR values every lane evaluates at each step; LOOP: loop weights.
+template <int NL, int RR, bool LOOP>
 __global__ __launch_bounds__(kBlock) void haf_kernel(const HafArgs a) {
+    constexpr int TO = NL + (RR > 1 ? 1 : 0);   // first time digit
     // sTT[t][s] = A[time s][time t]: lane s adds dX times it to T_s when
     // time digit t moves
     __shared__ cplx sTT[kHafMaxTime][kHafMaxTime];
@@ -45,7 +55,7 @@ __global__ __launch_bounds__(kBlock) void haf_kernel(const HafArgs a) {
     for (int e = (int)threadIdx.x; e < kHafMaxTime * kHafMaxTime; e += kBlock) {
         const int t = e / kHafMaxTime, s = e - t * kHafMaxTime;
         cplx v{0.0, 0.0};
-        if (t < nt && s < nt) v = a.Ac[(size_t)(NL + s) * (size_t)k + (NL + t)];
+        if (t < nt && s < nt) v = a.Ac[(size_t)(TO + s) * (size_t)k + (TO + t)];
         sTT[t][s] = v;
     }
     __syncthreads();
@@ -70,64 +80,120 @@ __global__ __launch_bounds__(kBlock) void haf_kernel(const HafArgs a) {
             wl *= digit_weight(rho, d);
         }
     }
-    // L_t: the lane digits' part of v_t = (A X)_t for time digit t
-    auto lane_part = [&](int t) {
-        const cplx* row = a.Ac + (size_t)(NL + t) * (size_t)k;
+    // sum over lane digits j of A[row][j] X_j
+    auto lane_dot = [&](int row) {
+        const cplx* r = a.Ac + (size_t)row * (size_t)k;
         cplx L{0.0, 0.0};
 #pragma unroll
-        for (int j = 0; j < NL; ++j) cfma_to(L, XL[j], row[j]);
+        for (int j = 0; j < NL; ++j) cfma_to(L, XL[j], r[j]);
         return L;
     };
     // lane-only parts of q and l
     cplx qLL{0.0, 0.0}, lL{0.0, 0.0};
 #pragma unroll
     for (int i = 0; i < NL; ++i) {
-        cplx r{0.0, 0.0};
-#pragma unroll
-        for (int j = 0; j < NL; ++j) cfma_to(r, XL[j], a.Ac[(size_t)i * (size_t)k + j]);
-        cfma_to(qLL, XL[i], r);
+        cfma_to(qLL, XL[i], lane_dot(i));
         cfma_to(lL, XL[i], a.gc[i]);
+    }
+    // register digit: values X_d = r - 2d, weights, and the constant parts
+    // (X_d^2 / 2) A_rr of x and X_d gamma_r of l
+    double XR[RR], WR[RR];
+    cplx cR[RR];
+    cplx uL{0.0, 0.0}, gR{0.0, 0.0};
+    if constexpr (RR > 1) {
+        const cplx arr = a.Ac[(size_t)NL * (size_t)k + NL];
+        gR = a.gc[NL];
+        uL = lane_dot(NL);
+#pragma unroll
+        for (int d = 0; d < RR; ++d) {
+            XR[d] = (double)(a.rep[NL] - 2 * d);
+            WR[d] = digit_weight(RR, d);
+            const double h = 0.5 * XR[d] * XR[d];
+            cR[d] = cplx{h * arr.re, h * arr.im};
+        }
+    } else {
+        XR[0] = 0.0;
+        WR[0] = 1.0;
+        cR[0] = cplx{0.0, 0.0};
     }
 
     const int N = a.N;
     const int J = N >> 1;
     cplx acc{0.0, 0.0};
-    // acc += w P_N(x, l), x = q / 2 (the 1 / (N/2)! of the loop-free case is
-    // applied once at the end)
-    auto term = [&](const cplx& x, const cplx& l, double w) {
-        cplx p;
+    // acc += w sum_d WR[d] P_N(x_d, l_d) with x_d = x + X_d u + (X_d^2/2) A_rr
+    // and l_d = l + X_d gamma_r, x = q / 2 over the other digits, u = (A X)_r
+    // (the 1 / (N/2)! of the loop-free case is applied once at the end).  The
+    // RR evaluations share every loop and coefficient load.
+    auto terms = [&](const cplx& x, const cplx& l, const cplx& u, double w) {
+        cplx xd[RR], p[RR];
+#pragma unroll
+        for (int d = 0; d < RR; ++d) {
+            xd[d].re = __builtin_fma(XR[d], u.re, x.re + cR[d].re);
+            xd[d].im = __builtin_fma(XR[d], u.im, x.im + cR[d].im);
+        }
         if constexpr (LOOP) {
             // s_j = s_{j-1} y + c_j x^j = sum_{i<=j} c_i x^i y^{j-i}, y = l^2;
             // two steps per trip, x^j always advanced (no selects)
-            const cplx y = cmul(l, l);
-            cplx s{a.coef[0], 0.0};
-            cplx xp = x;
+            cplx ld[RR], y[RR], xp[RR];
+#pragma unroll
+            for (int d = 0; d < RR; ++d) {
+                ld[d].re = __builtin_fma(XR[d], gR.re, l.re);
+                ld[d].im = __builtin_fma(XR[d], gR.im, l.im);
+                y[d] = cmul(ld[d], ld[d]);
+                p[d] = cplx{a.coef[0], 0.0};
+                xp[d] = xd[d];
+            }
             int j = 1;
             for (; j < J; j += 2) {
-                s = cmul(s, y);
-                cfma_to(s, a.coef[j], xp);
-                xp = cmul(xp, x);
-                s = cmul(s, y);
-                cfma_to(s, a.coef[j + 1], xp);
-                xp = cmul(xp, x);
+                const double c1 = a.coef[j], c2 = a.coef[j + 1];
+#pragma unroll
+                for (int d = 0; d < RR; ++d) {
+                    p[d] = cmul(p[d], y[d]);
+                    cfma_to(p[d], c1, xp[d]);
+                    xp[d] = cmul(xp[d], xd[d]);
+                    p[d] = cmul(p[d], y[d]);
+                    cfma_to(p[d], c2, xp[d]);
+                    xp[d] = cmul(xp[d], xd[d]);
+                }
             }
             if (j == J) {
-                s = cmul(s, y);
-                cfma_to(s, a.coef[j], xp);
+                const double c1 = a.coef[j];
+#pragma unroll
+                for (int d = 0; d < RR; ++d) {
+                    p[d] = cmul(p[d], y[d]);
+                    cfma_to(p[d], c1, xp[d]);
+                }
             }
-            if (N & 1) s = cmul(s, l);
-            p = s;
+            if (N & 1) {
+#pragma unroll
+                for (int d = 0; d < RR; ++d) p[d] = cmul(p[d], ld[d]);
+            }
         } else {
             // x^K by uniform loops: per set bit below the top one, z squarings
-            // then one multiply by x; the trailing squarings last
-            p = x;
+            // (4 bits each of pw_pack) then one multiply by x; the trailing
+            // squarings last
+#pragma unroll
+            for (int d = 0; d < RR; ++d) p[d] = xd[d];
+            uint32_t pk = (uint32_t)a.pw_pack;
             for (int i = 0; i < a.pw_nseg; ++i) {
-                for (int z = 0; z < a.pw_z[i]; ++z) p = cmul(p, p);
-                p = cmul(p, x);
+                const int z = (int)(pk & 15u);
+                pk >>= 4;
+                for (int q = 0; q < z; ++q) {
+#pragma unroll
+                    for (int d = 0; d < RR; ++d) csqr(p[d]);
+                }
+#pragma unroll
+                for (int d = 0; d < RR; ++d) p[d] = cmul(p[d], xd[d]);
             }
-            for (int z = 0; z < a.pw_tail; ++z) p = cmul(p, p);
+            for (int q = 0; q < a.pw_tail; ++q) {
+#pragma unroll
+                for (int d = 0; d < RR; ++d) csqr(p[d]);
+            }
         }
-        cfma_to(acc, w, p);
+        cplx in{0.0, 0.0};
+#pragma unroll
+        for (int d = 0; d < RR; ++d) cfma_to(in, WR[d], p[d]);
+        cfma_to(acc, w, in);
     };
 
     const int M = a.M;
@@ -142,24 +208,25 @@ __global__ __launch_bounds__(kBlock) void haf_kernel(const HafArgs a) {
         // state at time rank s: high digits from the segment index, inner
         // digits from the block position (reflected when the high digits'
         // sum is odd)
-        cplx T{0.0, 0.0}, qLT{0.0, 0.0}, lT{0.0, 0.0};
+        cplx T{0.0, 0.0}, qLT{0.0, 0.0}, lT{0.0, 0.0}, U{0.0, 0.0};
         double xm = 0.0;
         auto add_digit = [&](int t, int g) {
-            const double X = (double)(a.rep[NL + t] - 2 * g);
+            const double X = (double)(a.rep[TO + t] - 2 * g);
             cfma_to(T, X, sTT[t][sl]);
-            cfma_to(qLT, X, lane_part(t));
-            cfma_to(lT, X, a.gc[NL + t]);
+            cfma_to(qLT, X, lane_dot(TO + t));
+            cfma_to(lT, X, a.gc[TO + t]);
+            if constexpr (RR > 1) cfma_to(U, X, a.Ac[(size_t)(TO + t) * (size_t)k + NL]);
             if (t == lane) xm = X;
         };
         double wh = 1.0;
-        int refl = gray_digits_desc(n_hi, [&](int i) { return (int)a.rad[NL + n_in + i]; }, hi, 0, [&](int i, int g) {
-            wh *= digit_weight((int)a.rad[NL + n_in + i], g);
+        int refl = gray_digits_desc(n_hi, [&](int i) { return (int)a.rad[TO + n_in + i]; }, hi, 0, [&](int i, int g) {
+            wh *= digit_weight((int)a.rad[TO + n_in + i], g);
             add_digit(n_in + i, g);
         });
         refl = uniform_int(refl);
         wh = uniform_double(wh);
         const int q0 = refl ? M - 1 - pos0 : pos0;
-        gray_digits_desc(n_in, [&](int i) { return (int)a.rad[NL + i]; }, (uint64_t)q0, 0,
+        gray_digits_desc(n_in, [&](int i) { return (int)a.rad[TO + i]; }, (uint64_t)q0, 0,
                          [&](int i, int g) { add_digit(i, g); });
         // X_time^T A X_time = sum over lanes s < nt of X_s T_s (every lane
         // ends with the same sum: each butterfly level adds the same pair)
@@ -172,22 +239,24 @@ __global__ __launch_bounds__(kBlock) void haf_kernel(const HafArgs a) {
         cplx x{0.5 * (qLL.re + 2.0 * qLT.re + tt.re), 0.5 * (qLL.im + 2.0 * qLT.im + tt.im)};
         cplx l{lL.re + lT.re, lL.im + lT.im};
         const HafStep* tab = refl ? a.tab + M : a.tab;
-        term(x, l, wh * tab[pos0].w);
+        terms(x, l, cplx{uL.re + U.re, uL.im + U.im}, wh * tab[pos0].w);
         for (int p = pos0 + 1; p < pos0 + len; ++p) {
             const HafStep e = tab[p];
             const int t = e.t;
             const double dx = (double)e.dx;
+            const cplx* row = a.Ac + (size_t)(TO + t) * (size_t)k;
             // v_t before the move: lane part + T_t (held by lane t)
-            const cplx L = lane_part(t);
+            const cplx L = lane_dot(TO + t);
             const double vre = L.re + readlane_d(T.re, t);
             const double vim = L.im + readlane_d(T.im, t);
-            const cplx att = a.Ac[(size_t)(NL + t) * (size_t)k + (NL + t)];
+            const cplx att = row[TO + t];
             // x = q / 2 += dX v_t + (dX^2 / 2) A_tt, dX^2 / 2 = 2
             x.re = __builtin_fma(dx, vre, __builtin_fma(2.0, att.re, x.re));
             x.im = __builtin_fma(dx, vim, __builtin_fma(2.0, att.im, x.im));
-            if constexpr (LOOP) cfma_to(l, dx, a.gc[NL + t]);
+            if constexpr (RR > 1) cfma_to(U, dx, row[NL]);
+            if constexpr (LOOP) cfma_to(l, dx, a.gc[TO + t]);
             cfma_to(T, dx, sTT[t][sl]);
-            term(x, l, wh * e.w);
+            terms(x, l, cplx{uL.re + U.re, uL.im + U.im}, wh * e.w);
         }
         s = seg_end;
     }
@@ -210,12 +279,28 @@ hipError_t launch_haf_prep(const HafPrepArgs& a, hipStream_t s) {
 
 #define PQ_HAF_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7)
 
-hipError_t launch_haf(bool loops, int nl, const HafArgs& a, int grid, hipStream_t s) {
-    const dim3 g((unsigned)(grid > 0 ? grid : 1)), b(kBlock);
-#define PQ_HAF_LAUNCH(NL)                                                              \
-    case NL:                                                                           \
-        if (loops) hipLaunchKernelGGL((haf_kernel<NL, true>), g, b, 0, s, a);          \
-        else hipLaunchKernelGGL((haf_kernel<NL, false>), g, b, 0, s, a);               \
+template <int NL, int RR>
+static void launch_haf_nr(bool loops, const HafArgs& a, dim3 g, hipStream_t s) {
+    if (loops) hipLaunchKernelGGL((haf_kernel<NL, RR, true>), g, dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((haf_kernel<NL, RR, false>), g, dim3(kBlock), 0, s, a);
+}
+
+template <int NL, int RR>
+static int occupancy_haf_nr(bool loops) {
+    int nb = 0;
+    const hipError_t e = loops ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, haf_kernel<NL, RR, true>, kBlock, 0)
+                               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, haf_kernel<NL, RR, false>, kBlock, 0);
+    return e == hipSuccess ? nb : 0;
+}
+
+hipError_t launch_haf(bool loops, int nl, int rr, const HafArgs& a, int grid, hipStream_t s) {
+    const dim3 g((unsigned)(grid > 0 ? grid : 1));
+    if (rr < 1 || rr > 3) return hipErrorInvalidValue;
+#define PQ_HAF_LAUNCH(NL)                                          \
+    case NL:                                                       \
+        if (rr == 1) launch_haf_nr<NL, 1>(loops, a, g, s);         \
+        else if (rr == 2) launch_haf_nr<NL, 2>(loops, a, g, s);    \
+        else launch_haf_nr<NL, 3>(loops, a, g, s);                 \
         break;
     switch (nl) {
         PQ_HAF_CASES(PQ_HAF_LAUNCH)
@@ -225,20 +310,17 @@ hipError_t launch_haf(bool loops, int nl, const HafArgs& a, int grid, hipStream_
     return hipGetLastError();
 }
 
-int occupancy_haf(bool loops, int nl) {
-    int nb = 0;
-    hipError_t e = hipErrorInvalidValue;
-#define PQ_HAF_OCC(NL)                                                                                           \
-    case NL:                                                                                                     \
-        e = loops ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, haf_kernel<NL, true>, kBlock, 0)         \
-                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, haf_kernel<NL, false>, kBlock, 0);       \
-        break;
+int occupancy_haf(bool loops, int nl, int rr) {
+    if (rr < 1 || rr > 3) return 0;
+#define PQ_HAF_OCC(NL)                                                                  \
+    case NL:                                                                            \
+        return rr == 1 ? occupancy_haf_nr<NL, 1>(loops)                                 \
+                       : (rr == 2 ? occupancy_haf_nr<NL, 2>(loops) : occupancy_haf_nr<NL, 3>(loops));
     switch (nl) {
         PQ_HAF_CASES(PQ_HAF_OCC)
-        default: break;
+        default: return 0;
     }
 #undef PQ_HAF_OCC
-    return e == hipSuccess ? nb : 0;
 }
 
 }  // namespace pq

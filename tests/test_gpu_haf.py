@@ -170,10 +170,39 @@ def test_argument_errors(eng):
         eng.lhaf(A, None, [1, -1, 0, 0])
     with pytest.raises(pq.PqError):
         eng.lhaf(A, None, [30, 30, 4, 2])          # N > 64
+    with pytest.raises(pq.PqError):
+        eng.lhaf(A, None, [2 ** 31 - 1, 1, 0, 0])  # no overflow in the vertex count
     big = dev(workloads.gbs_matrix(50, 0))
     with pytest.raises(pq.PqError):
         eng.lhaf(big, None, [1] * 50)              # more than 48 occupied modes
     with pytest.raises(pq.PqError):
-        eng.lhaf(big, None, [1] * 40 + [0] * 10)   # 33 Gray-walked modes
+        eng.lhaf(big, None, [1] * 42 + [0] * 8)    # 34 Gray-walked modes (N even)
     with pytest.raises(ValueError):
         eng.lhaf(A, None, [1, 1])
+
+
+def test_gbs_photon_shells_match_squeezed_statistics(eng):
+    # squeezed vacua through a Haar interferometer: p(t) = |haf(B_t)|^2 /
+    # (prod t! prod cosh r), B = U diag(tanh r) U^T; a passive interferometer
+    # keeps the total photon number, so each shell sum equals the convolution
+    # of the single-mode squeezed distributions
+    import itertools
+    d = 4
+    r = np.array([0.5, 0.3, 0.4, 0.6])
+    U = workloads.haar(d, 4)
+    B = (U * np.tanh(r)) @ U.T
+    Bd = dev(B)
+    nmax = 14
+    want = np.zeros(nmax + 1)
+    want[0] = 1.0
+    for ri in r:
+        single = np.zeros(nmax + 1)
+        for k in range(nmax // 2 + 1):
+            single[2 * k] = math.factorial(2 * k) / (2 ** k * math.factorial(k)) ** 2 * np.tanh(ri) ** (2 * k) / np.cosh(ri)
+        want = np.convolve(want, single)[:nmax + 1]
+    for N in range(0, nmax + 1, 2):
+        pats = [t for t in itertools.product(range(N + 1), repeat=d) if sum(t) == N]
+        outs = torch.cat([eng.lhaf(Bd, None, list(t)) for t in pats]).cpu().numpy()
+        fact = np.array([math.prod(math.factorial(x) for x in t) for t in pats], dtype=np.float64)
+        shell = float(np.sum(np.abs(outs) ** 2 / fact)) / float(np.prod(np.cosh(r)))
+        assert abs(shell - want[N]) <= 1e-15 + 1e-12 * want[N], (N, shell, want[N])
