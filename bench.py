@@ -266,6 +266,31 @@ def main() -> int:
         batched["sampling_replay"] = {
             "samples": 1000, "jobs": len(jl), "sweep_ms": ms / 3, "wall_ms": tw * 1e3,
             "samples_per_s": 1000 / tw}
+        # the same two workloads with chunk sizes picked by the autotuner: the
+        # first call times 8 candidate policies, then 3 calls of the kept plan
+        teng = pq.Engine(0)
+        teng.autotune(True)
+        tuned_runs = {}
+        for name, fn in (("repeated_40_photons", lambda: teng.perm_patterns(U20, ps)),
+                         ("sampling_replay", lambda: teng.perm_many(U400, js, with_amp=False))):
+            fn()
+            torch.cuda.synchronize()
+            info = teng.autotune_last()
+            teng.profile(True)
+            teng.profile_read()
+            tw = time.perf_counter()
+            for _ in range(3):
+                fn()
+            torch.cuda.synchronize()
+            tw = (time.perf_counter() - tw) / 3
+            nl, ms = teng.profile_read()
+            teng.profile(False)
+            tuned_runs[name] = {
+                "policy": [info["waves_per_cu"], info["chunks_per_wave"], info["min_chunk"]],
+                "candidates": info["candidates"], "tuning_best_ms": info["best_ms"],
+                "tuning_default_ms": info["default_ms"], "sweep_ms": ms / 3, "wall_ms": tw * 1e3}
+        teng.close()
+        batched["autotuned"] = tuned_runs
         # the same sampling runs drawn entirely on the device (the chain rule
         # with uniforms and input orders as inputs)
         rng_s = np.random.default_rng(1)

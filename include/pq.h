@@ -147,6 +147,34 @@ int pq_perm_many(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m,
                  pq_c128* perm, pq_c128* amp, void* stream);
 
 /*
+ * Chunk-size autotuning of pq_perm_many (the batched form: uneven jobs of a
+ * boson-sampling run in one statically scheduled launch per column class).
+ * A plan aims at num_cu * waves_per_cu * chunks_per_wave chunks per class,
+ * none shorter than min_chunk Gray time states; the default policy is
+ * (8, 2, 64).
+ *
+ * pq_autotune_enable -- on (nonzero): the first pq_perm_many call on a job
+ * list whose shape (m, and for every job kind and padded column count the
+ * number of jobs and of Gray terms, each rounded to half an octave) has no
+ * recorded policy plans and runs the job
+ * list under each of 8 candidate policies (the default first), timing the
+ * sweep kernels with HIP events (best of two runs each), keeps the fastest
+ * plan and records its policy.  That call therefore runs the jobs about 16
+ * times and synchronizes the stream; its outputs are those of the kept plan.
+ * Later job lists of the same shape are planned with the recorded policy.
+ * Results differ between policies only by the order of the double-double
+ * partial sums.  Off (0, the default): the default policy.
+ *
+ * pq_autotune_last -- the last decision: policy = {waves_per_cu,
+ * chunks_per_wave, min_chunk}, the kept plan's sweep time and the default
+ * policy's (ms), and the number of candidates timed (0: the policy came
+ * from the record).  All zero before any tuning.  NULL arguments: PQ_EINVAL.
+ */
+int pq_autotune_enable(pq_ctx* ctx, int on);
+int pq_autotune_last(pq_ctx* ctx, int32_t policy[3], double* best_ms, double* default_ms,
+                     int32_t* candidates);
+
+/*
  * pq_perm_grad -- vector-Jacobian product over a batch of patterns on one U.
  * perm(U_{T,S}) is a polynomial (holomorphic) in U; following the
  * conjugate-Wirtinger convention of complex autograd,

@@ -245,6 +245,20 @@ class Engine:
         _check(st, self._ctx)
         return Ud
 
+    def autotune(self, on: bool = True):
+        """Chunk-size autotuning of perm_many (pq_autotune_enable)."""
+        _check(self._lib.pq_autotune_enable(self._ctx, 1 if on else 0), self._ctx)
+
+    def autotune_last(self) -> dict:
+        """The last autotuning decision (pq_autotune_last)."""
+        pol = (ctypes.c_int32 * 3)()
+        best, default = ctypes.c_double(), ctypes.c_double()
+        cand = ctypes.c_int32()
+        _check(self._lib.pq_autotune_last(self._ctx, pol, ctypes.byref(best), ctypes.byref(default),
+                                          ctypes.byref(cand)), self._ctx)
+        return {"waves_per_cu": pol[0], "chunks_per_wave": pol[1], "min_chunk": pol[2],
+                "best_ms": best.value, "default_ms": default.value, "candidates": cand.value}
+
     def lhaf(self, A: torch.Tensor, gamma: torch.Tensor | None, reps: Sequence[int]) -> torch.Tensor:
         """Loop hafnian of filldiag(A_r, gamma_r) with mode i repeated reps[i]
         times (pq_lhaf); gamma None gives the hafnian.  Returns a 1-element

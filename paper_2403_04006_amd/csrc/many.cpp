@@ -5,6 +5,7 @@
 // one kernel per column class (one wavefront per chunk), and reduces every
 // pattern's chunk slots in slot order.
 #include <hip/hip_runtime.h>
+#include <math.h>
 #include <stdint.h>
 #include <string.h>
 
@@ -25,9 +26,11 @@ namespace pq {
 
 namespace {
 
-constexpr uint64_t kFwdMinChunk = 64;
-constexpr uint64_t kFwdChunksPerWave = 2;
 constexpr uint64_t kWalkMinChunk = 256;
+// chunk policies the autotuner times (the first is the default)
+constexpr ChunkPolicy kTuneCandidates[] = {
+    {8, 2, 64}, {4, 1, 64}, {4, 2, 64}, {8, 1, 64}, {8, 4, 64}, {16, 2, 64}, {16, 4, 64}, {8, 2, 256},
+};
 constexpr int kMaxManyEntries = 4;
 
 struct ManyClass {
@@ -43,6 +46,7 @@ struct ManyEntry {
     int npat = 0, ntab = 0;
     size_t mat_elems = 0, partial_doubles = 0, dpat_elems = 0;
     std::vector<ManyClass> classes;
+    ChunkPolicy policy;
     // device
     char* dmem = nullptr;
     BJob* d_jobs = nullptr;
@@ -83,8 +87,9 @@ struct PatternSpec {
 };
 
 int build_many(pq_ctx* ctx, int mode, int32_t m, const std::vector<PatternSpec>& pats, ManyEntry& E,
-               hipStream_t st) {
+               hipStream_t st, const ChunkPolicy& pol) {
     E.mode = mode;
+    E.policy = pol;
     const bool adj = mode == kModeAdj;
     E.npat = (int)pats.size();
     std::vector<BJob> hj(pats.size());
@@ -208,9 +213,9 @@ int build_many(pq_ctx* ctx, int mode, int32_t m, const std::vector<PatternSpec>&
         C.slot_doubles = C.mode == kModeFwd ? 4 : (C.mode == kModeExt ? 4 * C.ncmax : 4 + 2 * rmax * C.ncmax);
         uint64_t chunk = 0;
         if (C.mode == kModeFwd || C.mode == kModeExt) {
-            const uint64_t waves = (uint64_t)ctx->num_cu * 4 * 2;
-            chunk = (total + waves * kFwdChunksPerWave - 1) / (waves * kFwdChunksPerWave);
-            if (chunk < kFwdMinChunk) chunk = kFwdMinChunk;
+            const uint64_t target = (uint64_t)ctx->num_cu * (uint64_t)pol.waves_per_cu * (uint64_t)pol.chunks_per_wave;
+            chunk = (total + target - 1) / target;
+            if (chunk < (uint64_t)pol.min_chunk) chunk = (uint64_t)pol.min_chunk;
         } else if (C.mode == kModeAdjWalk) {
             // two rounds of two resident wavefronts per SIMD
             const uint64_t waves = (uint64_t)ctx->num_cu * 4 * 2 * 2;
@@ -383,7 +388,8 @@ int build_many(pq_ctx* ctx, int mode, int32_t m, const std::vector<PatternSpec>&
 }
 
 int run_many(pq_ctx* ctx, ManyEntry& E, const cplx* U, int64_t ldu, int32_t m, cplx* perm, cplx* amp,
-             const cplx* gperm, cplx* dU, int64_t lddu, hipStream_t st) {
+             const cplx* gperm, cplx* dU, int64_t lddu, hipStream_t st, hipEvent_t t0 = nullptr,
+             hipEvent_t t1 = nullptr) {
     int rc;
     if (E.mat_elems > 0) {
         // BJob.nchunks > 0 marks every planned (non-trivial) pattern
@@ -404,6 +410,10 @@ int run_many(pq_ctx* ctx, ManyEntry& E, const cplx* U, int64_t ldu, int32_t m, c
         rc = ctx->check(hipEventRecord(e0, st), "profile: record");
         if (rc) return rc;
     }
+    if (t0) {
+        rc = ctx->check(hipEventRecord(t0, st), "tune: record");
+        if (rc) return rc;
+    }
     for (const ManyClass& C : E.classes) {
         ManyArgs a;
         a.jobs = E.d_jobs;
@@ -415,6 +425,10 @@ int run_many(pq_ctx* ctx, ManyEntry& E, const cplx* U, int64_t ldu, int32_t m, c
         a.tabs = E.d_tabs;
         a.partials = E.d_partials + C.slot_off;
         rc = ctx->check(launch_many(C.mode, C.ncmax, C.var, a, st), "many sweep");
+        if (rc) return rc;
+    }
+    if (t1) {
+        rc = ctx->check(hipEventRecord(t1, st), "tune: record");
         if (rc) return rc;
     }
     if (ctx->profiling) {
@@ -477,9 +491,73 @@ ManyCache* many_cache(pq_ctx* ctx) {
     return (ManyCache*)ctx->many_cache;
 }
 
-// Find or build the entry for `key`.
+// Shape signature of a job list: for every (op, padded column count) class,
+// the number of patterns and of Gray terms in half-octave buckets, and m.
+// Job lists with the same work per class (say, other sampling runs of the
+// same size, whose output collisions differ) share a tuned policy.
+uint64_t shape_sig(int32_t m, const std::vector<PatternSpec>& pats) {
+    std::map<std::pair<int, int>, std::pair<double, double>> cls;   // (op, ncmax) -> (patterns, terms)
+    for (const PatternSpec& ps : pats) {
+        const bool ext = ps.op == kOpExtend;
+        Plan p;
+        plan_sparse(ps.rows, ps.cols, !ext, p, ext);
+        if (p.status || p.trivial) continue;
+        auto& c = cls[std::make_pair(ps.op, ((p.nc + 3) / 4) * 4)];
+        c.first += 1.0;
+        c.second += (double)p.time_states * (double)p.lane_states;
+    }
+    uint64_t h = 1469598103934665603ull ^ (uint64_t)m;
+    auto mix = [&](uint64_t x) {
+        h ^= x;
+        h *= 1099511628211ull;
+        h ^= h >> 31;
+    };
+    auto bucket = [](double v) { return (uint64_t)llround(2.0 * log2(v > 1.0 ? v : 1.0)); };
+    for (const auto& kv : cls) {
+        mix((uint64_t)kv.first.first);
+        mix((uint64_t)kv.first.second);
+        mix(bucket(kv.second.first));
+        mix(bucket(kv.second.second));
+    }
+    return h;
+}
+
+// Build one candidate plan and time its class sweeps (best of two runs).
+int time_candidate(pq_ctx* ctx, int32_t m, const std::vector<PatternSpec>& pats, const ChunkPolicy& pol,
+                   const cplx* U, int64_t ldu, cplx* perm, cplx* amp, hipStream_t st,
+                   std::unique_ptr<ManyEntry>& out, double& ms) {
+    std::unique_ptr<ManyEntry> e(new ManyEntry());
+    int rc = build_many(ctx, kModeFwd, m, pats, *e, st, pol);
+    if (rc) return rc;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess) {
+        if (t0) hipEventDestroy(t0);
+        return ctx->fail(PQ_EDEVICE, "tune: hipEventCreate failed");
+    }
+    ms = -1.0;
+    for (int rep = 0; rep < 2 && !rc; ++rep) {
+        rc = run_many(ctx, *e, U, ldu, m, perm, amp, nullptr, nullptr, 0, st, t0, t1);
+        if (rc) break;
+        rc = ctx->check(hipEventSynchronize(t1), "tune: synchronize");
+        if (rc) break;
+        float f = 0.0f;
+        rc = ctx->check(hipEventElapsedTime(&f, t0, t1), "tune: elapsed");
+        if (!rc && (ms < 0.0 || f < ms)) ms = f;
+    }
+    hipEventDestroy(t0);
+    hipEventDestroy(t1);
+    if (rc) return rc;
+    out = std::move(e);
+    return PQ_OK;
+}
+
+// Find or build the entry for `key`.  With autotuning on (forward plans
+// only), a job-list shape seen for the first time is planned and timed
+// under every candidate chunk policy and the fastest plan is kept; later
+// job lists of that shape are planned with the recorded policy.
 int get_entry(pq_ctx* ctx, int mode, int32_t m, std::vector<int64_t>& key,
-              const std::vector<PatternSpec>& pats, hipStream_t st, ManyEntry** out) {
+              const std::vector<PatternSpec>& pats, hipStream_t st, ManyEntry** out,
+              const cplx* U = nullptr, int64_t ldu = 0, cplx* perm = nullptr, cplx* amp = nullptr) {
     ManyCache* cache = many_cache(ctx);
     for (auto& e : cache->entries)
         if (e->key == key) {
@@ -495,8 +573,45 @@ int get_entry(pq_ctx* ctx, int mode, int32_t m, std::vector<int64_t>& key,
         hipStreamSynchronize(st);
         cache->entries.erase(it);
     }
-    std::unique_ptr<ManyEntry> ne(new ManyEntry());
-    int rc = build_many(ctx, mode, m, pats, *ne, st);
+    std::unique_ptr<ManyEntry> ne;
+    int rc = PQ_OK;
+    if (ctx->autotune && mode == kModeFwd && perm) {
+        const uint64_t sig = shape_sig(m, pats);
+        const TuneRecord* known = nullptr;
+        for (const TuneRecord& t : ctx->tuned)
+            if (t.sig == sig) known = &t;
+        if (known) {
+            ctx->last_tune = *known;
+            ctx->last_tune.candidates = 0;
+            ne.reset(new ManyEntry());
+            rc = build_many(ctx, mode, m, pats, *ne, st, known->policy);
+        } else {
+            TuneRecord rec;
+            rec.sig = sig;
+            double best = -1.0;
+            for (const ChunkPolicy& pol : kTuneCandidates) {
+                std::unique_ptr<ManyEntry> cand;
+                double ms = 0.0;
+                rc = time_candidate(ctx, m, pats, pol, U, ldu, perm, amp, st, cand, ms);
+                if (rc) break;
+                ++rec.candidates;
+                if (rec.candidates == 1) rec.default_ms = ms;
+                if (best < 0.0 || ms < best) {
+                    best = ms;
+                    rec.policy = pol;
+                    ne = std::move(cand);
+                }
+            }
+            if (!rc) {
+                rec.best_ms = best;
+                ctx->tuned.push_back(rec);
+                ctx->last_tune = rec;
+            }
+        }
+    } else {
+        ne.reset(new ManyEntry());
+        rc = build_many(ctx, mode, m, pats, *ne, st, ChunkPolicy());
+    }
     if (rc) return rc;
     ne->key = std::move(key);
     ne->last_use = ++cache->clock;
@@ -558,7 +673,7 @@ int pq_perm_many(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m,
         pats.push_back(ps);
     }
     ManyEntry* E = nullptr;
-    rc = get_entry(ctx, kModeFwd, m, key, pats, st, &E);
+    rc = get_entry(ctx, kModeFwd, m, key, pats, st, &E, (const cplx*)U, ldu, (cplx*)perm, (cplx*)amp);
     if (rc) return rc;
     return run_many(ctx, *E, (const cplx*)U, ldu, m, (cplx*)perm, (cplx*)amp, nullptr, nullptr, 0, st);
 }
@@ -603,4 +718,23 @@ int pq_perm_grad(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m,
     if (rc) return rc;
     return run_many(ctx, *E, (const cplx*)U, ldu, m, (cplx*)perm, nullptr, (const cplx*)gperm, (cplx*)dU,
                     lddu, st);
+}
+
+int pq_autotune_enable(pq_ctx* ctx, int on) {
+    if (!ctx) return PQ_EINVAL;
+    ctx->clear_error();
+    ctx->autotune = on != 0;
+    return PQ_OK;
+}
+
+int pq_autotune_last(pq_ctx* ctx, int32_t policy[3], double* best_ms, double* default_ms, int32_t* candidates) {
+    if (!ctx || !policy || !best_ms || !default_ms || !candidates) return PQ_EINVAL;
+    const TuneRecord& t = ctx->last_tune;
+    policy[0] = t.policy.waves_per_cu;
+    policy[1] = t.policy.chunks_per_wave;
+    policy[2] = t.policy.min_chunk;
+    *best_ms = t.best_ms;
+    *default_ms = t.default_ms;
+    *candidates = t.candidates;
+    return PQ_OK;
 }

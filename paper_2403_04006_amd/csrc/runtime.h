@@ -11,6 +11,26 @@
 #include "plan.h"
 #include "pq_common.h"
 
+namespace pq {
+// How the forward and extend-row classes of a many-pattern plan are cut into
+// chunks (one wavefront each): aim at num_cu * waves_per_cu * chunks_per_wave
+// chunks per class, none shorter than min_chunk time states.
+struct ChunkPolicy {
+    int32_t waves_per_cu = 8;
+    int32_t chunks_per_wave = 2;
+    int32_t min_chunk = 64;
+};
+// One autotuning decision: the policy kept for a job-list shape, its sweep
+// time, the default policy's, and how many candidates were timed (0: taken
+// from the table).
+struct TuneRecord {
+    uint64_t sig = 0;
+    ChunkPolicy policy;
+    double best_ms = 0.0, default_ms = 0.0;
+    int32_t candidates = 0;
+};
+}  // namespace pq
+
 struct pq_ctx {
     int device = 0;
     int num_cu = 0;
@@ -31,6 +51,12 @@ struct pq_ctx {
     hipEvent_t upload_done = nullptr;
     // resident workgroups per CU per (binary, nc); 0 = not yet queried
     int occ[3][pq::kMaxDim + 1] = {};
+
+    // chunk-policy autotuning of pq_perm_many (pq_autotune_enable): tuned
+    // policies by job-list shape signature, and the last decision
+    bool autotune = false;
+    std::vector<pq::TuneRecord> tuned;
+    pq::TuneRecord last_tune;
 
     // sweep timing (pq_profile_enable / pq_profile_read)
     bool profiling = false;

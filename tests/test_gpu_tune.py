@@ -1,0 +1,119 @@
+"""Chunk-size autotuning of the many-pattern path (pq_autotune_enable /
+pq_autotune_last): tuned plans give the untuned outputs (up to the order of
+the partial sums) and the oracle's, the kept policy is never slower than the
+default one it was timed against, and a job list of the same shape reuses the
+recorded policy without timing again."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def rel(a, b):
+    return abs(a - b) / max(abs(b), 1e-300)
+
+
+@pytest.fixture(scope="module")
+def engines():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2403_04006_amd as pq
+    tuned, plain = pq.Engine(0), pq.Engine(0)
+    tuned.autotune(True)
+    return tuned, plain
+
+
+def dev(U):
+    return torch.from_numpy(np.ascontiguousarray(U, dtype=np.complex128)).cuda()
+
+
+def extend_jobs(samples, seed, photons=12, modes=60):
+    # Clifford-Clifford-shaped EXTEND_ROW jobs: k - 1 drawn rows, first k
+    # ordered input columns, k = 2..photons
+    cols, rows = workloads.sampling_jobs(samples=samples, photons=photons, modes=modes, seed=seed)
+    jobs, off = [], 0
+    for s in range(samples):
+        for k in range(2, photons + 1):
+            rc = np.bincount(rows[s, :k - 1], minlength=modes)
+            cc = np.bincount(cols[s, :k], minlength=modes)
+            jobs.append({"op": 1, "rows": [(i, int(c)) for i, c in enumerate(rc) if c],
+                         "cols": [(i, int(c)) for i, c in enumerate(cc) if c], "out": off})
+            off += modes
+    return jobs, off, cols, rows
+
+
+def test_tuned_plan_matches_default_and_oracle(engines):
+    tuned, plain = engines
+    modes = 60
+    U = workloads.haar(modes, 21)
+    jobs, n_out, cols, rows = extend_jobs(40, 1)
+    got, _ = tuned.perm_many(dev(U), jobs, n_out=n_out, with_amp=False)
+    info = tuned.autotune_last()
+    ref, _ = plain.perm_many(dev(U), jobs, n_out=n_out, with_amp=False)
+    torch.cuda.synchronize()
+    got, ref = got.cpu().numpy(), ref.cpu().numpy()
+    assert info["candidates"] == 8
+    assert 0 < info["best_ms"] <= info["default_ms"]
+    assert (info["waves_per_cu"], info["chunks_per_wave"], info["min_chunk"]) in {
+        (8, 2, 64), (4, 1, 64), (4, 2, 64), (8, 1, 64), (8, 4, 64), (16, 2, 64), (16, 4, 64), (8, 2, 256)}
+    scale = np.max(np.abs(ref))
+    assert np.max(np.abs(got - ref)) <= 1e-13 * scale
+    # a few extend-row outputs against the oracle's Laplace expansion
+    for s, k in ((0, 12), (7, 9), (39, 12)):
+        want = oracle.extend_row(U, list(rows[s, :k - 1]), list(cols[s, :k]))
+        j = s * 11 + (k - 2)
+        blk = got[j * modes:(j + 1) * modes]
+        assert np.max(np.abs(blk - want)) <= 1e-10 * np.max(np.abs(want))
+    # a repeated call reuses the kept plan
+    again, _ = tuned.perm_many(dev(U), jobs, n_out=n_out, with_amp=False)
+    torch.cuda.synchronize()
+    assert np.array_equal(again.cpu().numpy(), got)
+
+
+def test_same_shape_reuses_recorded_policy(engines):
+    tuned, plain = engines
+    modes = 60
+    U = workloads.haar(modes, 22)
+    jobs, n_out, _, _ = extend_jobs(40, 2)     # other draws, same shapes
+    first = tuned.autotune_last()
+    got, _ = tuned.perm_many(dev(U), jobs, n_out=n_out, with_amp=False)
+    info = tuned.autotune_last()
+    ref, _ = plain.perm_many(dev(U), jobs, n_out=n_out, with_amp=False)
+    torch.cuda.synchronize()
+    assert info["candidates"] == 0
+    assert (info["waves_per_cu"], info["chunks_per_wave"], info["min_chunk"]) == (
+        first["waves_per_cu"], first["chunks_per_wave"], first["min_chunk"])
+    got, ref = got.cpu().numpy(), ref.cpu().numpy()
+    assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+def test_tuning_repeated_permanents(engines):
+    # uneven PERM jobs with repeated rows and columns
+    tuned, plain = engines
+    rng = np.random.default_rng(5)
+    m = 12
+    U = workloads.haar(m, 23)
+    jobs, refs = [], []
+    for k in range(48):
+        n = int(rng.integers(6, 19))
+        S = workloads.random_occupations(rng, m, n, cap=3)
+        T = workloads.random_occupations(rng, m, n, cap=3)
+        jobs.append({"op": 0, "rows": [(i, int(c)) for i, c in enumerate(T) if c],
+                     "cols": [(i, int(c)) for i, c in enumerate(S) if c]})
+        if k < 6:
+            refs.append((k, oracle.perm_mult(U, S, T)))
+    got, _ = tuned.perm_many(dev(U), jobs)
+    info = tuned.autotune_last()
+    ref, _ = plain.perm_many(dev(U), jobs)
+    torch.cuda.synchronize()
+    got, ref = got.cpu().numpy(), ref.cpu().numpy()
+    assert info["candidates"] == 8 and info["best_ms"] <= info["default_ms"]
+    for k in range(len(jobs)):
+        assert rel(got[k], ref[k]) <= 1e-12
+    for k, want in refs:
+        assert rel(got[k], want) <= 1e-10
