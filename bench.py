@@ -267,7 +267,7 @@ def main() -> int:
             "samples": 1000, "jobs": len(jl), "sweep_ms": ms / 3, "wall_ms": tw * 1e3,
             "samples_per_s": 1000 / tw}
         # the same two workloads with chunk sizes picked by the autotuner: the
-        # first call times 8 candidate policies, then 3 calls of the kept plan
+        # first call times 11 candidate policies, then 3 calls of the kept plan
         teng = pq.Engine(0)
         teng.autotune(True)
         tuned_runs = {}
@@ -289,6 +289,17 @@ def main() -> int:
                 "policy": [info["waves_per_cu"], info["chunks_per_wave"], info["min_chunk"]],
                 "candidates": info["candidates"], "tuning_best_ms": info["best_ms"],
                 "tuning_default_ms": info["default_ms"], "sweep_ms": ms / 3, "wall_ms": tw * 1e3}
+        # the tuned replay as a captured HIP graph (one launch per call) into
+        # fixed output buffers
+        outg = torch.empty(len(jl) * 400, dtype=torch.complex128, device=dev)
+        teng.graphs(True)
+        teng.perm_many(U400, js, with_amp=False, out=(outg, None))
+        torch.cuda.synchronize()
+        tw = time.perf_counter()
+        for _ in range(5):
+            teng.perm_many(U400, js, with_amp=False, out=(outg, None))
+        torch.cuda.synchronize()
+        tuned_runs["sampling_replay"]["graph_wall_ms"] = (time.perf_counter() - tw) / 5 * 1e3
         teng.close()
         batched["autotuned"] = tuned_runs
         # the same sampling runs drawn entirely on the device (the chain rule

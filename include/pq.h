@@ -151,15 +151,15 @@ int pq_perm_many(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m,
  * boson-sampling run in one statically scheduled launch per column class).
  * A plan aims at num_cu * waves_per_cu * chunks_per_wave chunks per class,
  * none shorter than min_chunk Gray time states; the default policy is
- * (8, 2, 64).
+ * (16, 4, 64).
  *
  * pq_autotune_enable -- on (nonzero): the first pq_perm_many call on a job
  * list whose shape (m, and for every job kind and padded column count the
  * number of jobs and of Gray terms, each rounded to half an octave) has no
  * recorded policy plans and runs the job
- * list under each of 8 candidate policies (the default first), timing the
+ * list under each of 11 candidate policies (the default first), timing the
  * sweep kernels with HIP events (best of two runs each), keeps the fastest
- * plan and records its policy.  That call therefore runs the jobs about 16
+ * plan and records its policy.  That call therefore runs the jobs about 22
  * times and synchronizes the stream; its outputs are those of the kept plan.
  * Later job lists of the same shape are planned with the recorded policy.
  * Results differ between policies only by the order of the double-double
@@ -170,6 +170,18 @@ int pq_perm_many(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m,
  * policy's (ms), and the number of candidates timed (0: the policy came
  * from the record).  All zero before any tuning.  NULL arguments: PQ_EINVAL.
  */
+/*
+ * pq_graph_enable -- on (nonzero): pq_perm_many captures its launch sequence
+ * for a plan (gather of the compact matrices, step tables, one sweep per
+ * column class, final reduction; kernel nodes only) into a HIP graph the
+ * first time it runs with a given (U, ldu, perm, amp), and afterwards
+ * replays that graph on the caller's stream with one hipGraphLaunch.  Up to 4
+ * graphs are kept per cached plan.  The graph reads U and writes perm/amp
+ * through the captured pointers, so those buffers must stay allocated while
+ * the plan is cached.  Calls with profiling on launch the kernels directly.
+ * Off (0, the default): direct launches.  NULL ctx: PQ_EINVAL.
+ */
+int pq_graph_enable(pq_ctx* ctx, int on);
 int pq_autotune_enable(pq_ctx* ctx, int on);
 int pq_autotune_last(pq_ctx* ctx, int32_t policy[3], double* best_ms, double* default_ms,
                      int32_t* candidates);

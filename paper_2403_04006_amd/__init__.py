@@ -153,7 +153,7 @@ class Engine:
         ptr = ctypes.cast(arr.ctypes.data, ctypes.POINTER(pq_job))
         return ptr, (buf, arr), total
 
-    def _run_jobs(self, fn, U, jobs, n_out, with_amp):
+    def _run_jobs(self, fn, U, jobs, n_out, with_amp, out=None):
         U, ldu = _as_matrix(U)
         m = U.shape[0]
         if isinstance(jobs, JobSet):
@@ -164,8 +164,16 @@ class Engine:
         else:
             arr, keep, total = self._job_array(jobs, m)
         n_out = total if n_out is None else n_out
-        perm = torch.zeros(max(1, n_out), dtype=torch.complex128, device=U.device)
-        amp = torch.zeros(max(1, n_out), dtype=torch.complex128, device=U.device) if with_amp else None
+        if out is not None:
+            # caller-owned outputs (stable pointers, e.g. for graph replays)
+            perm, amp = out
+            for t in (perm, amp):
+                if t is not None and (t.dtype != torch.complex128 or t.device != U.device
+                                      or not t.is_contiguous() or t.numel() < max(1, n_out)):
+                    raise ValueError("out tensors must be contiguous complex128 on U's device, n_out long")
+        else:
+            perm = torch.zeros(max(1, n_out), dtype=torch.complex128, device=U.device)
+            amp = torch.zeros(max(1, n_out), dtype=torch.complex128, device=U.device) if with_amp else None
         st = fn(self._ctx, U.data_ptr(), ldu, m, arr, len(jobs), perm.data_ptr(),
                 amp.data_ptr() if amp is not None else None, _stream_handle(U.device))
         _check(st, self._ctx)
@@ -249,6 +257,11 @@ class Engine:
         """Chunk-size autotuning of perm_many (pq_autotune_enable)."""
         _check(self._lib.pq_autotune_enable(self._ctx, 1 if on else 0), self._ctx)
 
+    def graphs(self, on: bool = True):
+        """Replay perm_many launch sequences as captured HIP graphs
+        (pq_graph_enable)."""
+        _check(self._lib.pq_graph_enable(self._ctx, 1 if on else 0), self._ctx)
+
     def autotune_last(self) -> dict:
         """The last autotuning decision (pq_autotune_last)."""
         pol = (ctypes.c_int32 * 3)()
@@ -289,12 +302,14 @@ class Engine:
         out = self.sample_chain(self.loss_dilation(U, eta), order, uniforms)
         return torch.where(out >= m, torch.full_like(out, -1), out)
 
-    def perm_many(self, U: torch.Tensor, jobs: Sequence[dict], n_out: int | None = None, with_amp: bool = True):
+    def perm_many(self, U: torch.Tensor, jobs: Sequence[dict], n_out: int | None = None, with_amp: bool = True,
+                  out: tuple | None = None):
         """Jobs {op, rows: [(mode, mult)], cols: [(mode, mult)], out} through the
         statically scheduled many-pattern path (pq_perm_many).  PERM jobs write
         perm(U_{T,S}) (and the amplitude) at `out`; EXTEND_ROW jobs write
-        perm(U_{T+e_l,S}) for l = 0..m-1 at out..out+m-1.  Returns (perm, amp)."""
-        return self._run_jobs(self._lib.pq_perm_many, U, jobs, n_out, with_amp)
+        perm(U_{T+e_l,S}) for l = 0..m-1 at out..out+m-1.  Returns (perm, amp).
+        `out` = (perm, amp or None): caller-owned output tensors."""
+        return self._run_jobs(self._lib.pq_perm_many, U, jobs, n_out, with_amp, out)
 
     def perm_batched(self, U: torch.Tensor, jobs: Sequence[dict], n_out: int | None = None,
                      with_amp: bool = True):

@@ -29,7 +29,8 @@ namespace {
 constexpr uint64_t kWalkMinChunk = 256;
 // chunk policies the autotuner times (the first is the default)
 constexpr ChunkPolicy kTuneCandidates[] = {
-    {8, 2, 64}, {4, 1, 64}, {4, 2, 64}, {8, 1, 64}, {8, 4, 64}, {16, 2, 64}, {16, 4, 64}, {8, 2, 256},
+    {16, 4, 64}, {4, 2, 64}, {8, 1, 64}, {8, 2, 64}, {8, 4, 64}, {16, 2, 64},
+    {16, 8, 64}, {32, 4, 64}, {32, 8, 64}, {8, 2, 256}, {16, 4, 256},
 };
 constexpr int kMaxManyEntries = 4;
 
@@ -70,14 +71,36 @@ struct ManyEntry {
     cplx* d_red_part = nullptr;
     int nred1 = 0, nred2 = 0;
     uint64_t last_use = 0;
+    // captured launch sequences (forward plans), one per pointer set
+    struct GraphRec {
+        const cplx* U;
+        int64_t ldu;
+        cplx* perm;
+        cplx* amp;
+        hipGraph_t graph;
+        hipGraphExec_t exec;
+    };
+    std::vector<GraphRec> graphs;
     ~ManyEntry() {
+        if (!graphs.empty()) hipDeviceSynchronize();
+        for (GraphRec& g : graphs) {
+            hipGraphExecDestroy(g.exec);
+            hipGraphDestroy(g.graph);
+        }
         if (dmem) hipFree(dmem);
     }
 };
 
+constexpr size_t kMaxGraphsPerEntry = 4;
+
 struct ManyCache {
     std::vector<std::unique_ptr<ManyEntry>> entries;
     uint64_t clock = 0;
+    hipStream_t capture = nullptr;
+    ~ManyCache() {
+        entries.clear();
+        if (capture) hipStreamDestroy(capture);
+    }
 };
 
 struct PatternSpec {
@@ -491,6 +514,50 @@ ManyCache* many_cache(pq_ctx* ctx) {
     return (ManyCache*)ctx->many_cache;
 }
 
+// Replay the forward launch sequence of E for these pointers as a HIP graph,
+// capturing it (on the cache's own stream, thread-local mode) the first time.
+// The graph holds kernel nodes only.
+int run_many_graph(pq_ctx* ctx, ManyEntry& E, const cplx* U, int64_t ldu, int32_t m, cplx* perm, cplx* amp,
+                   hipStream_t st) {
+    ManyEntry::GraphRec* rec = nullptr;
+    for (auto& g : E.graphs)
+        if (g.U == U && g.ldu == ldu && g.perm == perm && g.amp == amp) rec = &g;
+    if (!rec) {
+        ManyCache* cache = many_cache(ctx);
+        int rc;
+        if (!cache->capture) {
+            rc = ctx->check(hipStreamCreateWithFlags(&cache->capture, hipStreamNonBlocking), "capture stream");
+            if (rc) return rc;
+        }
+        rc = ctx->check(hipStreamBeginCapture(cache->capture, hipStreamCaptureModeThreadLocal), "begin capture");
+        if (rc) return rc;
+        rc = run_many(ctx, E, U, ldu, m, perm, amp, nullptr, nullptr, 0, cache->capture);
+        hipGraph_t g = nullptr;
+        const hipError_t ee = hipStreamEndCapture(cache->capture, &g);
+        if (rc) {
+            if (g) hipGraphDestroy(g);
+            return rc;
+        }
+        rc = ctx->check(ee, "end capture");
+        if (rc) return rc;
+        hipGraphExec_t x = nullptr;
+        rc = ctx->check(hipGraphInstantiate(&x, g, nullptr, nullptr, 0), "graph instantiate");
+        if (rc) {
+            hipGraphDestroy(g);
+            return rc;
+        }
+        if (E.graphs.size() >= kMaxGraphsPerEntry) {
+            hipStreamSynchronize(st);
+            hipGraphExecDestroy(E.graphs.front().exec);
+            hipGraphDestroy(E.graphs.front().graph);
+            E.graphs.erase(E.graphs.begin());
+        }
+        E.graphs.push_back(ManyEntry::GraphRec{U, ldu, perm, amp, g, x});
+        rec = &E.graphs.back();
+    }
+    return ctx->check(hipGraphLaunch(rec->exec, st), "graph launch");
+}
+
 // Shape signature of a job list: for every (op, padded column count) class,
 // the number of patterns and of Gray terms in half-octave buckets, and m.
 // Job lists with the same work per class (say, other sampling runs of the
@@ -675,6 +742,8 @@ int pq_perm_many(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m,
     ManyEntry* E = nullptr;
     rc = get_entry(ctx, kModeFwd, m, key, pats, st, &E, (const cplx*)U, ldu, (cplx*)perm, (cplx*)amp);
     if (rc) return rc;
+    if (ctx->graphs && !ctx->profiling)
+        return run_many_graph(ctx, *E, (const cplx*)U, ldu, m, (cplx*)perm, (cplx*)amp, st);
     return run_many(ctx, *E, (const cplx*)U, ldu, m, (cplx*)perm, (cplx*)amp, nullptr, nullptr, 0, st);
 }
 
@@ -736,5 +805,12 @@ int pq_autotune_last(pq_ctx* ctx, int32_t policy[3], double* best_ms, double* de
     *best_ms = t.best_ms;
     *default_ms = t.default_ms;
     *candidates = t.candidates;
+    return PQ_OK;
+}
+
+int pq_graph_enable(pq_ctx* ctx, int on) {
+    if (!ctx) return PQ_EINVAL;
+    ctx->clear_error();
+    ctx->graphs = on != 0;
     return PQ_OK;
 }

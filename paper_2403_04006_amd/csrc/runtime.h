@@ -16,8 +16,8 @@ namespace pq {
 // chunks (one wavefront each): aim at num_cu * waves_per_cu * chunks_per_wave
 // chunks per class, none shorter than min_chunk time states.
 struct ChunkPolicy {
-    int32_t waves_per_cu = 8;
-    int32_t chunks_per_wave = 2;
+    int32_t waves_per_cu = 16;
+    int32_t chunks_per_wave = 4;
     int32_t min_chunk = 64;
 };
 // One autotuning decision: the policy kept for a job-list shape, its sweep
@@ -55,6 +55,9 @@ struct pq_ctx {
     // chunk-policy autotuning of pq_perm_many (pq_autotune_enable): tuned
     // policies by job-list shape signature, and the last decision
     bool autotune = false;
+    // pq_perm_many replays a captured HIP graph of its launch sequence
+    // (pq_graph_enable)
+    bool graphs = false;
     std::vector<pq::TuneRecord> tuned;
     pq::TuneRecord last_tune;
 
