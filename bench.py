@@ -40,6 +40,28 @@ SWEEP_TRAFFIC = {
 }
 
 
+def repeated_flops(S, T) -> tuple:
+    """FP64 flops of one repeated-row permanent, per Gray term times the
+    terms; c = occupied modes on the power side (the side not iterated):
+    - nominal: 2c for the column-sum update, 6 per complex multiply of the
+      product prod_j c_j^kappa_j taken column by column (pm(kappa) = 0, 1, 2,
+      2 for kappa = 1..4, plus c - 1 to join the columns), 2 for the weight
+      and 2 to accumulate;
+    - executed: the same, with the grouped product (columns by ascending
+      kappa, one running suffix product, one multiply per unit of rise):
+      c - 1 + max(kappa) complex multiplies."""
+    import numpy as np
+    import paper_2403_04006_amd as pq
+    info = pq.plan_describe(list(S), list(T))
+    pw = np.asarray(T if info["transposed"] else S)
+    kap = pw[pw > 0]
+    pm = {1: 0, 2: 1, 3: 2, 4: 2}
+    c = len(kap)
+    nominal = 2 * c + 6 * (sum(pm.get(int(k), int(np.ceil(np.log2(k))) + 1) for k in kap) + c - 1) + 4
+    executed = 2 * c + 6 * (c - 1 + int(kap.max())) + 4
+    return float(info["terms"]) * nominal, float(info["terms"]) * executed
+
+
 def sweep_traffic_bytes(n: int):
     """Calibrated HBM bytes per sweep launch, or None when the kernel sources
     differ from those the counters were taken on."""
@@ -227,6 +249,9 @@ def main() -> int:
         pats = workloads.repeated_patterns(count=256, seed=1)
         ps = pq.PatternSet([p_[0] for p_ in pats], [p_[1] for p_ in pats], 20)
         rterms = sum(pq.plan_describe(list(S_), list(T_))["terms"] for S_, T_ in pats)
+        rfl = [repeated_flops(S_, T_) for S_, T_ in pats]
+        rflops_nominal = sum(f[0] for f in rfl)
+        rflops = sum(f[1] for f in rfl)
         eng.perm_patterns(U20, ps)
         torch.cuda.synchronize()
         eng.profile(True)
@@ -240,7 +265,10 @@ def main() -> int:
         eng.profile(False)
         batched["repeated_40_photons"] = {
             "patterns": 256, "gray_terms": rterms, "sweep_ms": ms / 3, "wall_ms": tw * 1e3,
-            "terms_per_s": rterms / (ms / 3 * 1e-3)}
+            "terms_per_s": rterms / (ms / 3 * 1e-3), "executed_flops": rflops,
+            "achieved_tflops": rflops / (ms / 3 * 1e-3) / 1e12,
+            "frac": rflops / (ms / 3 * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
+            "nominal_flops": rflops_nominal}
         U400 = torch.from_numpy(workloads.haar(400, 0)).to(dev)
         cols, rows = workloads.sampling_jobs(samples=1000, seed=0)
         jl = []
