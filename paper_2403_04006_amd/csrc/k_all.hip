@@ -32,22 +32,31 @@ __global__ __launch_bounds__(kBlock) void all_sums_kernel(const AllSumsArgs a) {
 
 // One thread per output pattern T (lexicographic rank idx).  The thread's
 // photons are its output modes with repetition, r_0 <= ... <= r_{n-1}; per
-// delta term the product prod_q c_{r_q} takes n - 1 complex multiplies.
+// delta term the product prod_q c_{r_q}.  The 64 outputs of a wavefront are
+// consecutive in lexicographic order, so their lists share a prefix
+// r_0..r_{L-1} (the photons in the modes that do not change across the
+// wavefront).  Per tile of terms, lane j forms w_j prod_{q<L} c_{r_q} for term
+// j once (into LDS), and every lane multiplies in only its own r_L..r_{n-1}:
+// n - L complex multiplies and n - L + 1 LDS reads per (term, output).
 template <int NMAX>
 __global__ __launch_bounds__(kBlock) void all_out_kernel(const AllOutArgs a) {
     __shared__ cplx sC[kAllTile * kAllMaxModes];
     __shared__ double sW[kAllTile];
     __shared__ uint8_t sR[kBlock][NMAX];
+    __shared__ cplx sP[kWavesPerBlock][kAllTile];
     const int tid = (int)threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6;
     const int64_t idx = (int64_t)blockIdx.x * kBlock + tid;
     const bool act = idx < a.outputs;
     const int m = a.m, n = a.n;
 
     // unrank: T_i for i = 0..m-2 by counting the patterns that start with a
-    // smaller T_i; T_{m-1} takes the rest
+    // smaller T_i; T_{m-1} takes the rest.  Lanes past the last output take
+    // the last one (a valid list that does not shorten the common prefix
+    // more than any real output would).
     double tfact = 1.0;
     {
-        uint64_t rank = act ? (uint64_t)idx : 0;
+        uint64_t rank = act ? (uint64_t)idx : (uint64_t)(a.outputs - 1);
         int rem = n, q = 0;
         for (int i = 0; i < m; ++i) {
             int v = rem;
@@ -67,9 +76,27 @@ __global__ __launch_bounds__(kBlock) void all_out_kernel(const AllOutArgs a) {
         }
     }
     __syncthreads();
+    // common prefix over the wavefront: L = the smallest first disagreement
+    int R[NMAX];
+    int first = n;
+#pragma unroll
+    for (int q = 0; q < NMAX; ++q) {
+        const int r = q < n ? (int)sR[tid][q] : 0;
+        R[q] = __builtin_amdgcn_readfirstlane(r);
+        if (q < n && r != R[q] && first == n) first = q;
+    }
+    int L = first;
+#pragma unroll
+    for (int msk = 1; msk < 64; msk <<= 1) {
+        const int o = __shfl_xor(L, msk, 64);
+        L = o < L ? o : L;
+    }
+    L = __builtin_amdgcn_readfirstlane(L);
+    const int ns = n - L;
+    // this lane's suffix r_L..r_{n-1}
     int off[NMAX];
 #pragma unroll
-    for (int q = 0; q < NMAX; ++q) off[q] = q < n ? (int)sR[tid][q] : 0;
+    for (int q = 0; q < NMAX; ++q) off[q] = q < ns ? (int)sR[tid][q + L] : 0;
 
     cdd acc = to_cdd(cplx{0.0, 0.0});
     for (uint64_t d0 = 0; d0 < a.terms; d0 += kAllTile) {
@@ -78,14 +105,25 @@ __global__ __launch_bounds__(kBlock) void all_out_kernel(const AllOutArgs a) {
         for (int e = tid; e < nt * m; e += kBlock) sC[e] = a.csum[d0 * (uint64_t)m + e];
         for (int e = tid; e < nt; e += kBlock) sW[e] = a.w[d0 + e];
         __syncthreads();
+        // w_j prod_{q<L} c_{r_q} for the tile's terms, lane j
+        if (lane < nt) {
+            const cplx* cj = sC + lane * m;
+            cplx P{sW[lane], 0.0};
+#pragma unroll
+            for (int q = 0; q < NMAX; ++q)
+                if (q < L) P = cmul(P, cj[R[q]]);
+            sP[wv][lane] = P;
+        }
+        __syncthreads();
         cplx part{0.0, 0.0};
         for (int dd = 0; dd < nt; ++dd) {
             const cplx* cd = sC + dd * m;
-            cplx p = cd[off[0]];
+            cplx p = sP[wv][dd];
 #pragma unroll
-            for (int q = 1; q < NMAX; ++q)
-                if (q < n) p = cmul(p, cd[off[q]]);
-            cfma_to(part, sW[dd], p);
+            for (int q = 0; q < NMAX; ++q)
+                if (q < ns) p = cmul(p, cd[off[q]]);
+            part.re += p.re;
+            part.im += p.im;
         }
         acc = cdd_add(acc, to_cdd(part));
     }
