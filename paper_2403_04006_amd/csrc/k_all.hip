@@ -30,6 +30,47 @@ __global__ __launch_bounds__(kBlock) void all_sums_kernel(const AllSumsArgs a) {
     if (i == 0) a.w[d] = w;
 }
 
+// part += sum over the tile's terms dd of sP[dd] prod_{q<NS} cd[off[q]]: the
+// reads of a term go out four at a time ahead of their products (no
+// per-factor waits or branches), into two alternating product chains.
+template <int NS, int NMAX>
+__device__ __forceinline__ void suffix_tile(const cplx* sC, const cplx* sPw, const int (&off)[NMAX], int m, int nt,
+                                            cplx& part) {
+    for (int dd = 0; dd < nt; ++dd) {
+        const cplx* cd = sC + dd * m;
+        cplx p = sPw[dd];
+        if constexpr (NS > 0) {
+            cplx p2{1.0, 0.0};
+#pragma unroll
+            for (int q0 = 0; q0 < NS; q0 += 4) {
+                cplx f[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (q0 + k < NS) f[k] = cd[off[q0 + k]];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    if (q0 + k < NS) {
+                        if (k & 1) p2 = cmul(p2, f[k]);
+                        else p = cmul(p, f[k]);
+                    }
+                }
+            }
+            if constexpr (NS > 1) p = cmul(p, p2);
+        }
+        part.re += p.re;
+        part.im += p.im;
+    }
+}
+
+template <int NMAX, int NS = 0>
+__device__ __forceinline__ void suffix_dispatch(int ns, const cplx* sC, const cplx* sPw, const int (&off)[NMAX], int m,
+                                                int nt, cplx& part) {
+    if constexpr (NS <= NMAX) {
+        if (ns == NS) suffix_tile<NS, NMAX>(sC, sPw, off, m, nt, part);
+        else suffix_dispatch<NMAX, NS + 1>(ns, sC, sPw, off, m, nt, part);
+    }
+}
+
 // One thread per output pattern T (lexicographic rank idx).  The thread's
 // photons are its output modes with repetition, r_0 <= ... <= r_{n-1}; per
 // delta term the product prod_q c_{r_q}.  The 64 outputs of a wavefront are
@@ -39,7 +80,7 @@ __global__ __launch_bounds__(kBlock) void all_sums_kernel(const AllSumsArgs a) {
 // j once (into LDS), and every lane multiplies in only its own r_L..r_{n-1}:
 // n - L complex multiplies and n - L + 1 LDS reads per (term, output).
 template <int NMAX>
-__global__ __launch_bounds__(kBlock) void all_out_kernel(const AllOutArgs a) {
+__global__ __launch_bounds__(kBlock, 4) void all_out_kernel(const AllOutArgs a) {
     __shared__ cplx sC[kAllTile * kAllMaxModes];
     __shared__ double sW[kAllTile];
     __shared__ uint8_t sR[kBlock][NMAX];
@@ -116,15 +157,7 @@ __global__ __launch_bounds__(kBlock) void all_out_kernel(const AllOutArgs a) {
         }
         __syncthreads();
         cplx part{0.0, 0.0};
-        for (int dd = 0; dd < nt; ++dd) {
-            const cplx* cd = sC + dd * m;
-            cplx p = sP[wv][dd];
-#pragma unroll
-            for (int q = 0; q < NMAX; ++q)
-                if (q < ns) p = cmul(p, cd[off[q]]);
-            part.re += p.re;
-            part.im += p.im;
-        }
+        suffix_dispatch<NMAX>(ns, sC, sP[wv], off, m, nt, part);
         acc = cdd_add(acc, to_cdd(part));
     }
     if (!act) return;
