@@ -294,6 +294,20 @@ int pq_loss_dilation(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m, cons
 int pq_lhaf(pq_ctx* ctx, const pq_c128* A, int64_t lda, int32_t d, const pq_c128* gamma,
             const int32_t* reps, pq_c128* out, void* stream);
 
+/*
+ * pq_lhaf_many -- pq_lhaf for npat repetition vectors on one matrix (the
+ * probabilities of many output patterns of one Gaussian state), in one
+ * submission: every pattern is planned on the host, its Gray range is cut
+ * into chunks (four per workgroup, all of one pattern), one launch per
+ * kernel variant sweeps them, and each pattern's chunk sums are added in
+ * chunk order (results do not depend on timing).
+ *   reps   host int32[npat * d], pattern q at offset q * d.
+ *   out    device, npat complex, written (out[q] for pattern q).
+ * Limits and errors as for pq_lhaf, per pattern; npat == 0 does nothing.
+ */
+int pq_lhaf_many(pq_ctx* ctx, const pq_c128* A, int64_t lda, int32_t d, const pq_c128* gamma,
+                 const int32_t* reps, int32_t npat, pq_c128* out, void* stream);
+
 /* Number of occupation vectors with n photons on m modes, C(n+m-1, n);
  * -1 for m < 1, n < 0, or a count above 2^62 (host, no GPU work). */
 int64_t pq_fock_count(int32_t m, int32_t n);

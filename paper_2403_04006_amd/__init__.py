@@ -294,6 +294,29 @@ class Engine:
         _check(st, self._ctx)
         return out
 
+    def lhaf_many(self, A: torch.Tensor, gamma: torch.Tensor | None, reps) -> torch.Tensor:
+        """Loop hafnians of filldiag(A_r, gamma_r) for every repetition vector
+        in `reps` (npat x d), in one submission (pq_lhaf_many); gamma None
+        gives hafnians.  Returns an (npat,) complex128 tensor on A's device."""
+        A, lda = _as_matrix(A)
+        d = A.shape[0]
+        r = np.ascontiguousarray(np.asarray(reps, dtype=np.int32))
+        if r.ndim != 2 or r.shape[1] != d:
+            raise ValueError("reps must be npat x d")
+        g_ptr = None
+        if gamma is not None:
+            if gamma.dtype != torch.complex128 or gamma.device != A.device or tuple(gamma.shape) != (d,):
+                raise ValueError("gamma must be a complex128 vector of length d on A's device")
+            gamma = gamma.contiguous()
+            g_ptr = gamma.data_ptr()
+        npat = r.shape[0]
+        out = torch.empty(max(1, npat), dtype=torch.complex128, device=A.device)
+        st = self._lib.pq_lhaf_many(self._ctx, A.data_ptr(), lda, d, g_ptr,
+                                    r.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), npat, out.data_ptr(),
+                                    _stream_handle(A.device))
+        _check(st, self._ctx)
+        return out[:npat]
+
     def sample_chain_lossy(self, U: torch.Tensor, eta: Sequence[float], order: torch.Tensor,
                            uniforms: torch.Tensor) -> torch.Tensor:
         """Chain-rule samples through U followed by per-mode losses: the draws

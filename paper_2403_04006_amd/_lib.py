@@ -89,6 +89,8 @@ _SIGNATURES = {
                          _VP], ctypes.c_int),
     "pq_fock_unrank": ([ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, _I32P], ctypes.c_int),
     "pq_lhaf": ([_VP, _VP, ctypes.c_int64, ctypes.c_int32, _VP, _I32P, _VP, _VP], ctypes.c_int),
+    "pq_lhaf_many": ([_VP, _VP, ctypes.c_int64, ctypes.c_int32, _VP, _I32P, ctypes.c_int32, _VP, _VP],
+                     ctypes.c_int),
     "pq_autotune_enable": ([_VP, ctypes.c_int], ctypes.c_int),
     "pq_graph_enable": ([_VP, ctypes.c_int], ctypes.c_int),
     "pq_autotune_last": ([_VP, _I32P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), _I32P],

@@ -5,6 +5,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <tuple>
 #include <vector>
 
 #include "../../include/pq.h"
@@ -137,6 +139,71 @@ void haf_tables(const HafPlan& p, std::vector<HafStep>& tab) {
     }
 }
 
+// Validate one repetition vector: N in *N, PQ_OK or an error status.
+int check_reps(pq_ctx* ctx, const int32_t* reps, int d, int* N, const char* who) {
+    int n = 0;
+    for (int i = 0; i < d; ++i) {
+        if (reps[i] < 0) return ctx->fail(PQ_EINVAL, "%s: negative repetition", who);
+        if (reps[i] > kHafMaxN) return ctx->fail(PQ_ERANGE, "%s: more than %d vertices", who, kHafMaxN);
+        n += reps[i];
+        if (n > kHafMaxN) return ctx->fail(PQ_ERANGE, "%s: more than %d vertices", who, kHafMaxN);
+    }
+    *N = n;
+    return PQ_OK;
+}
+
+// Plan one pattern: its descriptor (offsets left to the caller), plan and
+// step tables.  Trivial patterns (N = 0; odd N without loops) get
+// nchunks = 0 and their value.
+int describe(pq_ctx* ctx, const int32_t* reps, int d, int N, bool loops, HafDesc& D, HafPlan& p,
+             std::vector<HafStep>& tab, const char* who) {
+    memset(&D, 0, sizeof(D));
+    D.N = N;
+    if (N == 0 || (!loops && (N & 1))) {
+        D.nchunks = 0;
+        D.trivial = cplx{N == 0 ? 1.0 : 0.0, 0.0};
+        return PQ_OK;
+    }
+    const char* why = "";
+    int rc = plan_haf(reps, d, p, &why);
+    if (rc) return ctx->fail(rc, "%s: %s", who, why);
+    haf_tables(p, tab);
+    D.time_states = p.time_states;
+    D.k = p.k;
+    D.nl = p.nl;
+    D.rr = p.rr;
+    D.nt = p.nt;
+    D.n_in = p.n_in;
+    D.lane_states = p.lane_states;
+    D.M = p.M;
+    {
+        // square-and-multiply schedule of x^{N/2}
+        const int K = N / 2;
+        int top = 0;
+        while ((K >> (top + 1)) > 0) ++top;
+        int z = 0;
+        for (int b = top - 1; b >= 0; --b) {
+            ++z;
+            if ((K >> b) & 1) {
+                D.pw_pack |= (uint32_t)z << (4 * D.pw_nseg++);
+                z = 0;
+            }
+        }
+        D.pw_tail = z;
+    }
+    for (int i = 0; i < p.k; ++i) {
+        D.rad[i] = (int8_t)p.rad[i];
+        D.rep[i] = (int8_t)p.rep[i];
+    }
+    double fact[kHafMaxN + 1];
+    fact[0] = 1.0;
+    for (int i = 1; i <= kHafMaxN; ++i) fact[i] = fact[i - 1] * (double)i;
+    for (int j = 0; j <= N / 2; ++j) D.coef[j] = 1.0 / (fact[j] * fact[N - 2 * j]);
+    D.scale = ldexp(1.0, -(N - 1)) / (loops ? 1.0 : fact[N / 2]);
+    D.nchunks = 1;
+    return PQ_OK;
+}
+
 }  // namespace
 
 int pq_lhaf(pq_ctx* ctx, const pq_c128* A, int64_t lda, int32_t d, const pq_c128* gamma, const int32_t* reps,
@@ -145,24 +212,18 @@ int pq_lhaf(pq_ctx* ctx, const pq_c128* A, int64_t lda, int32_t d, const pq_c128
     ctx->clear_error();
     if (d < 0 || !out || (d > 0 && !reps)) return ctx->fail(PQ_EINVAL, "pq_lhaf: NULL argument or d < 0");
     int N = 0;
-    for (int i = 0; i < d; ++i) {
-        if (reps[i] < 0) return ctx->fail(PQ_EINVAL, "pq_lhaf: negative repetition");
-        if (reps[i] > kHafMaxN) return ctx->fail(PQ_ERANGE, "pq_lhaf: more than %d vertices", kHafMaxN);
-        N += reps[i];
-        if (N > kHafMaxN) return ctx->fail(PQ_ERANGE, "pq_lhaf: more than %d vertices", kHafMaxN);
-    }
+    int rc = check_reps(ctx, reps, d, &N, "pq_lhaf");
+    if (rc) return rc;
     if (N > 0 && (!A || lda < d)) return ctx->fail(PQ_EINVAL, "pq_lhaf: NULL matrix or lda < d");
     DeviceGuard guard(ctx->device);
     hipStream_t st = (hipStream_t)stream;
     const bool loops = gamma != nullptr;
-    if (N == 0) return ctx->check(launch_fill((cplx*)out, nullptr, cplx{1.0, 0.0}, st), "fill");
-    if (!loops && (N & 1)) return ctx->check(launch_fill((cplx*)out, nullptr, cplx{0.0, 0.0}, st), "fill");
+    HafDesc D;
     HafPlan p;
-    const char* why = "";
-    int rc = plan_haf(reps, d, p, &why);
-    if (rc) return ctx->fail(rc, "pq_lhaf: %s", why);
     std::vector<HafStep> tab;
-    haf_tables(p, tab);
+    rc = describe(ctx, reps, d, N, loops, D, p, tab, "pq_lhaf");
+    if (rc) return rc;
+    if (D.nchunks == 0) return ctx->check(launch_fill((cplx*)out, nullptr, D.trivial, st), "fill");
 
     const int occ = occupancy_haf(loops, p.nl, p.rr);
     if (occ <= 0) return ctx->fail(PQ_EDEVICE, "pq_lhaf: occupancy query failed");
@@ -203,41 +264,8 @@ int pq_lhaf(pq_ctx* ctx, const pq_c128* A, int64_t lda, int32_t d, const pq_c128
     a.gc = pa.gc;
     a.tab = (const HafStep*)(ws + oT);
     a.partials = (double*)(ws + oP);
-    a.time_states = p.time_states;
     a.waves = (uint32_t)waves;
-    a.k = p.k;
-    a.nl = p.nl;
-    a.rr = p.rr;
-    a.nt = p.nt;
-    a.n_in = p.n_in;
-    a.lane_states = p.lane_states;
-    a.M = p.M;
-    a.N = N;
-    {
-        // square-and-multiply schedule of x^{N/2}
-        const int K = N / 2;
-        int top = 0;
-        while ((K >> (top + 1)) > 0) ++top;
-        int z = 0;
-        a.pw_nseg = 0;
-        a.pw_pack = 0;
-        for (int b = top - 1; b >= 0; --b) {
-            ++z;
-            if ((K >> b) & 1) {
-                a.pw_pack |= (uint32_t)z << (4 * a.pw_nseg++);
-                z = 0;
-            }
-        }
-        a.pw_tail = z;
-    }
-    for (int i = 0; i < p.k; ++i) {
-        a.rad[i] = (int8_t)p.rad[i];
-        a.rep[i] = (int8_t)p.rep[i];
-    }
-    double fact[kHafMaxN + 1];
-    fact[0] = 1.0;
-    for (int i = 1; i <= kHafMaxN; ++i) fact[i] = fact[i - 1] * (double)i;
-    for (int j = 0; j <= N / 2; ++j) a.coef[j] = 1.0 / (fact[j] * fact[N - 2 * j]);
+    a.d = D;
 
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (ctx->profiling) {
@@ -257,9 +285,157 @@ int pq_lhaf(pq_ctx* ctx, const pq_c128* A, int64_t lda, int32_t d, const pq_c128
     FinalArgs fa;
     fa.partials = a.partials;
     fa.count = (int32_t)waves;
-    fa.scale = ldexp(1.0, -(N - 1)) / (loops ? 1.0 : fact[N / 2]);
+    fa.scale = D.scale;
     fa.norm = 1.0;
     fa.perm = (cplx*)out;
     fa.amp = nullptr;
     return ctx->check(launch_final(fa, st), "hafnian final");
+}
+
+int pq_lhaf_many(pq_ctx* ctx, const pq_c128* A, int64_t lda, int32_t d, const pq_c128* gamma, const int32_t* reps,
+                 int32_t npat, pq_c128* out, void* stream) {
+    if (!ctx) return PQ_EINVAL;
+    ctx->clear_error();
+    if (d < 0 || npat < 0) return ctx->fail(PQ_EINVAL, "pq_lhaf_many: negative size");
+    if (npat == 0) return PQ_OK;
+    if (!out || (d > 0 && !reps)) return ctx->fail(PQ_EINVAL, "pq_lhaf_many: NULL reps or out");
+    const bool loops = gamma != nullptr;
+    std::vector<HafDesc> descs((size_t)npat);
+    std::vector<HafPlan> plans((size_t)npat);
+    std::vector<int32_t> modes;
+    std::vector<int64_t> mode_off((size_t)npat, 0);
+    std::vector<HafStep> tabs;
+    std::map<std::vector<int>, int64_t> tab_of;    // inner radices -> table offset
+    bool any = false;
+    int64_t ac = 0, gcn = 0;
+    for (int q = 0; q < npat; ++q) {
+        const int32_t* r = reps + (size_t)q * d;
+        int N = 0;
+        int rc = check_reps(ctx, r, d, &N, "pq_lhaf_many");
+        if (rc) return rc;
+        std::vector<HafStep> tab;
+        rc = describe(ctx, r, d, N, loops, descs[q], plans[q], tab, "pq_lhaf_many");
+        if (rc) return rc;
+        if (descs[q].nchunks == 0) continue;
+        any = true;
+        const HafPlan& p = plans[q];
+        HafDesc& D = descs[q];
+        std::vector<int> sig(p.rad + p.to, p.rad + p.to + p.n_in);
+        auto it = tab_of.find(sig);
+        if (it == tab_of.end()) {
+            it = tab_of.emplace(sig, (int64_t)tabs.size()).first;
+            tabs.insert(tabs.end(), tab.begin(), tab.end());
+        }
+        D.tab_off = it->second;
+        D.ac_off = ac;
+        D.gc_off = gcn;
+        ac += (int64_t)p.k * p.k;
+        gcn += p.k;
+        mode_off[q] = (int64_t)modes.size();
+        modes.insert(modes.end(), p.mode, p.mode + p.k);
+    }
+    if (any && (!A || lda < d)) return ctx->fail(PQ_EINVAL, "pq_lhaf_many: NULL matrix or lda < d");
+    // chunks per class (lane digits, register digit): one workgroup of four
+    // chunks per pattern at least; about 16 wavefronts per CU per class
+    std::map<std::pair<int, int>, std::vector<int>> classes;
+    for (int q = 0; q < npat; ++q)
+        if (descs[q].nchunks) classes[std::make_pair(descs[q].nl, descs[q].rr)].push_back(q);
+    std::vector<HafChunk> chunks;
+    std::vector<std::tuple<int, int, int, int>> launches;   // nl, rr, first block, blocks
+    int slots = 0;
+    for (auto& kv : classes) {
+        uint64_t total = 0;
+        for (int q : kv.second) total += descs[q].time_states;
+        const uint64_t target = (uint64_t)ctx->num_cu * 16;
+        uint64_t len = (total + target - 1) / target;
+        if (len < kHafMinChunk) len = kHafMinChunk;
+        const int first = (int)(chunks.size() / kWavesPerBlock);
+        for (int q : kv.second) {
+            HafDesc& D = descs[q];
+            uint64_t n = (D.time_states + len - 1) / len;
+            n = (n + kWavesPerBlock - 1) / kWavesPerBlock * kWavesPerBlock;
+            D.slot_base = slots;
+            D.nchunks = (int32_t)n;
+            for (uint64_t c = 0; c < n; ++c) {
+                HafChunk ch;
+                ch.pat = q;
+                ch.slot = slots + (int32_t)c;
+                ch.start = c * len;
+                ch.count = c * len < D.time_states ? std::min(len, D.time_states - c * len) : 0;
+                chunks.push_back(ch);
+            }
+            slots += (int)n;
+        }
+        launches.emplace_back(kv.first.first, kv.first.second, first, (int)(chunks.size() / kWavesPerBlock) - first);
+    }
+    DeviceGuard guard(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    Carve cv;
+    auto sz = [](size_t n) { return std::max<size_t>(1, n); };
+    const size_t oD = cv.take(sizeof(HafDesc) * (size_t)npat);
+    const size_t oC = cv.take(sizeof(HafChunk) * sz(chunks.size()));
+    const size_t oM = cv.take(sizeof(int32_t) * sz(modes.size()));
+    const size_t oMo = cv.take(sizeof(int64_t) * (size_t)npat);
+    const size_t oT = cv.take(sizeof(HafStep) * sz(tabs.size()));
+    const size_t upload = cv.off;
+    const size_t oA = cv.take(sizeof(cplx) * sz((size_t)ac));
+    const size_t oG = cv.take(sizeof(cplx) * sz((size_t)gcn));
+    const size_t oP = cv.take(sizeof(double) * 4 * sz((size_t)slots));
+    char* ws = (char*)ctx->workspace(cv.off);
+    if (!ws) return PQ_ENOMEM;
+    char* stage = (char*)ctx->staging(upload);
+    if (!stage) return PQ_ENOMEM;
+    memset(stage, 0, upload);
+    memcpy(stage + oD, descs.data(), sizeof(HafDesc) * descs.size());
+    if (!chunks.empty()) memcpy(stage + oC, chunks.data(), sizeof(HafChunk) * chunks.size());
+    if (!modes.empty()) memcpy(stage + oM, modes.data(), sizeof(int32_t) * modes.size());
+    memcpy(stage + oMo, mode_off.data(), sizeof(int64_t) * mode_off.size());
+    if (!tabs.empty()) memcpy(stage + oT, tabs.data(), sizeof(HafStep) * tabs.size());
+    int rc = ctx->upload(ws, stage, upload, st);
+    if (rc) return rc;
+    const HafDesc* d_desc = (const HafDesc*)(ws + oD);
+    if (any) {
+        HafManyPrepArgs pa;
+        pa.A = (const cplx*)A;
+        pa.lda = lda;
+        pa.gamma = (const cplx*)gamma;
+        pa.descs = d_desc;
+        pa.modes = (const int32_t*)(ws + oM);
+        pa.mode_off = (const int64_t*)(ws + oMo);
+        pa.Ac = (cplx*)(ws + oA);
+        pa.gc = (cplx*)(ws + oG);
+        rc = ctx->check(launch_haf_many_prep(pa, npat, st), "hafnian prep");
+        if (rc) return rc;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (ctx->profiling) {
+            e0 = ctx->take_event();
+            e1 = ctx->take_event();
+            if (!e0 || !e1) return ctx->fail(PQ_EDEVICE, "profile: hipEventCreate failed");
+            rc = ctx->check(hipEventRecord(e0, st), "profile: record");
+            if (rc) return rc;
+        }
+        for (const auto& L : launches) {
+            HafManyArgs ma;
+            ma.descs = d_desc;
+            ma.chunks = (const HafChunk*)(ws + oC) + (size_t)std::get<2>(L) * kWavesPerBlock;
+            ma.Ac = (const cplx*)(ws + oA);
+            ma.gc = (const cplx*)(ws + oG);
+            ma.tab = (const HafStep*)(ws + oT);
+            ma.partials = (double*)(ws + oP);
+            rc = ctx->check(launch_haf_many(loops, std::get<0>(L), std::get<1>(L), ma, std::get<3>(L), st),
+                            "hafnian sweep");
+            if (rc) return rc;
+        }
+        if (ctx->profiling) {
+            rc = ctx->check(hipEventRecord(e1, st), "profile: record");
+            if (rc) return rc;
+            ctx->ev_used.emplace_back(e0, e1);
+        }
+    }
+    HafManyFinalArgs fa;
+    fa.descs = d_desc;
+    fa.partials = (const double*)(ws + oP);
+    fa.npat = npat;
+    fa.out = (cplx*)out;
+    return ctx->check(launch_haf_many_final(fa, st), "hafnian final");
 }

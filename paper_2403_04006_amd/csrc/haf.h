@@ -64,13 +64,10 @@ struct HafPrepArgs {
     cplx* gc;                         // [k]
 };
 
-struct HafArgs {
-    const cplx* Ac;                   // [k][k]
-    const cplx* gc;                   // [k]
-    const HafStep* tab;               // [2][M]: forward block, reflected block
-    double* partials;                 // [waves][4] double-double per wavefront
+// Plan of one loop hafnian sweep: digits, term polynomial and (batched path)
+// the pattern's place in the arenas.
+struct HafDesc {
     uint64_t time_states;
-    uint32_t waves;
     int32_t k, nl, nt, n_in;          // modes, lane digits, time digits, inner time digits
     int32_t rr;                       // radix of the register digit (digit nl), 1: none
     int32_t lane_states;
@@ -85,6 +82,58 @@ struct HafArgs {
     int8_t rad[kHafMaxModes];         // radix per digit
     int8_t rep[kHafMaxModes];         // r per digit
     double coef[kHafMaxN / 2 + 1];    // 1 / (j! (N - 2j)!) (loops)
+    // batched path
+    int64_t ac_off;                   // complex elements into the Ac arena
+    int64_t gc_off;                   // complex elements into the gc arena
+    int64_t tab_off;                  // entries into the step-table arena
+    int32_t slot_base;                // first partial slot
+    int32_t nchunks;                  // 0: trivial pattern (value below)
+    double scale;                     // 2^{-(N-1)}, / (N/2)! without loops
+    cplx trivial;
+};
+
+struct HafArgs {
+    const cplx* Ac;                   // [k][k]
+    const cplx* gc;                   // [k]
+    const HafStep* tab;               // [2][M]: forward block, reflected block
+    double* partials;                 // [waves][4] double-double per wavefront
+    uint32_t waves;
+    HafDesc d;
+};
+
+// Batched path: chunks of the patterns' time ranges, four consecutive chunks
+// (one workgroup) per pattern; count 0 pads a group.
+struct HafChunk {
+    int32_t pat;
+    int32_t slot;
+    uint64_t start, count;
+};
+
+struct HafManyArgs {
+    const HafDesc* descs;
+    const HafChunk* chunks;           // 4 per workgroup
+    const cplx* Ac;                   // arenas
+    const cplx* gc;
+    const HafStep* tab;
+    double* partials;                 // [slots][4]
+};
+
+struct HafManyPrepArgs {
+    const cplx* A;
+    int64_t lda;
+    const cplx* gamma;                // may be null
+    const HafDesc* descs;
+    const int32_t* modes;             // per pattern, k modes in digit order, at mode_off[p]
+    const int64_t* mode_off;
+    cplx* Ac;
+    cplx* gc;
+};
+
+struct HafManyFinalArgs {
+    const HafDesc* descs;
+    const double* partials;
+    int32_t npat;
+    cplx* out;
 };
 
 hipError_t launch_haf_prep(const HafPrepArgs& a, hipStream_t s);
@@ -92,5 +141,8 @@ hipError_t launch_haf_prep(const HafPrepArgs& a, hipStream_t s);
 // rr in 1..3.
 hipError_t launch_haf(bool loops, int nl, int rr, const HafArgs& a, int grid, hipStream_t s);
 int occupancy_haf(bool loops, int nl, int rr);
+hipError_t launch_haf_many_prep(const HafManyPrepArgs& a, int npat, hipStream_t s);
+hipError_t launch_haf_many(bool loops, int nl, int rr, const HafManyArgs& a, int blocks, hipStream_t s);
+hipError_t launch_haf_many_final(const HafManyFinalArgs& a, hipStream_t s);
 
 }  // namespace pq

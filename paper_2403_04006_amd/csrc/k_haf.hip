@@ -42,29 +42,32 @@ __device__ __forceinline__ void csqr(cplx& p) {
     p.re = __builtin_fma(p.re, p.re, -t);
 }
 
-// One wavefront sweeps [start, start + count) of the time states; lanes hold
-// the lane digits.  NL: lane digits; RR: radix of the register digit (1: none)
-// whose RR values every lane evaluates at each step; LOOP: loop weights.
-template <int NL, int RR, bool LOOP>
-__global__ __launch_bounds__(kBlock) void haf_kernel(const HafArgs a) {
-    constexpr int TO = NL + (RR > 1 ? 1 : 0);   // first time digit
-    // sTT[t][s] = A[time s][time t]: lane s adds dX times it to T_s when
-    // time digit t moves
-    __shared__ cplx sTT[kHafMaxTime][kHafMaxTime];
+// sTT[t][s] = A[time s][time t] of one pattern (zero outside): lane s adds dX
+// times it to T_s when time digit t moves.  Every thread of the workgroup.
+template <int NL, int RR>
+__device__ __forceinline__ void haf_fill_tt(const HafDesc& a, const cplx* Ac, cplx (*sTT)[kHafMaxTime]) {
+    constexpr int TO = NL + (RR > 1 ? 1 : 0);
     const int k = a.k, nt = a.nt;
     for (int e = (int)threadIdx.x; e < kHafMaxTime * kHafMaxTime; e += kBlock) {
         const int t = e / kHafMaxTime, s = e - t * kHafMaxTime;
         cplx v{0.0, 0.0};
-        if (t < nt && s < nt) v = a.Ac[(size_t)(TO + s) * (size_t)k + (TO + t)];
+        if (t < nt && s < nt) v = Ac[(size_t)(TO + s) * (size_t)k + (TO + t)];
         sTT[t][s] = v;
     }
-    __syncthreads();
-    const uint32_t wave = wave_id_uniform();
-    if (wave >= a.waves) return;
+}
+
+// One wavefront sweeps [start, start + count) of the time states of one
+// pattern; lanes hold the lane digits.  NL: lane digits; RR: radix of the
+// register digit (1: none) whose RR values every lane evaluates at each
+// step; LOOP: loop weights.  Returns the wavefront's double-double sum (in
+// lane 0).
+template <int NL, int RR, bool LOOP>
+__device__ __forceinline__ cdd haf_sweep(const HafDesc& a, const cplx* Ac, const cplx* gc, const HafStep* tabp,
+                                         const cplx (*sTT)[kHafMaxTime], uint64_t start, uint64_t count) {
+    constexpr int TO = NL + (RR > 1 ? 1 : 0);   // first time digit
+    const int k = a.k, nt = a.nt;
     const int lane = (int)(threadIdx.x & 63);
     const int sl = lane & (kHafMaxTime - 1);   // lanes 32..63 mirror lanes 0..31
-    uint64_t start, count;
-    split_range(a.time_states, a.waves, wave, start, count);
 
     // lane digits: X_j = r_j - 2 d_j and their weight (0 for idle lanes)
     double XL[NL];
@@ -82,7 +85,7 @@ __global__ __launch_bounds__(kBlock) void haf_kernel(const HafArgs a) {
     }
     // sum over lane digits j of A[row][j] X_j
     auto lane_dot = [&](int row) {
-        const cplx* r = a.Ac + (size_t)row * (size_t)k;
+        const cplx* r = Ac + (size_t)row * (size_t)k;
         cplx L{0.0, 0.0};
 #pragma unroll
         for (int j = 0; j < NL; ++j) cfma_to(L, XL[j], r[j]);
@@ -93,7 +96,7 @@ __global__ __launch_bounds__(kBlock) void haf_kernel(const HafArgs a) {
 #pragma unroll
     for (int i = 0; i < NL; ++i) {
         cfma_to(qLL, XL[i], lane_dot(i));
-        cfma_to(lL, XL[i], a.gc[i]);
+        cfma_to(lL, XL[i], gc[i]);
     }
     // register digit: values X_d = r - 2d, weights, and the constant parts
     // (X_d^2 / 2) A_rr of x and X_d gamma_r of l
@@ -101,8 +104,8 @@ __global__ __launch_bounds__(kBlock) void haf_kernel(const HafArgs a) {
     cplx cR[RR];
     cplx uL{0.0, 0.0}, gR{0.0, 0.0};
     if constexpr (RR > 1) {
-        const cplx arr = a.Ac[(size_t)NL * (size_t)k + NL];
-        gR = a.gc[NL];
+        const cplx arr = Ac[(size_t)NL * (size_t)k + NL];
+        gR = gc[NL];
         uL = lane_dot(NL);
 #pragma unroll
         for (int d = 0; d < RR; ++d) {
@@ -214,8 +217,8 @@ __global__ __launch_bounds__(kBlock) void haf_kernel(const HafArgs a) {
             const double X = (double)(a.rep[TO + t] - 2 * g);
             cfma_to(T, X, sTT[t][sl]);
             cfma_to(qLT, X, lane_dot(TO + t));
-            cfma_to(lT, X, a.gc[TO + t]);
-            if constexpr (RR > 1) cfma_to(U, X, a.Ac[(size_t)(TO + t) * (size_t)k + NL]);
+            cfma_to(lT, X, gc[TO + t]);
+            if constexpr (RR > 1) cfma_to(U, X, Ac[(size_t)(TO + t) * (size_t)k + NL]);
             if (t == lane) xm = X;
         };
         double wh = 1.0;
@@ -238,13 +241,13 @@ __global__ __launch_bounds__(kBlock) void haf_kernel(const HafArgs a) {
         }
         cplx x{0.5 * (qLL.re + 2.0 * qLT.re + tt.re), 0.5 * (qLL.im + 2.0 * qLT.im + tt.im)};
         cplx l{lL.re + lT.re, lL.im + lT.im};
-        const HafStep* tab = refl ? a.tab + M : a.tab;
+        const HafStep* tab = refl ? tabp + M : tabp;
         terms(x, l, cplx{uL.re + U.re, uL.im + U.im}, wh * tab[pos0].w);
         for (int p = pos0 + 1; p < pos0 + len; ++p) {
             const HafStep e = tab[p];
             const int t = e.t;
             const double dx = (double)e.dx;
-            const cplx* row = a.Ac + (size_t)(TO + t) * (size_t)k;
+            const cplx* row = Ac + (size_t)(TO + t) * (size_t)k;
             // v_t before the move: lane part + T_t (held by lane t)
             const cplx L = lane_dot(TO + t);
             const double vre = L.re + readlane_d(T.re, t);
@@ -254,21 +257,96 @@ __global__ __launch_bounds__(kBlock) void haf_kernel(const HafArgs a) {
             x.re = __builtin_fma(dx, vre, __builtin_fma(2.0, att.re, x.re));
             x.im = __builtin_fma(dx, vim, __builtin_fma(2.0, att.im, x.im));
             if constexpr (RR > 1) cfma_to(U, dx, row[NL]);
-            if constexpr (LOOP) cfma_to(l, dx, a.gc[TO + t]);
+            if constexpr (LOOP) cfma_to(l, dx, gc[TO + t]);
             cfma_to(T, dx, sTT[t][sl]);
             terms(x, l, cplx{uL.re + U.re, uL.im + U.im}, wh * e.w);
         }
         s = seg_end;
     }
-    cdd v = wave_reduce(to_cdd(cplx{acc.re * wl, acc.im * wl}));
-    if (lane == 0) {
-        double* o = a.partials + 4 * (size_t)wave;
-        o[0] = v.re.hi;
-        o[1] = v.re.lo;
-        o[2] = v.im.hi;
-        o[3] = v.im.lo;
+    return wave_reduce(to_cdd(cplx{acc.re * wl, acc.im * wl}));
+}
+
+__device__ __forceinline__ void store_partial(double* o, const cdd& v) {
+    o[0] = v.re.hi;
+    o[1] = v.re.lo;
+    o[2] = v.im.hi;
+    o[3] = v.im.lo;
+}
+
+// One pattern: the time states split evenly over a.waves wavefronts.
+template <int NL, int RR, bool LOOP>
+__global__ __launch_bounds__(kBlock) void haf_kernel(const HafArgs a) {
+    __shared__ cplx sTT[kHafMaxTime][kHafMaxTime];
+    haf_fill_tt<NL, RR>(a.d, a.Ac, sTT);
+    __syncthreads();
+    const uint32_t wave = wave_id_uniform();
+    if (wave >= a.waves) return;
+    uint64_t start, count;
+    split_range(a.d.time_states, a.waves, wave, start, count);
+    const cdd v = haf_sweep<NL, RR, LOOP>(a.d, a.Ac, a.gc, a.tab, sTT, start, count);
+    if ((threadIdx.x & 63) == 0) store_partial(a.partials + 4 * (size_t)wave, v);
+}
+
+// Many patterns: workgroup b sweeps chunks 4b..4b+3, all of one pattern.
+template <int NL, int RR, bool LOOP>
+__global__ __launch_bounds__(kBlock) void haf_many_kernel(const HafManyArgs a) {
+    __shared__ cplx sTT[kHafMaxTime][kHafMaxTime];
+    const int pat = __builtin_amdgcn_readfirstlane(a.chunks[(size_t)blockIdx.x * kWavesPerBlock].pat);
+    const HafDesc& J = a.descs[pat];
+    const cplx* Ac = a.Ac + J.ac_off;
+    haf_fill_tt<NL, RR>(J, Ac, sTT);
+    __syncthreads();
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const HafChunk ch = a.chunks[(size_t)blockIdx.x * kWavesPerBlock + wv];
+    cdd v{{0.0, 0.0}, {0.0, 0.0}};
+    if (ch.count > 0) v = haf_sweep<NL, RR, LOOP>(J, Ac, a.gc + J.gc_off, a.tab + J.tab_off, sTT, ch.start, ch.count);
+    if ((threadIdx.x & 63) == 0) store_partial(a.partials + 4 * (size_t)ch.slot, v);
+}
+
+// Compact matrices and loop weights of every pattern: workgroup p builds
+// pattern p's, from the upper triangle of A.
+__global__ __launch_bounds__(kBlock) void haf_many_prep_kernel(const HafManyPrepArgs a) {
+    const int p = (int)blockIdx.x;
+    const HafDesc& J = a.descs[p];
+    if (J.nchunks == 0) return;
+    const int k = J.k;
+    const int32_t* mode = a.modes + a.mode_off[p];
+    cplx* Ac = a.Ac + J.ac_off;
+    for (int e = (int)threadIdx.x; e < k * k + k; e += kBlock) {
+        if (e < k * k) {
+            int mi = mode[e / k], mj = mode[e - (e / k) * k];
+            if (mi > mj) {
+                const int t = mi;
+                mi = mj;
+                mj = t;
+            }
+            Ac[e] = a.A[(size_t)mi * (size_t)a.lda + mj];
+        } else {
+            const int i = e - k * k;
+            a.gc[J.gc_off + i] = a.gamma ? a.gamma[mode[i]] : cplx{0.0, 0.0};
+        }
     }
 }
+
+// Every pattern's value: its slots added in slot order, then scaled (one
+// thread per pattern; trivial patterns take their value).
+__global__ __launch_bounds__(kBlock) void haf_many_final_kernel(const HafManyFinalArgs a) {
+    const int p = (int)(blockIdx.x * kBlock + threadIdx.x);
+    if (p >= a.npat) return;
+    const HafDesc& J = a.descs[p];
+    if (J.nchunks == 0) {
+        a.out[p] = J.trivial;
+        return;
+    }
+    const double* o = a.partials + 4 * (size_t)J.slot_base;
+    cdd s{{o[0], o[1]}, {o[2], o[3]}};
+    for (int c = 1; c < J.nchunks; ++c) {
+        const double* q = o + 4 * (size_t)c;
+        s = cdd_add(s, cdd{{q[0], q[1]}, {q[2], q[3]}});
+    }
+    a.out[p] = cplx{(s.re.hi + s.re.lo) * J.scale, (s.im.hi + s.im.lo) * J.scale};
+}
+
 
 hipError_t launch_haf_prep(const HafPrepArgs& a, hipStream_t s) {
     const int n = a.k * a.k + a.k;
@@ -278,6 +356,12 @@ hipError_t launch_haf_prep(const HafPrepArgs& a, hipStream_t s) {
 }
 
 #define PQ_HAF_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7)
+
+template <int NL, int RR>
+static void launch_haf_many_nr(bool loops, const HafManyArgs& a, dim3 g, hipStream_t s) {
+    if (loops) hipLaunchKernelGGL((haf_many_kernel<NL, RR, true>), g, dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((haf_many_kernel<NL, RR, false>), g, dim3(kBlock), 0, s, a);
+}
 
 template <int NL, int RR>
 static void launch_haf_nr(bool loops, const HafArgs& a, dim3 g, hipStream_t s) {
@@ -321,6 +405,34 @@ int occupancy_haf(bool loops, int nl, int rr) {
         default: return 0;
     }
 #undef PQ_HAF_OCC
+}
+
+hipError_t launch_haf_many(bool loops, int nl, int rr, const HafManyArgs& a, int blocks, hipStream_t s) {
+    const dim3 g((unsigned)(blocks > 0 ? blocks : 1));
+    if (rr < 1 || rr > 3) return hipErrorInvalidValue;
+#define PQ_HAF_MANY_LAUNCH(NL)                                          \
+    case NL:                                                            \
+        if (rr == 1) launch_haf_many_nr<NL, 1>(loops, a, g, s);         \
+        else if (rr == 2) launch_haf_many_nr<NL, 2>(loops, a, g, s);    \
+        else launch_haf_many_nr<NL, 3>(loops, a, g, s);                 \
+        break;
+    switch (nl) {
+        PQ_HAF_CASES(PQ_HAF_MANY_LAUNCH)
+        default: return hipErrorInvalidValue;
+    }
+#undef PQ_HAF_MANY_LAUNCH
+    return hipGetLastError();
+}
+
+hipError_t launch_haf_many_prep(const HafManyPrepArgs& a, int npat, hipStream_t s) {
+    hipLaunchKernelGGL(haf_many_prep_kernel, dim3((unsigned)(npat > 0 ? npat : 1)), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_haf_many_final(const HafManyFinalArgs& a, hipStream_t s) {
+    const int blocks = (a.npat + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(haf_many_final_kernel, dim3((unsigned)(blocks > 0 ? blocks : 1)), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
 }
 
 }  // namespace pq

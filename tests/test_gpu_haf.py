@@ -202,7 +202,44 @@ def test_gbs_photon_shells_match_squeezed_statistics(eng):
         want = np.convolve(want, single)[:nmax + 1]
     for N in range(0, nmax + 1, 2):
         pats = [t for t in itertools.product(range(N + 1), repeat=d) if sum(t) == N]
-        outs = torch.cat([eng.lhaf(Bd, None, list(t)) for t in pats]).cpu().numpy()
+        outs = eng.lhaf_many(Bd, None, np.array(pats)).cpu().numpy()
         fact = np.array([math.prod(math.factorial(x) for x in t) for t in pats], dtype=np.float64)
         shell = float(np.sum(np.abs(outs) ** 2 / fact)) / float(np.prod(np.cosh(r)))
         assert abs(shell - want[N]) <= 1e-15 + 1e-12 * want[N], (N, shell, want[N])
+
+
+def test_many_patterns_match_single_calls_and_oracle(eng):
+    # uneven batch: trivial, odd, zero and (2, ..., 2) patterns, loops on
+    # and off; every value equals its single call (up to the order of the
+    # chunk sums) and, where small, the oracle
+    rng = np.random.default_rng(77)
+    d = 14
+    A = workloads.gbs_matrix(d, 8)
+    g = workloads.loop_vector(d, 8)
+    pats = [np.zeros(d, np.int64), np.eye(d, dtype=np.int64)[3], np.full(d, 2)]
+    for _ in range(37):
+        v = rng.integers(0, 3, d)
+        v[rng.random(d) < 0.4] = 0
+        pats.append(v)
+    pats = np.array(pats)
+    for gamma in (g, None):
+        many = eng.lhaf_many(dev(A), None if gamma is None else dev(gamma), pats).cpu().numpy()
+        for q, v in enumerate(pats):
+            single = gpu_lhaf(eng, A, gamma, v)
+            N = int(v.sum())
+            if gamma is None and N % 2:
+                assert many[q] == 0 and single == 0
+                continue
+            assert rel(many[q], single) <= 1e-12, (q, list(v))
+            if np.prod(v + 1) <= (1 << 16):
+                assert rel(many[q], oracle.lhaf_rep(A, gamma, v)) <= tol(N), (q, list(v))
+
+
+def test_many_argument_errors(eng):
+    import paper_2403_04006_amd as pq
+    A = dev(workloads.gbs_matrix(4, 0))
+    assert eng.lhaf_many(A, None, np.zeros((0, 4), np.int32)).numel() == 0
+    with pytest.raises(pq.PqError):
+        eng.lhaf_many(A, None, np.array([[1, 1, 0, 0], [1, -1, 0, 0]]))
+    with pytest.raises(ValueError):
+        eng.lhaf_many(A, None, np.array([1, 1, 0, 0]))
