@@ -394,6 +394,28 @@ def main() -> int:
             hafnian[name] = {"modes": dh, "repetitions": 2, "vertices": 2 * dh, "loops": gam is not None,
                              "gray_terms": hterms, "sweep_ms": ms / nl_, "wall_ms": tw * 1e3,
                              "terms_per_s": hterms / (ms / nl_ / 1e3)}
+        # a GBS probability table: every output with 16 photons in 6 modes
+        # (20349 repetition vectors) of the same kind of matrix, one batched
+        # call, against separate calls on a sample
+        import itertools
+        d6 = 6
+        A6 = torch.from_numpy(workloads.gbs_matrix(d6, 1)).to(dev)
+        pats6 = np.array([t for t in itertools.product(range(17), repeat=d6) if sum(t) == 16], dtype=np.int32)
+        eng.lhaf_many(A6, None, pats6)
+        torch.cuda.synchronize()
+        tw = time.perf_counter()
+        for _ in range(3):
+            eng.lhaf_many(A6, None, pats6)
+        torch.cuda.synchronize()
+        tmany = (time.perf_counter() - tw) / 3
+        tw = time.perf_counter()
+        for t in pats6[:500]:
+            eng.lhaf(A6, None, t)
+        torch.cuda.synchronize()
+        tsingle = (time.perf_counter() - tw) / 500
+        hafnian["table_16_in_6"] = {"patterns": int(len(pats6)), "wall_ms": tmany * 1e3,
+                                    "patterns_per_s": len(pats6) / tmany,
+                                    "separate_calls_patterns_per_s": 1.0 / tsingle}
         print(f"# hafnian: {hafnian}", file=sys.stderr, flush=True)
 
     cpu = None
