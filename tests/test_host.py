@@ -57,6 +57,8 @@ def test_null_arguments_are_rejected_without_a_device():
     d1, d2, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()
     assert lib.pq_autotune_last(None, pol, ctypes.byref(d1), ctypes.byref(d2), ctypes.byref(c)) == _lib.PQ_EINVAL
     assert lib.pq_lhaf(None, None, 0, 0, None, None, None, None) == _lib.PQ_EINVAL
+    assert lib.pq_lhaf_many(None, None, 0, 0, None, None, 0, None, None) == _lib.PQ_EINVAL
+    assert lib.pq_graph_enable(None, 1) == _lib.PQ_EINVAL
     lib.pq_destroy(None)
     assert lib.pq_last_error(None) == b""
 
