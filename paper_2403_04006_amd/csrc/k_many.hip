@@ -25,12 +25,14 @@ __global__ __launch_bounds__(64) void many_final_kernel(const ManyFinalArgs a) {
     const int sd = a.class_sd[cls];
     const double* base = a.partials + a.class_off[cls] + (size_t)a.pat_slot[p] * sd;
     if (J.op == kOpPerm) {
+        // thread t adds slots t, t + 64, ... in order, then a fixed butterfly
+        cdd s{{0.0, 0.0}, {0.0, 0.0}};
+        for (int k = t; k < J.nchunks; k += 64) {
+            const double* q = base + (size_t)k * sd;
+            s = cdd_add(s, cdd{{q[0], q[1]}, {q[2], q[3]}});
+        }
+        s = wave_reduce(s);
         if (t == 0) {
-            cdd s{{base[0], base[1]}, {base[2], base[3]}};
-            for (int k = 1; k < J.nchunks; ++k) {
-                const double* q = base + (size_t)k * sd;
-                s = cdd_add(s, cdd{{q[0], q[1]}, {q[2], q[3]}});
-            }
             const double re = (s.re.hi + s.re.lo) * J.scale;
             const double im = (s.im.hi + s.im.lo) * J.scale;
             if (a.perm) a.perm[J.out_offset] = cplx{re, im};
