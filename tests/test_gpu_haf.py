@@ -243,3 +243,47 @@ def test_many_argument_errors(eng):
         eng.lhaf_many(A, None, np.array([[1, 1, 0, 0], [1, -1, 0, 0]]))
     with pytest.raises(ValueError):
         eng.lhaf_many(A, None, np.array([1, 1, 0, 0]))
+
+
+def sum_condition(a, gv, reps, loops):
+    # sum |w P| / |sum w P| of the vertex-sign sum on a constant matrix (the
+    # cancellation the FP64 sum goes through; used for the error bound only)
+    import itertools
+    from math import comb
+    d, N = len(reps), sum(reps)
+    f = min((i for i in range(d) if reps[i] > 0), key=lambda i: reps[i])
+    J = N // 2
+    absum, tot = 0.0, 0j
+    for digs in itertools.product(*[range(reps[i] if i == f else reps[i] + 1) if reps[i] else range(1)
+                                    for i in range(d)]):
+        S = sum(reps[i] - 2 * digs[i] for i in range(d) if reps[i])
+        w = 1.0
+        for i in range(d):
+            if reps[i]:
+                w *= (-1) ** digs[i] * comb(reps[i] - 1 if i == f else reps[i], digs[i])
+        x, l = a * S * S / 2, gv * S
+        if loops:
+            P = sum(x ** j * l ** (N - 2 * j) / (math.factorial(j) * math.factorial(N - 2 * j)) for j in range(J + 1))
+        else:
+            P = x ** J / math.factorial(J)
+        absum += abs(w * P)
+        tot += w * P
+    return absum / abs(tot)
+
+
+@pytest.mark.parametrize("reps", [[32, 32], [1, 63], [20, 0, 44], [64], [8, 8, 8, 8]])
+def test_largest_vertex_count(eng, reps):
+    # N up to 64 (the limit) on few modes: radix-33, -45 and -64 digits, the
+    # power x^32 (squarings only); constant matrix against the Hermite form.
+    # The alternating sum cancels strongly here (condition ~1e11 at N = 64),
+    # so the bound is the FP64 rounding of the sum times its condition.
+    a, gv = 0.02 + 0.01j, 0.15 - 0.05j
+    d = len(reps)
+    N = sum(reps)
+    want = sum(math.factorial(N) / (math.factorial(j) * math.factorial(N - 2 * j) * 2 ** j) * a ** j * gv ** (N - 2 * j)
+               for j in range(N // 2 + 1))
+    got = gpu_lhaf(eng, np.full((d, d), a), np.full(d, gv), reps)
+    assert rel(got, want) <= 64 * 2.0 ** -52 * sum_condition(a, gv, reps, True)
+    want_haf = math.factorial(N) / (math.factorial(N // 2) * 2 ** (N // 2)) * a ** (N // 2)
+    got_haf = gpu_lhaf(eng, np.full((d, d), a), None, reps)
+    assert rel(got_haf, want_haf) <= 64 * 2.0 ** -52 * sum_condition(a, gv, reps, False)
