@@ -139,6 +139,37 @@ void haf_tables(const HafPlan& p, std::vector<HafStep>& tab) {
     }
 }
 
+// b_k = 1 / (2 h_k^2) for the floor(N/2) positive roots h_k of He_N, the
+// eigenvalues of the Jacobi matrix with zero diagonal and off-diagonal
+// sqrt(1), ..., sqrt(N-1): bisection on the Sturm count in long double.
+void hermite_factors(int N, double* b) {
+    // number of eigenvalues below x: negative pivots of T - x I
+    auto below = [N](long double x) {
+        int cnt = 0;
+        long double d = 1.0L;
+        for (int i = 0; i < N; ++i) {
+            d = -x - (i == 0 ? 0.0L : (long double)i / d);
+            if (d == 0.0L) d = -1e-4000L;
+            if (d < 0.0L) ++cnt;
+        }
+        return cnt;
+    };
+    const int J = N / 2;
+    const long double bound = 2.0L * sqrtl((long double)N) + 1.0L;
+    for (int k = 0; k < J; ++k) {
+        // the (N - J + k + 1)-th smallest eigenvalue (the positive ones)
+        const int want = N - J + k + 1;
+        long double lo = 0.0L, hi = bound;
+        for (int it = 0; it < 200; ++it) {
+            const long double mid = 0.5L * (lo + hi);
+            if (below(mid) >= want) hi = mid;
+            else lo = mid;
+        }
+        const long double h = 0.5L * (lo + hi);
+        b[k] = (double)(1.0L / (2.0L * h * h));
+    }
+}
+
 // Validate one repetition vector: N in *N, PQ_OK or an error status.
 int check_reps(pq_ctx* ctx, const int32_t* reps, int d, int* N, const char* who) {
     int n = 0;
@@ -198,8 +229,8 @@ int describe(pq_ctx* ctx, const int32_t* reps, int d, int N, bool loops, HafDesc
     double fact[kHafMaxN + 1];
     fact[0] = 1.0;
     for (int i = 1; i <= kHafMaxN; ++i) fact[i] = fact[i - 1] * (double)i;
-    for (int j = 0; j <= N / 2; ++j) D.coef[j] = 1.0 / (fact[j] * fact[N - 2 * j]);
-    D.scale = ldexp(1.0, -(N - 1)) / (loops ? 1.0 : fact[N / 2]);
+    if (loops) hermite_factors(N, D.hb);
+    D.scale = ldexp(1.0, -(N - 1)) / fact[N / 2];
     D.nchunks = 1;
     return PQ_OK;
 }

@@ -13,6 +13,10 @@
 //   q = X^T A X,  l = gamma^T X,
 //   P_N(q, l) = sum_{j=0}^{floor(N/2)} (q/2)^j l^{N-2j} / (j! (N-2j)!),
 //
+// evaluated as a product: with x = q/2, P_N = (-2x)^{N/2} He_N(l / sqrt(-2x)) / N!
+// (He_N the probabilists' Hermite polynomial), and pairing its real roots
+// +-h_k gives P_N = l^(N mod 2) prod_k (x + l^2 / (2 h_k^2)) / floor(N/2)!,
+//
 // with radix rho_f = r_f (d_f = 0..r_f - 1) and rho_i = r_i + 1 otherwise --
 // the digit structure of the generalised permanent sum.  Without loops
 // P_N = (q/2)^{N/2} / (N/2)! (zero for odd N).
@@ -81,7 +85,10 @@ struct HafDesc {
     uint32_t pw_pack;
     int8_t rad[kHafMaxModes];         // radix per digit
     int8_t rep[kHafMaxModes];         // r per digit
-    double coef[kHafMaxN / 2 + 1];    // 1 / (j! (N - 2j)!) (loops)
+    // loops: P_N(x, l) = l^(N mod 2) prod_{k < N/2} (x + hb[k] l^2) / (N/2)!,
+    // hb[k] = 1 / (2 h_k^2) over the positive roots h_k of the probabilists'
+    // Hermite polynomial He_N
+    double hb[kHafMaxN / 2];
     // batched path
     int64_t ac_off;                   // complex elements into the Ac arena
     int64_t gc_off;                   // complex elements into the gc arena

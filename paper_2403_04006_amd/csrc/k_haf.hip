@@ -125,8 +125,8 @@ __device__ __forceinline__ cdd haf_sweep(const HafDesc& a, const cplx* Ac, const
     cplx acc{0.0, 0.0};
     // acc += w sum_d WR[d] P_N(x_d, l_d) with x_d = x + X_d u + (X_d^2/2) A_rr
     // and l_d = l + X_d gamma_r, x = q / 2 over the other digits, u = (A X)_r
-    // (the 1 / (N/2)! of the loop-free case is applied once at the end).  The
-    // RR evaluations share every loop and coefficient load.
+    // (the common 1 / (N/2)! is applied once at the end).  The RR evaluations
+    // share every loop and coefficient load.
     auto terms = [&](const cplx& x, const cplx& l, const cplx& u, double w) {
         cplx xd[RR], p[RR];
 #pragma unroll
@@ -135,37 +135,36 @@ __device__ __forceinline__ cdd haf_sweep(const HafDesc& a, const cplx* Ac, const
             xd[d].im = __builtin_fma(XR[d], u.im, x.im + cR[d].im);
         }
         if constexpr (LOOP) {
-            // s_j = s_{j-1} y + c_j x^j = sum_{i<=j} c_i x^i y^{j-i}, y = l^2;
-            // two steps per trip, x^j always advanced (no selects)
-            cplx ld[RR], y[RR], xp[RR];
+            // P_N = l^(N mod 2) prod_k (x + hb[k] l^2) (the 1 / (N/2)! is
+            // applied at the end): two FMAs and a complex multiply per factor
+            cplx ld[RR], y[RR];
 #pragma unroll
             for (int d = 0; d < RR; ++d) {
                 ld[d].re = __builtin_fma(XR[d], gR.re, l.re);
                 ld[d].im = __builtin_fma(XR[d], gR.im, l.im);
                 y[d] = cmul(ld[d], ld[d]);
-                p[d] = cplx{a.coef[0], 0.0};
-                xp[d] = xd[d];
-            }
-            int j = 1;
-            for (; j < J; j += 2) {
-                const double c1 = a.coef[j], c2 = a.coef[j + 1];
-#pragma unroll
-                for (int d = 0; d < RR; ++d) {
-                    p[d] = cmul(p[d], y[d]);
-                    cfma_to(p[d], c1, xp[d]);
-                    xp[d] = cmul(xp[d], xd[d]);
-                    p[d] = cmul(p[d], y[d]);
-                    cfma_to(p[d], c2, xp[d]);
-                    xp[d] = cmul(xp[d], xd[d]);
+                if (J > 0) {
+                    p[d].re = __builtin_fma(a.hb[0], y[d].re, xd[d].re);
+                    p[d].im = __builtin_fma(a.hb[0], y[d].im, xd[d].im);
+                } else {
+                    p[d] = cplx{1.0, 0.0};
                 }
             }
-            if (j == J) {
-                const double c1 = a.coef[j];
+            int k = 1;
+            for (; k + 1 < J; k += 2) {
+                const double b1 = a.hb[k], b2 = a.hb[k + 1];
 #pragma unroll
                 for (int d = 0; d < RR; ++d) {
-                    p[d] = cmul(p[d], y[d]);
-                    cfma_to(p[d], c1, xp[d]);
+                    const cplx f1{__builtin_fma(b1, y[d].re, xd[d].re), __builtin_fma(b1, y[d].im, xd[d].im)};
+                    const cplx f2{__builtin_fma(b2, y[d].re, xd[d].re), __builtin_fma(b2, y[d].im, xd[d].im)};
+                    p[d] = cmul(p[d], cmul(f1, f2));
                 }
+            }
+            if (k < J) {
+                const double b1 = a.hb[k];
+#pragma unroll
+                for (int d = 0; d < RR; ++d)
+                    p[d] = cmul(p[d], cplx{__builtin_fma(b1, y[d].re, xd[d].re), __builtin_fma(b1, y[d].im, xd[d].im)});
             }
             if (N & 1) {
 #pragma unroll
