@@ -150,7 +150,10 @@ __device__ __forceinline__ cdd haf_sweep(const HafDesc& a, const cplx* Ac, const
                     p[d] = cplx{1.0, 0.0};
                 }
             }
+            // unrolled twice: the register allocator then keeps p in place
+            // instead of rotating it through copies every pair
             int k = 1;
+#pragma unroll 2
             for (; k + 1 < J; k += 2) {
                 const double b1 = a.hb[k], b2 = a.hb[k + 1];
 #pragma unroll
