@@ -139,10 +139,17 @@ void haf_tables(const HafPlan& p, std::vector<HafStep>& tab) {
     }
 }
 
-// b_k = 1 / (2 h_k^2) for the floor(N/2) positive roots h_k of He_N, the
+// Coefficients of the loop polynomial's product form.  With b_k =
+// 1 / (2 h_k^2) over the floor(N/2) positive roots h_k of He_N (the
 // eigenvalues of the Jacobi matrix with zero diagonal and off-diagonal
-// sqrt(1), ..., sqrt(N-1): bisection on the Sturm count in long double.
-void hermite_factors(int N, double* b) {
+// sqrt(1), ..., sqrt(N-1), found by bisection on the Sturm count in long
+// double), the factors (x + b_k y) are grouped four at a time, then a pair,
+// then a single, and each group is stored as the elementary symmetric
+// functions of its b's:
+//   quad: e1, e2, e3, e4 of prod (x + b y) = x^4 + e1 x^3 y + ... + e4 y^4
+//   pair: e1, e2;  single: b.
+// That is floor(N/2) values in all.
+void hermite_factors(int N, double* out) {
     // number of eigenvalues below x: negative pivots of T - x I
     auto below = [N](long double x) {
         int cnt = 0;
@@ -156,6 +163,7 @@ void hermite_factors(int N, double* b) {
     };
     const int J = N / 2;
     const long double bound = 2.0L * sqrtl((long double)N) + 1.0L;
+    long double b[kHafMaxN / 2];
     for (int k = 0; k < J; ++k) {
         // the (N - J + k + 1)-th smallest eigenvalue (the positive ones)
         const int want = N - J + k + 1;
@@ -166,8 +174,21 @@ void hermite_factors(int N, double* b) {
             else lo = mid;
         }
         const long double h = 0.5L * (lo + hi);
-        b[k] = (double)(1.0L / (2.0L * h * h));
+        b[k] = 1.0L / (2.0L * h * h);
     }
+    int k = 0;
+    for (; k + 4 <= J; k += 4) {
+        long double e[5] = {1.0L, 0.0L, 0.0L, 0.0L, 0.0L};
+        for (int i = 0; i < 4; ++i)
+            for (int j = i + 1; j >= 1; --j) e[j] += b[k + i] * e[j - 1];
+        for (int j = 0; j < 4; ++j) out[k + j] = (double)e[j + 1];
+    }
+    if (k + 2 <= J) {
+        out[k] = (double)(b[k] + b[k + 1]);
+        out[k + 1] = (double)(b[k] * b[k + 1]);
+        k += 2;
+    }
+    if (k < J) out[k] = (double)b[k];
 }
 
 // Validate one repetition vector: N in *N, PQ_OK or an error status.

@@ -85,9 +85,10 @@ struct HafDesc {
     uint32_t pw_pack;
     int8_t rad[kHafMaxModes];         // radix per digit
     int8_t rep[kHafMaxModes];         // r per digit
-    // loops: P_N(x, l) = l^(N mod 2) prod_{k < N/2} (x + hb[k] l^2) / (N/2)!,
-    // hb[k] = 1 / (2 h_k^2) over the positive roots h_k of the probabilists'
-    // Hermite polynomial He_N
+    // loops: P_N(x, l) = l^(N mod 2) prod_{k < N/2} (x + b_k l^2) / (N/2)!,
+    // b_k = 1 / (2 h_k^2) over the positive roots h_k of the probabilists'
+    // Hermite polynomial He_N; hb holds the factors grouped by four (then a
+    // pair, then a single) as elementary symmetric functions of their b's
     double hb[kHafMaxN / 2];
     // batched path
     int64_t ac_off;                   // complex elements into the Ac arena

@@ -135,43 +135,50 @@ __device__ __forceinline__ cdd haf_sweep(const HafDesc& a, const cplx* Ac, const
             xd[d].im = __builtin_fma(XR[d], u.im, x.im + cR[d].im);
         }
         if constexpr (LOOP) {
-            // P_N = l^(N mod 2) prod_k (x + hb[k] l^2) (the 1 / (N/2)! is
-            // applied at the end): two FMAs and a complex multiply per factor
-            cplx ld[RR], y[RR];
+            // P_N = l^(N mod 2) prod_k (x + b_k y), y = l^2 (the 1 / (N/2)!
+            // is applied at the end).  A group of four factors is
+            // x^4 + e1 x^3 y + e2 x^2 y^2 + e3 x y^3 + e4 y^4: the five
+            // monomials are formed once, then each group costs eight FMAs and
+            // a complex multiply.  A leftover pair is x^2 + e1 x y + e2 y^2, a
+            // leftover single x + b y.
+            const int nq = J >> 2, rem = J & 3;
 #pragma unroll
             for (int d = 0; d < RR; ++d) {
-                ld[d].re = __builtin_fma(XR[d], gR.re, l.re);
-                ld[d].im = __builtin_fma(XR[d], gR.im, l.im);
-                y[d] = cmul(ld[d], ld[d]);
-                if (J > 0) {
-                    p[d].re = __builtin_fma(a.hb[0], y[d].re, xd[d].re);
-                    p[d].im = __builtin_fma(a.hb[0], y[d].im, xd[d].im);
-                } else {
-                    p[d] = cplx{1.0, 0.0};
+                cplx ld;
+                ld.re = __builtin_fma(XR[d], gR.re, l.re);
+                ld.im = __builtin_fma(XR[d], gR.im, l.im);
+                const cplx y = cmul(ld, ld);
+                const cplx x2 = cmul(xd[d], xd[d]), xy = cmul(xd[d], y), y2 = cmul(y, y);
+                cplx pd{1.0, 0.0};
+                if (rem & 1) {
+                    const double b = a.hb[J - 1];
+                    pd = cplx{__builtin_fma(b, y.re, xd[d].re), __builtin_fma(b, y.im, xd[d].im)};
                 }
-            }
-            // unrolled twice: the register allocator then keeps p in place
-            // instead of rotating it through copies every pair
-            int k = 1;
-#pragma unroll 2
-            for (; k + 1 < J; k += 2) {
-                const double b1 = a.hb[k], b2 = a.hb[k + 1];
-#pragma unroll
-                for (int d = 0; d < RR; ++d) {
-                    const cplx f1{__builtin_fma(b1, y[d].re, xd[d].re), __builtin_fma(b1, y[d].im, xd[d].im)};
-                    const cplx f2{__builtin_fma(b2, y[d].re, xd[d].re), __builtin_fma(b2, y[d].im, xd[d].im)};
-                    p[d] = cmul(p[d], cmul(f1, f2));
+                if (rem >= 2) {
+                    const double e1 = a.hb[4 * nq], e2 = a.hb[4 * nq + 1];
+                    const cplx f{__builtin_fma(e2, y2.re, __builtin_fma(e1, xy.re, x2.re)),
+                                 __builtin_fma(e2, y2.im, __builtin_fma(e1, xy.im, x2.im))};
+                    pd = (rem & 1) ? cmul(pd, f) : f;
                 }
-            }
-            if (k < J) {
-                const double b1 = a.hb[k];
-#pragma unroll
-                for (int d = 0; d < RR; ++d)
-                    p[d] = cmul(p[d], cplx{__builtin_fma(b1, y[d].re, xd[d].re), __builtin_fma(b1, y[d].im, xd[d].im)});
-            }
-            if (N & 1) {
-#pragma unroll
-                for (int d = 0; d < RR; ++d) p[d] = cmul(p[d], ld[d]);
+                if (nq > 0) {
+                    const cplx m0 = cmul(x2, x2), m1 = cmul(x2, xy), m2 = cmul(xy, xy), m3 = cmul(xy, y2),
+                               m4 = cmul(y2, y2);
+                    auto quad = [&](int q) {
+                        const double* e = a.hb + 4 * q;
+                        return cplx{__builtin_fma(e[3], m4.re, __builtin_fma(e[2], m3.re,
+                                        __builtin_fma(e[1], m2.re, __builtin_fma(e[0], m1.re, m0.re)))),
+                                    __builtin_fma(e[3], m4.im, __builtin_fma(e[2], m3.im,
+                                        __builtin_fma(e[1], m2.im, __builtin_fma(e[0], m1.im, m0.im))))};
+                    };
+                    int q = 0;
+                    if (rem == 0) {
+                        pd = quad(0);
+                        q = 1;
+                    }
+                    for (; q < nq; ++q) pd = cmul(pd, quad(q));
+                }
+                if (N & 1) pd = cmul(pd, ld);
+                p[d] = pd;
             }
         } else {
             // x^K by uniform loops: per set bit below the top one, z squarings
