@@ -175,6 +175,7 @@ __device__ __forceinline__ cdd haf_sweep(const HafDesc& a, const cplx* Ac, const
                         pd = quad(0);
                         q = 1;
                     }
+#pragma unroll 2
                     for (; q < nq; ++q) pd = cmul(pd, quad(q));
                 }
                 if (N & 1) pd = cmul(pd, ld);
