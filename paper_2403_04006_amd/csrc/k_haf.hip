@@ -191,6 +191,7 @@ __device__ __forceinline__ cdd haf_sweep(const HafDesc& a, const cplx* Ac, const
             for (int i = 0; i < a.pw_nseg; ++i) {
                 const int z = (int)(pk & 15u);
                 pk >>= 4;
+#pragma unroll 2
                 for (int q = 0; q < z; ++q) {
 #pragma unroll
                     for (int d = 0; d < RR; ++d) csqr(p[d]);
@@ -198,6 +199,7 @@ __device__ __forceinline__ cdd haf_sweep(const HafDesc& a, const cplx* Ac, const
 #pragma unroll
                 for (int d = 0; d < RR; ++d) p[d] = cmul(p[d], xd[d]);
             }
+#pragma unroll 2
             for (int q = 0; q < a.pw_tail; ++q) {
 #pragma unroll
                 for (int d = 0; d < RR; ++d) csqr(p[d]);
