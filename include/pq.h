@@ -121,10 +121,10 @@ typedef struct {
 } pq_job;
 
 /*
- * pq_perm_batched -- all jobs in one stream-ordered submission (one persistent
- * work-queue launch for the Gray-code sums, captured into a HIP graph).
- * This path is switched off in this build: after validating its arguments it
- * returns PQ_EDEVICE.  pq_perm_many computes the same outputs.
+ * pq_perm_batched -- all jobs in one stream-ordered submission.  It runs them
+ * exactly as pq_perm_many below (static schedule; same validation, errors and
+ * outputs; HIP-graph replay and chunk autotuning as enabled on ctx).  A
+ * persistent work-queue schedule was built for it but is switched off.
  *   perm  device, complex, large enough for every job's outputs.
  *   amp   device, may be NULL; written for PQ_OP_PERM jobs only.
  * Output ranges of different jobs must not overlap (PQ_EINVAL otherwise).

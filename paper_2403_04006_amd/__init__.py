@@ -336,8 +336,8 @@ class Engine:
 
     def perm_batched(self, U: torch.Tensor, jobs: Sequence[dict], n_out: int | None = None,
                      with_amp: bool = True):
-        """The same jobs through the persistent work-queue entry point
-        (pq_perm_batched, switched off in this build: raises PqError)."""
+        """The same jobs through pq_perm_batched (the boundary's batched
+        call; it runs them on pq_perm_many's static schedule)."""
         return self._run_jobs(self._lib.pq_perm_batched, U, jobs, n_out, with_amp)
 
     # -------------------------------------------------------- pq_perm_grad

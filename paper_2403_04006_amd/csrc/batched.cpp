@@ -1,4 +1,5 @@
-// pq_perm_batched: planning of uneven jobs into per-class chunk queues, device
+// Persistent work-queue form of a batch of uneven jobs (switched off; see
+// pq_perm_batched below): planning into per-class chunk queues, device
 // buffers, and the launch sequence (captured once into a hipGraph and replayed
 // while the batch description and pointers stay the same).
 #include <hip/hip_runtime.h>
@@ -386,28 +387,17 @@ void pq_release_batch_cache(pq_ctx* ctx) {
 // batch of 495 small permanents through it did not complete on the device,
 // while CPU emulation of the same kernels and host planning (sequential and
 // with concurrent wavefronts) completes with correct results, so no mistake
-// in this code that would explain it has been shown.  Until one is,
-// pq_perm_batched reports PQ_EDEVICE after validating its arguments;
-// pq_perm_many computes the same jobs with a static schedule.
-static int perm_batched_queue(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m,
-                              const pq_job* jobs, int32_t njobs,
-                              pq_c128* perm, pq_c128* amp, void* stream);
+// in this code that would explain it has been shown.  Until one is, nothing
+// calls it: pq_perm_batched runs its jobs on the static schedule of
+// pq_perm_many (same validation, same outputs).
+[[maybe_unused]] static int perm_batched_queue(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m,
+                                               const pq_job* jobs, int32_t njobs,
+                                               pq_c128* perm, pq_c128* amp, void* stream);
 
 int pq_perm_batched(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m,
                     const pq_job* jobs, int32_t njobs,
                     pq_c128* perm, pq_c128* amp, void* stream) {
-    if (!ctx) return PQ_EINVAL;
-    ctx->clear_error();
-    if (m < 0 || njobs < 0) return ctx->fail(PQ_EINVAL, "pq_perm_batched: negative size");
-    if (njobs == 0) return PQ_OK;
-    if (!jobs || !perm) return ctx->fail(PQ_EINVAL, "pq_perm_batched: NULL jobs or perm");
-    if (m > 0 && (!U || ldu < m)) return ctx->fail(PQ_EINVAL, "pq_perm_batched: NULL U or ldu < m");
-    std::vector<int64_t> key;
-    int rc = pq_validate_jobs(ctx, m, jobs, njobs, key);
-    if (rc) return rc;
-    if (getenv("PQ_BATCH_QUEUE") == nullptr)
-        return ctx->fail(PQ_EDEVICE, "pq_perm_batched: the persistent work-queue path is disabled in this build");
-    return perm_batched_queue(ctx, U, ldu, m, jobs, njobs, perm, amp, stream);
+    return pq_perm_many(ctx, U, ldu, m, jobs, njobs, perm, amp, stream);
 }
 
 static int perm_batched_queue(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m,

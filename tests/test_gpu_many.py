@@ -226,5 +226,11 @@ def test_argument_errors(eng):
         eng.perm_many(U, [{"op": 0, "rows": [(7, 1)], "cols": [(0, 1)]}])
     with pytest.raises(pq.PqError):
         eng.perm_many(U, [{"op": 1, "rows": [(1, 1)], "cols": [(0, 1)], "out": 0}])
+    # the boundary's batched call runs the same schedule: same errors, same values
     with pytest.raises(pq.PqError):
-        eng.perm_batched(U, [perm_job([1, 0, 0, 0], [1, 0, 0, 0])])     # switched-off path
+        eng.perm_batched(U, [{"op": 0, "rows": [(7, 1)], "cols": [(0, 1)]}])
+    jobs = [perm_job([1, 1, 0, 0], [0, 1, 1, 0]), perm_job([2, 0, 1, 0], [0, 1, 0, 2])]
+    a, _ = eng.perm_batched(U, jobs)
+    b, _ = eng.perm_many(U, jobs)
+    torch.cuda.synchronize()
+    assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
