@@ -30,17 +30,20 @@ __global__ __launch_bounds__(kBlock) void all_sums_kernel(const AllSumsArgs a) {
     if (i == 0) a.w[d] = w;
 }
 
-// part += sum over the tile's terms dd of sP[dd] prod_{q<NS} cd[off[q]]: the
-// reads of a term go out four at a time ahead of their products (no
-// per-factor waits or branches), into two alternating product chains.
+// part += sum over the tile's terms dd of sP[dd] prod_{q<NS} cd[off[q]], with
+// cd = sC + dd * kAllMaxModes: the reads of a term go out four at a time ahead
+// of their products (no per-factor waits or branches), into two alternating
+// product chains; the term loop is unrolled four times, so consecutive terms'
+// reads differ by immediate offsets instead of per-factor address updates.
 template <int NS, int NMAX>
-__device__ __forceinline__ void suffix_tile(const cplx* sC, const cplx* sPw, const int (&off)[NMAX], int m, int nt,
+__device__ __forceinline__ void suffix_tile(const cplx* sC, const cplx* sPw, const int (&off)[NMAX], int nt,
                                             cplx& part) {
+#pragma unroll 4
     for (int dd = 0; dd < nt; ++dd) {
-        const cplx* cd = sC + dd * m;
+        const cplx* cd = sC + dd * kAllMaxModes;
         cplx p = sPw[dd];
         if constexpr (NS > 0) {
-            cplx p2{1.0, 0.0};
+            cplx p2;
 #pragma unroll
             for (int q0 = 0; q0 < NS; q0 += 4) {
                 cplx f[4];
@@ -50,7 +53,8 @@ __device__ __forceinline__ void suffix_tile(const cplx* sC, const cplx* sPw, con
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     if (q0 + k < NS) {
-                        if (k & 1) p2 = cmul(p2, f[k]);
+                        if (q0 + k == 1) p2 = f[k];
+                        else if (k & 1) p2 = cmul(p2, f[k]);
                         else p = cmul(p, f[k]);
                     }
                 }
@@ -63,11 +67,11 @@ __device__ __forceinline__ void suffix_tile(const cplx* sC, const cplx* sPw, con
 }
 
 template <int NMAX, int NS = 0>
-__device__ __forceinline__ void suffix_dispatch(int ns, const cplx* sC, const cplx* sPw, const int (&off)[NMAX], int m,
-                                                int nt, cplx& part) {
+__device__ __forceinline__ void suffix_dispatch(int ns, const cplx* sC, const cplx* sPw, const int (&off)[NMAX], int nt,
+                                                cplx& part) {
     if constexpr (NS <= NMAX) {
-        if (ns == NS) suffix_tile<NS, NMAX>(sC, sPw, off, m, nt, part);
-        else suffix_dispatch<NMAX, NS + 1>(ns, sC, sPw, off, m, nt, part);
+        if (ns == NS) suffix_tile<NS, NMAX>(sC, sPw, off, nt, part);
+        else suffix_dispatch<NMAX, NS + 1>(ns, sC, sPw, off, nt, part);
     }
 }
 
@@ -143,12 +147,17 @@ __global__ __launch_bounds__(kBlock, 4) void all_out_kernel(const AllOutArgs a) 
     for (uint64_t d0 = 0; d0 < a.terms; d0 += kAllTile) {
         const int nt = (int)((a.terms - d0) < (uint64_t)kAllTile ? (a.terms - d0) : (uint64_t)kAllTile);
         __syncthreads();
-        for (int e = tid; e < nt * m; e += kBlock) sC[e] = a.csum[d0 * (uint64_t)m + e];
+        // term dd's column sums at sC[dd * kAllMaxModes ...]: a fixed stride,
+        // so the suffix loop reaches the next terms by immediate offsets
+        for (int e = tid; e < nt * kAllMaxModes; e += kBlock) {
+            const int dd = e / kAllMaxModes, r = e - dd * kAllMaxModes;
+            if (r < m) sC[e] = a.csum[(d0 + (uint64_t)dd) * (uint64_t)m + (uint64_t)r];
+        }
         for (int e = tid; e < nt; e += kBlock) sW[e] = a.w[d0 + e];
         __syncthreads();
         // w_j prod_{q<L} c_{r_q} for the tile's terms, lane j
         if (lane < nt) {
-            const cplx* cj = sC + lane * m;
+            const cplx* cj = sC + lane * kAllMaxModes;
             cplx P{sW[lane], 0.0};
 #pragma unroll
             for (int q = 0; q < NMAX; ++q)
@@ -157,7 +166,7 @@ __global__ __launch_bounds__(kBlock, 4) void all_out_kernel(const AllOutArgs a) 
         }
         __syncthreads();
         cplx part{0.0, 0.0};
-        suffix_dispatch<NMAX>(ns, sC, sP[wv], off, m, nt, part);
+        suffix_dispatch<NMAX>(ns, sC, sP[wv], off, nt, part);
         acc = cdd_add(acc, to_cdd(part));
     }
     if (!act) return;
