@@ -31,16 +31,21 @@ __global__ __launch_bounds__(kBlock) void all_sums_kernel(const AllSumsArgs a) {
 }
 
 // part += sum over the tile's terms dd of sP[dd] prod_{q<NS} cd[off[q]], with
-// cd = sC + dd * kAllMaxModes: the reads of a term go out four at a time ahead
+// cd = sC + dd * kAllStride: the reads of a term go out four at a time ahead
 // of their products (no per-factor waits or branches), into two alternating
 // product chains; the term loop is unrolled four times, so consecutive terms'
 // reads differ by immediate offsets instead of per-factor address updates.
+// LDS row stride of one term's column sums: one entry more than the largest
+// mode count, so the prefix pass (lane j reads term j's row) spreads over the
+// banks instead of every lane hitting the same one.
+constexpr int kAllStride = kAllMaxModes + 1;
+
 template <int NS, int NMAX>
 __device__ __forceinline__ void suffix_tile(const cplx* sC, const cplx* sPw, const int (&off)[NMAX], int nt,
                                             cplx& part) {
 #pragma unroll 4
     for (int dd = 0; dd < nt; ++dd) {
-        const cplx* cd = sC + dd * kAllMaxModes;
+        const cplx* cd = sC + dd * kAllStride;
         cplx p = sPw[dd];
         if constexpr (NS > 0) {
             cplx p2;
@@ -85,7 +90,7 @@ __device__ __forceinline__ void suffix_dispatch(int ns, const cplx* sC, const cp
 // n - L complex multiplies and n - L + 1 LDS reads per (term, output).
 template <int NMAX>
 __global__ __launch_bounds__(kBlock, 4) void all_out_kernel(const AllOutArgs a) {
-    __shared__ cplx sC[kAllTile * kAllMaxModes];
+    __shared__ cplx sC[kAllTile * kAllStride];
     __shared__ double sW[kAllTile];
     __shared__ uint8_t sR[kBlock][NMAX];
     __shared__ cplx sP[kWavesPerBlock][kAllTile];
@@ -147,17 +152,17 @@ __global__ __launch_bounds__(kBlock, 4) void all_out_kernel(const AllOutArgs a) 
     for (uint64_t d0 = 0; d0 < a.terms; d0 += kAllTile) {
         const int nt = (int)((a.terms - d0) < (uint64_t)kAllTile ? (a.terms - d0) : (uint64_t)kAllTile);
         __syncthreads();
-        // term dd's column sums at sC[dd * kAllMaxModes ...]: a fixed stride,
+        // term dd's column sums at sC[dd * kAllStride ...]: a fixed stride,
         // so the suffix loop reaches the next terms by immediate offsets
         for (int e = tid; e < nt * kAllMaxModes; e += kBlock) {
             const int dd = e / kAllMaxModes, r = e - dd * kAllMaxModes;
-            if (r < m) sC[e] = a.csum[(d0 + (uint64_t)dd) * (uint64_t)m + (uint64_t)r];
+            if (r < m) sC[dd * kAllStride + r] = a.csum[(d0 + (uint64_t)dd) * (uint64_t)m + (uint64_t)r];
         }
         for (int e = tid; e < nt; e += kBlock) sW[e] = a.w[d0 + e];
         __syncthreads();
         // w_j prod_{q<L} c_{r_q} for the tile's terms, lane j
         if (lane < nt) {
-            const cplx* cj = sC + lane * kAllMaxModes;
+            const cplx* cj = sC + lane * kAllStride;
             cplx P{sW[lane], 0.0};
 #pragma unroll
             for (int q = 0; q < NMAX; ++q)
