@@ -13,13 +13,15 @@
 //   q = X^T A X,  l = gamma^T X,
 //   P_N(q, l) = sum_{j=0}^{floor(N/2)} (q/2)^j l^{N-2j} / (j! (N-2j)!),
 //
-// evaluated as a product: with x = q/2, P_N = (-2x)^{N/2} He_N(l / sqrt(-2x)) / N!
-// (He_N the probabilists' Hermite polynomial), and pairing its real roots
-// +-h_k gives P_N = l^(N mod 2) prod_k (x + l^2 / (2 h_k^2)) / floor(N/2)!,
-//
 // with radix rho_f = r_f (d_f = 0..r_f - 1) and rho_i = r_i + 1 otherwise --
 // the digit structure of the generalised permanent sum.  Without loops
 // P_N = (q/2)^{N/2} / (N/2)! (zero for odd N).
+//
+// The loop polynomial is evaluated as a product: with x = q/2,
+// P_N = (-2x)^{N/2} He_N(l / sqrt(-2x)) / N! (He_N the probabilists' Hermite
+// polynomial), and pairing its real roots +-h_k gives
+// P_N = l^(N mod 2) prod_k (x + l^2 / (2 h_k^2)) / floor(N/2)!; the factors
+// are multiplied four at a time in expanded form (HafDesc::hb).
 //
 // Work split: lane digits (product of radices <= 64) are fixed per lane; a
 // register digit of radix 2 or 3 (if one is left) is evaluated at all its
