@@ -285,9 +285,14 @@ __device__ __forceinline__ void store_partial(double* o, const cdd& v) {
     o[3] = v.im.lo;
 }
 
+// Registers for four waves per SIMD where the sweep nearly fits in them (the
+// loop-free kernels with up to four lane digits; the rest keep their need).
+template <int NL, bool LOOP>
+struct HafMinWaves { static constexpr int value = (!LOOP && NL <= 4) ? 4 : 1; };
+
 // One pattern: the time states split evenly over a.waves wavefronts.
 template <int NL, int RR, bool LOOP>
-__global__ __launch_bounds__(kBlock) void haf_kernel(const HafArgs a) {
+__global__ __launch_bounds__(kBlock, (HafMinWaves<NL, LOOP>::value)) void haf_kernel(const HafArgs a) {
     __shared__ cplx sTT[kHafMaxTime][kHafMaxTime];
     haf_fill_tt<NL, RR>(a.d, a.Ac, sTT);
     __syncthreads();
@@ -301,7 +306,7 @@ __global__ __launch_bounds__(kBlock) void haf_kernel(const HafArgs a) {
 
 // Many patterns: workgroup b sweeps chunks 4b..4b+3, all of one pattern.
 template <int NL, int RR, bool LOOP>
-__global__ __launch_bounds__(kBlock) void haf_many_kernel(const HafManyArgs a) {
+__global__ __launch_bounds__(kBlock, (HafMinWaves<NL, LOOP>::value)) void haf_many_kernel(const HafManyArgs a) {
     __shared__ cplx sTT[kHafMaxTime][kHafMaxTime];
     const int pat = __builtin_amdgcn_readfirstlane(a.chunks[(size_t)blockIdx.x * kWavesPerBlock].pat);
     const HafDesc& J = a.descs[pat];
