@@ -287,3 +287,19 @@ def test_largest_vertex_count(eng, reps):
     want_haf = math.factorial(N) / (math.factorial(N // 2) * 2 ** (N // 2)) * a ** (N // 2)
     got_haf = gpu_lhaf(eng, np.full((d, d), a), None, reps)
     assert rel(got_haf, want_haf) <= 64 * 2.0 ** -52 * sum_condition(a, gv, reps, False)
+
+
+@pytest.mark.parametrize("N", range(1, 34))
+def test_constant_matrix_every_vertex_count(eng, N):
+    # every grouping of the loop polynomial's floor(N/2) Hermite factors (four
+    # at a time, then a pair and a single) and both parities of N, on a
+    # constant matrix against the closed form (matchings of the complete
+    # graph); the bound is the larger of the size tolerance and the FP64
+    # rounding of the vertex-sign sum times its condition
+    a, gv = 0.04 - 0.03j, 0.2 + 0.15j
+    reps = [N // 3, N // 3, N - 2 * (N // 3)]
+    want = sum(math.factorial(N) / (math.factorial(j) * math.factorial(N - 2 * j) * 2 ** j) * a ** j * gv ** (N - 2 * j)
+               for j in range(N // 2 + 1))
+    got = gpu_lhaf(eng, np.full((3, 3), a), np.full(3, gv), reps)
+    bound = max(tol(N), 64 * 2.0 ** -52 * sum_condition(a, gv, reps, True))
+    assert rel(got, want) <= bound, (N, rel(got, want), bound)
