@@ -151,8 +151,17 @@ def main() -> int:
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     launches, sweep_ms = eng.profile_read()
-    eng.profile(False)
     print(f"# timed {args.steps} steps in {elapsed:.3f}s", file=sys.stderr, flush=True)
+    # per-seed sweep times after the timed region (3 sweeps per seed, HIP
+    # events on each launch): median and extremes across the seeds
+    per_seed = []
+    for s in range(args.seeds):
+        for _ in range(3):
+            eng.perm(blocks[s], ones, ones, out_perm=outp[s], out_amp=outa[s])
+        torch.cuda.synchronize()
+        nl, ms = eng.profile_read()
+        per_seed.append(ms / max(1, nl))
+    eng.profile(False)
 
     perms = args.steps * args.seeds
     perms_per_s = perms / elapsed
@@ -456,6 +465,8 @@ def main() -> int:
         "glynn_terms_per_s": perms_per_s * terms,
         "ms_per_perm": 1e3 * elapsed / perms,
         "sweep_ms_avg": avg_sweep_s * 1e3,
+        "sweep_ms_per_seed": {"median": float(np.median(per_seed)), "min": float(np.min(per_seed)),
+                              "max": float(np.max(per_seed)), "seeds": len(per_seed)},
         "roofline": {
             "bound": "alu",
             "achieved": achieved_tflops,
