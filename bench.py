@@ -437,10 +437,20 @@ def main() -> int:
         tcpu = time.perf_counter() - tc
         # Ryser visits 2^n subsets with n row sums each: scale the sample to n
         t_at_n = tcpu * (2 ** (n - ns)) * (n / ns)
+        model = "unknown CPU"
+        try:
+            with open("/proc/cpuinfo") as fh:
+                for ln in fh:
+                    if ln.startswith("model name"):
+                        model = ln.split(":", 1)[1].strip()
+                        break
+        except OSError:
+            pass
         cpu = {
             "value": 1.0 / t_at_n, "unit": "perms/s", "cores": oracle.num_threads(), "kind": "oracle",
             "sample": f"one n={ns} collision-free block (seed 0), oracle Ryser in 80-bit long double, "
-                      f"{tcpu:.2f}s; scaled to n={n} by 2^{n - ns} x {n}/{ns}",
+                      f"{tcpu:.2f}s on {oracle.num_threads()} threads of {model}; "
+                      f"scaled to n={n} by 2^{n - ns} x {n}/{ns}",
         }
         print(f"# cpu baseline sample {tcpu:.2f}s", file=sys.stderr, flush=True)
 
