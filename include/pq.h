@@ -187,7 +187,12 @@ int pq_autotune_last(pq_ctx* ctx, int32_t policy[3], double* best_ms, double* de
                      int32_t* candidates);
 
 /*
- * pq_perm_grad -- vector-Jacobian product over a batch of patterns on one U.
+ * pq_perm_grad -- vector-Jacobian product over a batch of patterns on one U:
+ * the gradient of a cost built from transition amplitudes, which the paper
+ * requires of circuit simulations used for machine learning (Goals: quantum
+ * machine learning support and custom gradients in the Built-in simulators
+ * section; Benchmarks / Fock-space based simulations: Differentiability,
+ * one learning step of a photonic circuit's parameters).
  * perm(U_{T,S}) is a polynomial (holomorphic) in U; following the
  * conjugate-Wirtinger convention of complex autograd,
  *     dU = sum_p gperm[p] * conj( d perm(U_{T_p,S_p}) / dU ),
@@ -236,19 +241,26 @@ int pq_perm_all_outputs(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m, c
  * pq_sample_chain -- chain-rule boson sampling (Clifford & Clifford's
  * algorithm A, named in the Boson Sampling benchmark section), every sample's
  * whole draw sequence in one launch.  For sample s with input modes
- * order[s][0..n-1] (a random order of the occupied input modes, one photon
- * each) and uniforms u = uniforms[s][0..n-1] in [0, 1), step k = 1..n draws
+ * order[s][0..n-1] (a random order of the input photons' modes: a mode with
+ * s_j photons appears s_j times, so random Fock inputs with repeated modes
+ * are allowed) and uniforms u = uniforms[s][0..n-1] in [0, 1), step k = 1..n
+ * draws
  *     r_k = the first mode l whose cumulative weight (modes in ascending
  *           order) exceeds u_k times the total, with weights
  *           |perm(U_{r_1..r_{k-1}, l ; order[0..k-1]})|^2,
  * and writes out[s][k-1] = r_k.  Averaged over uniformly random orders and
  * uniforms, the multiset {r_k} follows the Born rule of Eq. BS_prob.
  *   U         device, m x m, leading dimension ldu >= m.
- *   order     device int32[samples * n], input modes (distinct, < m).
+ *   order     device int32[samples * n], input modes in [0, m), repeats allowed.
  *   uniforms  device double[samples * n].
  *   out       device int32[samples * n], written.
  * Limits (PQ_ERANGE): m <= 1024, n <= 24 and n <= m.  The random numbers are
  * inputs, so a run replays exactly from its uniforms and orders.
+ * The kernel checks every order entry: a sample with an entry outside
+ * [0, m) reads no row of U through it, its draws are all written as -1, and
+ * the call returns PQ_EINVAL.  To report that, the call waits for the
+ * sampler to finish on `stream` before it returns (unlike the other entry
+ * points, it is synchronous).
  */
 int pq_sample_chain(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m, int32_t n, int32_t samples,
                     const int32_t* order, const double* uniforms, int32_t* out, void* stream);

@@ -3,6 +3,12 @@ only): a beamsplitter mesh (angles -> U), permanents of many output patterns
 (U -> perm), and the mean negative log-probability (perm -> loss).  Chained,
 gradients flow from the loss to every mesh angle through the adjoint
 Gray-code sweep.
+
+This is the paper's differentiable-circuit use (Goals: machine learning
+support with automatic differentiation and custom gradients; Benchmarks /
+Fock-space based simulations, Differentiability: the gradient of a cost with
+respect to the gate parameters of one photonic layer), with the
+"Beamsplitter gate" section's cells as the parameterised gates.
 """
 from __future__ import annotations
 
@@ -56,7 +62,10 @@ def _sparse(v):
 
 class PermAmp(torch.autograd.Function):
     """perm(U_{T_p,S_p}) for every pattern of a PatternSet (forward:
-    pq_perm_many; backward: pq_perm_grad, the adjoint sweep)."""
+    pq_perm_many; backward: pq_perm_grad, the adjoint sweep).  The amplitude
+    is Eq. BS_prob's; its gradient, d perm / d U_ij = t_i s_j perm(U_{T-e_i,
+    S-e_j}), is what the Differentiability benchmark (Fock-space based
+    simulations) needs from a circuit's transition amplitudes."""
 
     @staticmethod
     def forward(ctx, U: torch.Tensor, pats: PatternSet):

@@ -19,6 +19,10 @@ int pq_sample_chain(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m, int32
     if (!U || ldu < m || !order || !uniforms || !out)
         return ctx->fail(PQ_EINVAL, "pq_sample_chain: NULL argument or ldu < m");
     DeviceGuard guard(ctx->device);
+    // every call waits for its sampler (below), so no earlier kernel can still
+    // write the status word when it is cleared here
+    int rc = ctx->status_reset();
+    if (rc) return rc;
     ChainArgs a;
     a.U = (const cplx*)U;
     a.ldu = ldu;
@@ -28,9 +32,9 @@ int pq_sample_chain(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m, int32
     a.order = order;
     a.uniforms = uniforms;
     a.out = out;
+    a.status = ctx->status_word_dev;
     hipStream_t st = (hipStream_t)stream;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    int rc;
     if (ctx->profiling) {
         e0 = ctx->take_event();
         e1 = ctx->take_event();
@@ -45,5 +49,9 @@ int pq_sample_chain(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m, int32
         if (rc) return rc;
         ctx->ev_used.emplace_back(e0, e1);
     }
+    rc = ctx->check(hipStreamSynchronize(st), "chain sampler: wait");
+    if (rc) return rc;
+    if (__atomic_load_n(ctx->status_word, __ATOMIC_SEQ_CST) & 1)
+        return ctx->fail(PQ_EINVAL, "pq_sample_chain: an input mode in order[] is outside [0, %d)", m);
     return PQ_OK;
 }

@@ -31,14 +31,32 @@ __global__ __launch_bounds__(kChainWaves * 64) void chain_kernel(const ChainArgs
     __shared__ cplx sL[K];
     __shared__ double sW[kChainMaxModes];
     __shared__ int sRow[K], sCol[K];
+    __shared__ int sBad;
     const int s = (int)blockIdx.x;
     if (s >= a.samples) return;
     const int tid = (int)threadIdx.x;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63, tau = lane >> 2, q = lane & 3;
     const int n = a.n, m = a.m;
-    for (int j = tid; j < n; j += kChainWaves * 64) sCol[j] = a.order[(size_t)s * n + j];
+    if (tid == 0) sBad = 0;
     __syncthreads();
+    // the input modes come from device memory the host cannot check: an entry
+    // outside [0, m) marks the sample (every draw -1) and the call's status,
+    // and no row of U is read through it
+    for (int j = tid; j < n; j += kChainWaves * 64) {
+        int c = a.order[(size_t)s * n + j];
+        if (c < 0 || c >= m) {
+            atomicOr(&sBad, 1);
+            c = 0;
+        }
+        sCol[j] = c;
+    }
+    __syncthreads();
+    if (sBad) {
+        for (int j = tid; j < n; j += kChainWaves * 64) a.out[(size_t)s * n + j] = -1;
+        if (tid == 0) __hip_atomic_fetch_or(a.status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        return;
+    }
     for (int k = 1; k <= n; ++k) {
         if (k == 1) {
             if (tid == 0) sL[0] = cplx{1.0, 0.0};

@@ -90,7 +90,27 @@ int pq_ctx::upload(void* dst, const void* stage_src, size_t bytes, hipStream_t s
     return check(hipEventRecord(upload_done, st), "upload record");
 }
 
+int pq_ctx::status_reset() {
+    if (!status_word) {
+        void* h = nullptr;
+        if (hipHostMalloc(&h, 256, hipHostMallocMapped) != hipSuccess)
+            return fail(PQ_ENOMEM, "status word: hipHostMalloc failed");
+        void* d = nullptr;
+        if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess) {
+            hipHostFree(h);
+            return fail(PQ_EDEVICE, "status word: hipHostGetDevicePointer failed");
+        }
+        status_word = (int32_t*)h;
+        status_word_dev = (int32_t*)d;
+    }
+    __atomic_store_n(status_word, 0, __ATOMIC_SEQ_CST);
+    return PQ_OK;
+}
+
 void pq_ctx::release_all() {
+    if (status_word) hipHostFree(status_word);
+    status_word = nullptr;
+    status_word_dev = nullptr;
     if (upload_done) hipEventDestroy(upload_done);
     upload_done = nullptr;
     if (stage) hipHostFree(stage);

@@ -61,6 +61,12 @@ struct pq_ctx {
     std::vector<pq::TuneRecord> tuned;
     pq::TuneRecord last_tune;
 
+    // pinned, device-mapped status word that kernels validating device-side
+    // inputs (the sampler's input modes) mark; read after the stream finishes
+    int32_t* status_word = nullptr;
+    int32_t* status_word_dev = nullptr;
+    int status_reset();   // allocate on first use and clear; PQ_OK or an error
+
     // sweep timing (pq_profile_enable / pq_profile_read)
     bool profiling = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used;
