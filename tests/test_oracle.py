@@ -1,6 +1,7 @@
 """Pins for the oracle: values and identities fixed by the paper and by the
 mathematics, chosen so that a dropped term, a wrong sign or index, or a
 transposed operand in any oracle routine fails at least one of them."""
+import itertools as it
 import math
 import os
 
@@ -280,22 +281,32 @@ def test_mesh_is_unitary_and_cells_compose():
     assert np.allclose(one, oracle.beamsplitter(0.4, 1.3))
 
 
-def test_golden_values_present_and_pinned():
-    """Stored oracle values for full-size single permanents were written by
-    tests/golden/make_golden.py (calls only the oracle); check the file parses
-    and that each stored matrix reproduces its stored value's magnitude scale
-    |perm| ~ sqrt(n!) m^{-n/2} within a few orders of magnitude."""
-    path = os.path.join(GOLDEN, "single_permanents.txt")
-    if not os.path.exists(path):
-        pytest.skip("golden file not generated")
-    from tests.golden import load_single
-    cases = load_single(path)
-    assert cases
+@pytest.mark.parametrize("n", [24, 28, 30, 32])
+def test_golden_values_present_and_pinned(n):
+    """Stored oracle values for the full-size single permanents (16 seeds per
+    size) were written by tests/golden/make_golden.py, which calls only the
+    oracle.  Check that every stored block is the workload's (the leading
+    n x n block of haar(2 n^2, seed), to rounding of the QR on this host), and
+    that each value has the scale |perm| ~ sqrt(n!) m^(-n/2) of such blocks
+    within a few orders of magnitude."""
+    from tests.golden import load_single_set
+    cases = load_single_set(n)
+    assert [c["seed"] for c in cases] == list(range(16))
+    m = 2 * n * n
+    scale = math.sqrt(math.factorial(n)) * m ** (-n / 2)
     for c in cases:
-        n = c["n"]
-        m = 2 * n * n
-        scale = math.sqrt(math.factorial(n)) * m ** (-n / 2)
         assert 1e-4 < abs(c["perm"]) / scale < 1e4
+    for c in cases[:2]:
+        A = workloads.collision_free_block(n, c["seed"])
+        assert np.max(np.abs(A - c["A"])) < 1e-12
+
+
+def test_golden_value_recomputes_at_n24():
+    # the stored n = 24 values are the oracle's, not a later edit
+    from tests.golden import load_single_set
+    for c in load_single_set(24)[:3]:
+        re, im = oracle.perm_ryser_ld(c["A"])
+        assert complex(float(re), float(im)) == c["perm"]
 
 
 def test_mesh_jacobian_matches_finite_differences():
@@ -389,6 +400,33 @@ def test_chain_rule_sampler_reproduces_born_rule():
     assert abs(sum(prob.values()) - 1.0) < 1e-12
 
 
+@pytest.mark.parametrize("inputs", [[0, 0, 1], [2, 2, 2], [0, 1, 1, 3]])
+def test_chain_rule_reproduces_born_rule_with_repeated_inputs(inputs):
+    # random Fock inputs put several photons in one mode: the column list then
+    # repeats that mode, and the exhaustive walk over input orders and draws
+    # must still give |perm(U_{T,S})|^2 / (prod S! prod T!) for every T
+    m = 4
+    U = workloads.haar(m, 5)
+    n = len(inputs)
+    S = np.bincount(inputs, minlength=m).astype(np.int32)
+    prob = {}
+    orders = list(it.permutations(inputs))
+    for order in orders:
+        def walk(rows, p):
+            if len(rows) == n:
+                T = tuple(np.bincount(rows, minlength=m))
+                prob[T] = prob.get(T, 0.0) + p / len(orders)
+                return
+            w = oracle.chain_rule_distribution(U, order, rows)
+            w = w / w.sum()
+            for l in range(m):
+                if w[l] > 0:
+                    walk(rows + [l], p * w[l])
+        walk([], 1.0)
+    for T in workloads.fock_outputs(m, n):
+        assert abs(prob.get(tuple(int(v) for v in T), 0.0) - oracle.probability(U, S, T)) < 1e-12, T
+
+
 def test_chain_rule_sample_inverts_the_cdf():
     U = workloads.haar(5, 2)
     order = [3, 0, 1]
@@ -396,6 +434,37 @@ def test_chain_rule_sample_inverts_the_cdf():
     w0 = oracle.chain_rule_distribution(U, order, [])
     assert rows[0] == int(np.argmax(w0 > 0))          # u = 0 picks the first mode with weight
     assert len(rows) == 3 and all(0 <= r < 5 for r in rows) and len(margins) == 3
+
+
+def test_chain_rule_sample_interior_uniforms_closed_form():
+    # Two photons, weights written out by hand (not through the oracle's
+    # permanent): step 1 draws l with weight |U[l, c1]|^2 (a 1 x 1 permanent),
+    # step 2 with weight |U[r1, c1] U[l, c2] + U[r1, c2] U[l, c1]|^2 (the
+    # 2 x 2 permanent ad + bc).  For uniforms strictly inside every CDF
+    # interval the draw must be that interval's mode: an off-by-one in the
+    # inversion, a reversed cumulative order or a swapped column fails here.
+    m = 5
+    U = workloads.haar(m, 12)
+    for order in ([3, 0], [1, 4], [2, 2]):        # the last one repeats an input mode
+        c1, c2 = order
+        w1 = np.abs(U[:, c1]) ** 2
+        cdf1 = np.cumsum(w1) / w1.sum()
+        lo1 = np.concatenate([[0.0], cdf1[:-1]])
+        for i in range(m):
+            if w1[i] < 1e-12:
+                continue
+            for frac in (0.25, 0.5, 0.75):
+                u1 = lo1[i] + frac * (cdf1[i] - lo1[i])
+                w2 = np.abs(U[i, c1] * U[:, c2] + U[i, c2] * U[:, c1]) ** 2
+                cdf2 = np.cumsum(w2) / w2.sum()
+                lo2 = np.concatenate([[0.0], cdf2[:-1]])
+                for j in range(m):
+                    if w2[j] < 1e-12:
+                        continue
+                    u2 = lo2[j] + 0.5 * (cdf2[j] - lo2[j])
+                    rows, margins = oracle.chain_rule_sample(U, order, [u1, u2])
+                    assert rows == [i, j], (order, i, j, rows)
+                    assert min(margins) > 0.0
 
 
 # ------------------------------------------------------------------ losses
