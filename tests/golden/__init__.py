@@ -4,27 +4,29 @@ that calls only the oracle."""
 import numpy as np
 
 
-def load_single(path):
-    """Parse single_permanents.txt: blocks of
-    ``case n seed``, ``perm re im``, then n rows of 2n numbers (re im ...)."""
+def load_single_set(n):
+    """Stored values for n x n collision-free blocks (make_golden.py): a list
+    of {n, seed, perm, A}, the blocks read from single_n<n>_blocks.npy."""
+    import os
+    here = os.path.dirname(os.path.abspath(__file__))
+    txt = os.path.join(here, f"single_n{n}.txt")
+    npy = os.path.join(here, f"single_n{n}_blocks.npy")
+    blocks = np.load(npy, allow_pickle=False)
     cases = []
-    with open(path) as f:
-        lines = [ln.strip() for ln in f if ln.strip() and not ln.startswith("#")]
-    i = 0
-    while i < len(lines):
-        head = lines[i].split()
-        assert head[0] == "case"
-        n, seed = int(head[1]), int(head[2])
-        pr = lines[i + 1].split()
-        assert pr[0] == "perm"
-        perm = complex(float(pr[1]), float(pr[2]))
-        rows = []
-        for r in range(n):
-            v = np.array([float(x) for x in lines[i + 2 + r].split()])
-            rows.append(v[0::2] + 1j * v[1::2])
-        cases.append({"n": n, "seed": seed, "perm": perm, "A": np.array(rows)})
-        i += 2 + n
+    with open(txt) as f:
+        for ln in f:
+            if not ln.strip() or ln.startswith("#"):
+                continue
+            head = ln.split()
+            assert head[0] == "case" and int(head[1]) == n
+            k = len(cases)
+            cases.append({"n": n, "seed": int(head[2]), "perm": complex(float(head[3]), float(head[4])),
+                          "A": blocks[k]})
+    assert blocks.shape == (len(cases), n, n)
     return cases
+
+
+SINGLE_SIZES = (24, 28, 30, 32)
 
 
 def load_repeated(path):

@@ -5,8 +5,10 @@ modes) drawn by the seeded generator; the interferometer is the 20-mode Haar
 unitary of seed 0.  At 40 photons the alternating Ryser sum cancels beyond
 what an 80-bit mantissa holds, so the values are computed with the oracle's
 quad-precision multiplicity formula, on the side with fewer digit vectors
-(perm(A^T) = perm(A)).  The three patterns with the fewest digit vectors are
-stored with the unitary itself.
+(perm(A^T) = perm(A)).  Ten patterns are stored with the unitary itself:
+the three with the fewest digit vectors, and seven more chosen to span the
+cost range up to the most expensive of the 256 (6e8 digit vectors) in both
+column classes (at most 16 and 17 to 20 distinct power modes).
 
 usage: python tests/golden/make_golden_repeated.py [out_path]
 """
@@ -22,14 +24,16 @@ sys.path.insert(0, ROOT)
 import oracle     # noqa: E402
 import workloads  # noqa: E402
 
-COUNT = 3
+# pattern indices into repeated_patterns(256, seed=1): cheapest three, then
+# quantiles of the cost for 13..16 and 17..20 distinct power modes
+PATTERNS = [46, 78, 235, 107, 246, 61, 222, 156, 124, 242]
 
 
 def main():
     out = sys.argv[1] if len(sys.argv) > 1 else os.path.join(os.path.dirname(__file__), "repeated_permanents.txt")
     pats = workloads.repeated_patterns(count=256, seed=1)
     cost = [min(int(np.prod(S[S > 0] + 1)), int(np.prod(T[T > 0] + 1))) for S, T in pats]
-    order = np.argsort(cost, kind="stable")[:COUNT]
+    order = PATTERNS
     U = workloads.haar(20, 0)
     with open(out + ".tmp", "w") as f:
         f.write("# oracle (multiplicity Ryser, IEEE quad precision) permanents, 40 photons in 20 modes\n")

@@ -8,6 +8,7 @@ import pytest
 
 import oracle
 import workloads
+from tests.tolerance import assert_entries_close, extend_floor
 
 pytestmark = pytest.mark.gpu
 
@@ -123,8 +124,7 @@ def test_extend_row_jobs(eng, seed):
     out = perm.cpu().numpy()
     for k, r in enumerate(refs):
         got = out[k * m:(k + 1) * m]
-        scale = np.max(np.abs(r))
-        assert np.max(np.abs(got - r)) < 1e-10 * scale, k
+        assert_entries_close(got, r, 1e-10, extend_floor(U, jobs[k]), f"job {k}")
 
 
 def test_extend_row_with_repeated_input_columns(eng):
@@ -222,13 +222,15 @@ def test_argument_errors(eng):
 
 
 def test_repeated_40_photons_full_size(eng):
-    # the 256-pattern workload in one call; the cheapest patterns against the
-    # oracle's quad-precision values (80-bit Ryser cancels too much at 40
-    # photons), and a sample against single calls
+    # the 256-pattern workload in one call; the stored patterns (the three
+    # cheapest, and seven spanning the cost range up to the most expensive, in
+    # both column classes) against the oracle's quad-precision values (80-bit
+    # Ryser cancels too much at 40 photons), and a sample against single calls
     import os
     from tests.golden import load_repeated
     U, cases = load_repeated(os.path.join(os.path.dirname(__file__), "golden", "repeated_permanents.txt"))
     assert np.max(np.abs(U - workloads.haar(20, 0))) < 1e-12
+    assert len(cases) >= 10
     pats = workloads.repeated_patterns(count=256, seed=1)
     Ud = dev(U)
     perm, _ = eng.perm_batched(Ud, [perm_job(S, T) for S, T in pats])
@@ -259,7 +261,5 @@ def test_sampling_shaped_extend_jobs_full_size(eng):
     out = perm.cpu().numpy()
     for s in range(3):
         got = out[s * 400:(s + 1) * 400]
-        scale = np.max(np.abs(refs[s]))
-        err = np.max(np.abs(got - refs[s])) / scale
-        print(f"extend k=20 sample {s}: max rel err {err:.2e}")
-        assert err < 1e-10
+        err = assert_entries_close(got, refs[s], 1e-10, extend_floor(U, jobs[s]), f"sample {s}")
+        print(f"extend k=20 sample {s}: max per-entry rel err {err:.2e}")

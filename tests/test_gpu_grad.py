@@ -5,6 +5,7 @@ import pytest
 
 import oracle
 import workloads
+from tests.tolerance import assert_entries_close, floor_of, vjp_floor
 
 pytestmark = pytest.mark.gpu
 
@@ -38,16 +39,16 @@ def oracle_vjp(U, Ss, Ts, g):
 
 
 def check(eng, U, Ss, Ts, g, tol=1e-10):
+    # every entry by its own relative error; an absolute floor only below the
+    # rounding scale of that entry's Gray-code sum (tests/tolerance.py)
     dU, perm = eng.perm_grad(dev(U), Ss, Ts, torch.from_numpy(np.asarray(g, dtype=np.complex128)))
     dU = dU.cpu().numpy()
     perm = perm.cpu().numpy()
     ref = oracle_vjp(U, Ss, Ts, g)
-    scale = max(1e-300, np.max(np.abs(ref)))
-    err = np.max(np.abs(dU - ref)) / scale
+    assert_entries_close(dU, ref, tol, vjp_floor(U, Ss, Ts, g), "dU")
     for p, (S, T) in enumerate(zip(Ss, Ts)):
         r = oracle.perm_mult(U, S, T)
-        assert abs(perm[p] - r) <= tol * max(abs(r), 1e-300) or abs(r) < 1e-14
-    assert err < tol, err
+        assert_entries_close(perm[p], r, tol, floor_of(U, S, T), f"perm[{p}]")
     return dU
 
 
