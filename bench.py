@@ -78,6 +78,33 @@ def sweep_traffic_bytes(n: int):
     return 1024.0 * (t["fetch_kib"] * t["fetch_factor"] + t["write_kib"] * t["write_factor"])
 
 
+def load_stored(n: int):
+    """The stored blocks and oracle values for size n, or None."""
+    from tests.golden import load_single_set
+    try:
+        return load_single_set(n)
+    except (OSError, ValueError, AssertionError):
+        return None
+
+
+def host_cpu() -> dict:
+    """CPU model (as lscpu reports it), logical CPUs and the CPUs this process may use."""
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count() or 1
+    return {"model": model, "nproc": usable, "logical_cpus": os.cpu_count()}
+
+
 def flops_per_term(n: int) -> int:
     # per Gray-code term at unit multiplicities: n complex adds (row update),
     # n-1 complex multiplies (product), one complex multiply-add by the +-1
@@ -92,7 +119,6 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=30)
     ap.add_argument("--seeds", type=int, default=16)
-    ap.add_argument("--cpu-sample-n", type=int, default=28)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--no-haf", action="store_true", help="skip the loop hafnian workloads")
@@ -128,7 +154,19 @@ def main() -> int:
         torch.cuda.synchronize()
         del src, dst
     t0 = time.time()
-    blocks = [torch.from_numpy(workloads.collision_free_block(n, s)).to(dev) for s in range(args.seeds)]
+    # the stored workload blocks (tests/golden/make_golden.py stores each block
+    # beside the oracle's value of its permanent, so the timed outputs can be
+    # checked without depending on the host's LAPACK build); generated when
+    # no stored set covers the size
+    stored = load_stored(n)
+    if stored is not None and args.seeds <= len(stored):
+        host_blocks = [c["A"] for c in stored[:args.seeds]]
+        input_source = f"blocks stored by tests/golden/make_golden.py (seeds 0..{args.seeds - 1})"
+    else:
+        host_blocks = [workloads.collision_free_block(n, s) for s in range(args.seeds)]
+        input_source = "generated by workloads.collision_free_block"
+        stored = None
+    blocks = [torch.from_numpy(np.ascontiguousarray(b)).to(dev) for b in host_blocks]
     print(f"# inputs ready ({time.time() - t0:.1f}s)", file=sys.stderr, flush=True)
     ones = [1] * n
     eng = pq.Engine(0)
@@ -162,6 +200,17 @@ def main() -> int:
         nl, ms = eng.profile_read()
         per_seed.append(ms / max(1, nl))
     eng.profile(False)
+
+    # parity of the timed outputs (the last step's) against the oracle's
+    # stored values, after the timed region
+    parity = None
+    if stored is not None:
+        got = outp.cpu().numpy()
+        errs = [abs(complex(got[s]) - stored[s]["perm"]) / abs(stored[s]["perm"]) for s in range(args.seeds)]
+        parity = {"max_rel_err": float(max(errs)), "cases": args.seeds, "tolerance": 1e-8,
+                  "reference": "oracle Ryser (80-bit) values stored by tests/golden/make_golden.py",
+                  "pass": bool(max(errs) < 1e-8)}
+        print(f"# parity vs stored oracle values: max rel err {max(errs):.2e}", file=sys.stderr, flush=True)
 
     perms = args.steps * args.seeds
     perms_per_s = perms / elapsed
@@ -197,6 +246,32 @@ def main() -> int:
                 tb += t2 - t1
         grad_ratio = {"forward_ms": 1e3 * tf / reps, "backward_ms": 1e3 * tb / reps, "ratio": tb / tf,
                       "workload": "12-mode mesh, 132 angles, 8 photons, 4096 output patterns"}
+        # GPU time of each pass: a spin kernel holds the stream while the host
+        # enqueues the forward and the backward behind it, so the events
+        # between them bracket the passes' kernels run back to back, without
+        # the host's marshalling gaps (median of 5)
+        if hasattr(torch.cuda, "_sleep"):
+            gf, gb = [], []
+            for it in range(6):
+                a = ang0.clone().requires_grad_(True)
+                torch.cuda.synchronize()
+                e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+                torch.cuda._sleep(100_000_000)
+                e0.record()
+                loss = ag.mesh_loss(a, workloads.MESH_CELLS, workloads.MESH_MODES, pats)
+                e1.record()
+                loss.backward()
+                e2.record()
+                t_enq = time.perf_counter()
+                torch.cuda.synchronize()
+                t_done = time.perf_counter()
+                if it > 0:
+                    gf.append(e0.elapsed_time(e1))
+                    gb.append(e1.elapsed_time(e2))
+            grad_ratio.update({"gpu_forward_ms": float(np.median(gf)), "gpu_backward_ms": float(np.median(gb)),
+                               "gpu_ratio": float(np.median(gb) / np.median(gf)),
+                               "host_waited_ms": 1e3 * (t_done - t_enq)})
+            print(f"# grad/forward GPU time {np.median(gb) / np.median(gf):.2f}", file=sys.stderr, flush=True)
         print(f"# grad/forward {tb / tf:.2f}", file=sys.stderr, flush=True)
 
     # kernel-level reverse/forward sweep time for one collision-free block
@@ -358,6 +433,30 @@ def main() -> int:
         batched["sampling_device_chain"] = {
             "samples": 1000, "photons": 20, "modes": 400, "kernel_ms": ms / 3, "wall_ms": tw * 1e3,
             "samples_per_s": 1000 / tw}
+        # the shape of the paper's boson-sampling benchmark: random Fock
+        # inputs (photons thrown uniformly into the modes, so input modes
+        # repeat) with photons = modes / 2, 20 photons in 40 modes
+        rng_f = np.random.default_rng(2)
+        U40 = torch.from_numpy(workloads.haar(40, 1)).to(dev)
+        occ40 = workloads.random_occupations(rng_f, 40, 20)
+        inputs40 = np.repeat(np.arange(40), occ40)
+        order_f = torch.from_numpy(np.stack([rng_f.permutation(inputs40) for _ in range(1000)]).astype(np.int32)).to(dev)
+        u_f = torch.from_numpy(rng_f.random((1000, 20))).to(dev)
+        eng.sample_chain(U40, order_f, u_f)
+        torch.cuda.synchronize()
+        eng.profile(True)
+        eng.profile_read()
+        tw = time.perf_counter()
+        for _ in range(3):
+            eng.sample_chain(U40, order_f, u_f)
+        torch.cuda.synchronize()
+        tw = (time.perf_counter() - tw) / 3
+        nl, ms = eng.profile_read()
+        eng.profile(False)
+        batched["sampling_random_fock_input"] = {
+            "samples": 1000, "photons": 20, "modes": 40, "occupied_input_modes": int((occ40 > 0).sum()),
+            "max_input_occupation": int(occ40.max()), "kernel_ms": ms / 3, "wall_ms": tw * 1e3,
+            "samples_per_s": 1000 / tw}
         # the same runs with a loss of 10 % on every mode: the draws on the
         # 800-mode unitary dilation (built once, outside the timing); photons
         # drawn in modes >= 400 are the lost ones
@@ -446,32 +545,29 @@ def main() -> int:
                                     "separate_calls_patterns_per_s": 1.0 / tsingle}
         print(f"# hafnian: {hafnian}", file=sys.stderr, flush=True)
 
+    # the oracle on the host cores: Ryser in 80-bit long double with OpenMP
+    # over every thread it is given, on the bench's own seed-0 block (one
+    # permanent of the timed workload, about 10 to 30 s), and its value as one
+    # more parity point
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        ns = args.cpu_sample_n
-        A = workloads.collision_free_block(ns, 0)
+        A0 = host_blocks[0]
         tc = time.perf_counter()
-        oracle.perm_ryser(A)
+        ref0 = oracle.perm_ryser(A0)
         tcpu = time.perf_counter() - tc
-        # Ryser visits 2^n subsets with n row sums each: scale the sample to n
-        t_at_n = tcpu * (2 ** (n - ns)) * (n / ns)
-        model = "unknown CPU"
-        try:
-            with open("/proc/cpuinfo") as fh:
-                for ln in fh:
-                    if ln.startswith("model name"):
-                        model = ln.split(":", 1)[1].strip()
-                        break
-        except OSError:
-            pass
+        hc = host_cpu()
+        got0 = complex(outp[0].item())
         cpu = {
-            "value": 1.0 / t_at_n, "unit": "perms/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"one n={ns} collision-free block (seed 0), oracle Ryser in 80-bit long double, "
-                      f"{tcpu:.2f}s on {oracle.num_threads()} threads of {model}; "
-                      f"scaled to n={n} by 2^{n - ns} x {n}/{ns}",
+            "value": 1.0 / tcpu, "unit": "perms/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"the bench's seed-0 block (n={n}, m={m}), one permanent by the oracle's Ryser sum in "
+                      f"80-bit long double: {tcpu:.2f}s on {oracle.num_threads()} OpenMP threads "
+                      f"({hc['nproc']} usable of {hc['logical_cpus']} logical CPUs, {hc['model']})",
+            "seconds": tcpu, "cpu_model": hc["model"], "nproc": hc["nproc"],
+            "ryser_terms_per_s": 2.0 ** n / tcpu,
+            "gpu_vs_oracle_rel_err": abs(got0 - ref0) / abs(ref0),
         }
-        print(f"# cpu baseline sample {tcpu:.2f}s", file=sys.stderr, flush=True)
+        print(f"# cpu baseline {tcpu:.2f}s on {oracle.num_threads()} threads", file=sys.stderr, flush=True)
 
     line = {
         "metric": "Glynn terms/sec & permanents/sec (complex128, n=30); grad/forward time ratio",
@@ -506,6 +602,8 @@ def main() -> int:
             "kernel": f"glynn_bin<{n}>",
             "flops_per_launch": algo_flops,
         },
+        "parity": parity,
+        "inputs": input_source,
         "cpu_baseline": cpu,
         "grad_forward": grad_ratio,
         "grad_kernel": grad_kernel,
