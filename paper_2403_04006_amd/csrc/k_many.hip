@@ -7,17 +7,28 @@
 
 namespace pq {
 
-// One workgroup per pattern: add its chunk slots in slot order.
+// One workgroup per distinct pattern: add its chunk slots in slot order and
+// write the value to every copy's output.
 __global__ __launch_bounds__(64) void many_final_kernel(const ManyFinalArgs a) {
     const int p = blockIdx.x;
     if (p >= a.npat) return;
     const int t = threadIdx.x;
     const int cls = a.pat_class[p];
+    const int q0 = a.dup_off[p], q1 = a.dup_off[p + 1];
+    if (a.adjoint && t == 0) {
+        // the copies' cotangents, summed in pattern order
+        double re = 0.0, im = 0.0;
+        for (int q = q0; q < q1; ++q) {
+            const cplx g = a.gperm[a.dup_pat[q]];
+            re += g.re;
+            im += g.im;
+        }
+        a.gsum[p] = cplx{re, im};
+    }
     if (cls < 0) {
-        if (t == 0) {
-            const BJob& J = a.jobs[p];
-            if (a.perm) a.perm[J.out_offset] = a.trivial[p];
-            if (a.amp) a.amp[J.out_offset] = a.trivial[p];
+        for (int q = q0 + t; q < q1; q += 64) {
+            if (a.perm) a.perm[a.dup_out[q]] = a.trivial[p];
+            if (a.amp) a.amp[a.dup_out[q]] = a.trivial[p];
         }
         return;
     }
@@ -32,14 +43,30 @@ __global__ __launch_bounds__(64) void many_final_kernel(const ManyFinalArgs a) {
             s = cdd_add(s, cdd{{q[0], q[1]}, {q[2], q[3]}});
         }
         s = wave_reduce(s);
-        if (t == 0) {
-            const double re = (s.re.hi + s.re.lo) * J.scale;
-            const double im = (s.im.hi + s.im.lo) * J.scale;
-            if (a.perm) a.perm[J.out_offset] = cplx{re, im};
-            if (a.amp) a.amp[J.out_offset] = cplx{re * J.norm, im * J.norm};
+        // lane 0's sum, for every lane
+        const double rh = __shfl(s.re.hi, 0, 64), rl = __shfl(s.re.lo, 0, 64);
+        const double ih = __shfl(s.im.hi, 0, 64), il = __shfl(s.im.lo, 0, 64);
+        const double re = (rh + rl) * J.scale;
+        const double im = (ih + il) * J.scale;
+        for (int q = q0 + t; q < q1; q += 64) {
+            if (a.perm) a.perm[a.dup_out[q]] = cplx{re, im};
+            if (a.amp) a.amp[a.dup_out[q]] = cplx{re * J.norm, im * J.norm};
         }
-        // (reverse sweeps: the derivative part of the slots is reduced by
-        // the two dred stages)
+        if (a.adjoint && a.fuse_dred) {
+            // derivative part of the slots: entry e adds its chunks in order
+            // (the same sums as the two reduction stages for <= 64 chunks)
+            const int nent = J.r * J.nc;
+            for (int e = t; e < nent; e += 64) {
+                double dre = 0.0, dim = 0.0;
+                for (int k = 0; k < J.nchunks; ++k) {
+                    dre += base[(size_t)k * sd + 4 + 2 * e];
+                    dim += base[(size_t)k * sd + 4 + 2 * e + 1];
+                }
+                a.dpat[a.dpat_off[p] + e] = cplx{dre * J.scale, dim * J.scale};
+            }
+        }
+        // (otherwise the derivative part of the slots is reduced by the two
+        // dred stages)
     } else {
         // Laplace expansion: L_j from the chunk sums, then out[l] = sum_j U[l, C_j] L_j
         __shared__ cplx L[kMaxExtendCols];
@@ -63,7 +90,8 @@ __global__ __launch_bounds__(64) void many_final_kernel(const ManyFinalArgs a) {
                 im = __builtin_fma(u.re, L[j].im, im);
                 im = __builtin_fma(u.im, L[j].re, im);
             }
-            if (a.perm) a.perm[J.out_offset + l] = cplx{re, im};
+            if (a.perm)
+                for (int q = q0; q < q1; ++q) a.perm[a.dup_out[q] + l] = cplx{re, im};
         }
     }
 }

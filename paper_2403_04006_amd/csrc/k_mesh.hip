@@ -4,8 +4,9 @@
 // Mesh: U = B_last ... B_2 B_1, cell q acting on modes (k, l) with the
 // beamsplitter mode matrix [[t, -r*], [r, t]], t = cos(theta), r = e^{i phi}
 // sin(theta) (Beamsplitter gate section; row = output mode).  Left
-// multiplication mixes rows k and l of every column independently, so one
-// thread owns one column.
+// multiplication mixes rows k and l of every column independently, and cells
+// on disjoint mode pairs commute: the host groups the cells into layers, and
+// one thread per (cell of the layer, column) applies a whole layer at once.
 //
 // Reverse mode (conjugate-Wirtinger convention of complex autograd: for a
 // real loss L the gradient of a complex z is dL/dRe z + i dL/dIm z):
@@ -27,28 +28,29 @@ struct BS {
     cplx t, mrc, r;     // t (real), -r*, r
 };
 
-__device__ __forceinline__ BS cell_matrix(double th, double ph) {
-    const double c = cos(th), s = sin(th);
-    const double cp = cos(ph), sp = sin(ph);
-    BS b;
-    b.t = cplx{c, 0.0};
-    b.r = cplx{cp * s, sp * s};
-    b.mrc = cplx{-cp * s, sp * s};
-    return b;
-}
-
 __device__ __forceinline__ cplx cadd(cplx a, cplx b) { return cplx{a.re + b.re, a.im + b.im}; }
 __device__ __forceinline__ cplx cconj(cplx a) { return cplx{a.re, -a.im}; }
 
-// cos/sin of every cell's angles, computed by the 64 threads together
-__device__ __forceinline__ void cell_trig(const double* angles, int ncell, double (*trig)[4]) {
+// cos/sin of every cell's angles, and the layer schedule, into LDS (all
+// threads together)
+struct MeshShared {
+    double trig[kMeshMaxCells][4];
+    int16_t order[kMeshMaxCells];
+    int16_t start[kMeshMaxCells + 1];
+    int8_t modes[2 * kMeshMaxCells];
+};
+
+__device__ __forceinline__ void mesh_setup(const double* angles, int ncell, const MeshLayers& lay, MeshShared& sh) {
     for (int q = threadIdx.x; q < ncell; q += blockDim.x) {
-        trig[q][0] = cos(angles[2 * q]);
-        trig[q][1] = sin(angles[2 * q]);
-        trig[q][2] = cos(angles[2 * q + 1]);
-        trig[q][3] = sin(angles[2 * q + 1]);
+        sh.trig[q][0] = cos(angles[2 * q]);
+        sh.trig[q][1] = sin(angles[2 * q]);
+        sh.trig[q][2] = cos(angles[2 * q + 1]);
+        sh.trig[q][3] = sin(angles[2 * q + 1]);
+        sh.order[q] = lay.order[q];
+        sh.modes[2 * q] = lay.modes[2 * q];
+        sh.modes[2 * q + 1] = lay.modes[2 * q + 1];
     }
-    __syncthreads();
+    for (int L = threadIdx.x; L <= lay.nlayers; L += blockDim.x) sh.start[L] = lay.start[L];
 }
 
 __device__ __forceinline__ BS cell_from_trig(const double* tg) {
@@ -59,52 +61,76 @@ __device__ __forceinline__ BS cell_from_trig(const double* tg) {
     return b;
 }
 
-__global__ __launch_bounds__(64) void mesh_forward_kernel(const MeshArgs a) {
+// Threads: slot p = threadIdx.x / 32 (the p-th cell of a layer) and column
+// col = threadIdx.x % 32.  One layer is one parallel step: every (cell,
+// column) pair mixes rows k and l of its column, then a barrier.
+__global__ __launch_bounds__(kMeshThreads) void mesh_forward_kernel(const MeshArgs a) {
     __shared__ cplx sU[kMeshMaxModes][kMeshMaxModes];
-    __shared__ double trig[kMeshMaxCells][4];
-    cell_trig(a.angles, a.ncell, trig);
-    const int col = threadIdx.x;
-    if (col < a.m)
-        for (int r = 0; r < a.m; ++r) sU[r][col] = cplx{r == col ? 1.0 : 0.0, 0.0};
-    for (int q = 0; q < a.ncell; ++q) {
-        const int k = a.modes[2 * q], l = a.modes[2 * q + 1];
-        const BS b = cell_from_trig(trig[q]);
-        if (col < a.m) {
+    __shared__ MeshShared sh;
+    mesh_setup(a.angles, a.ncell, a.lay, sh);
+    const int m = a.m;
+    for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
+        const int r = e / m, c = e - r * m;
+        sU[r][c] = cplx{r == c ? 1.0 : 0.0, 0.0};
+    }
+    __syncthreads();
+    const int p = threadIdx.x / kMeshColGroup, col = threadIdx.x % kMeshColGroup;
+    for (int L = 0; L < a.lay.nlayers; ++L) {
+        const int beg = sh.start[L], cnt = sh.start[L + 1] - beg;
+        if (p < cnt && col < m) {
+            const int q = sh.order[beg + p];
+            const int k = sh.modes[2 * q], l = sh.modes[2 * q + 1];
+            const BS b = cell_from_trig(sh.trig[q]);
             const cplx uk = sU[k][col], ul = sU[l][col];
             sU[k][col] = cadd(cmul(b.t, uk), cmul(b.mrc, ul));
             sU[l][col] = cadd(cmul(b.r, uk), cmul(b.t, ul));
         }
+        __syncthreads();
     }
-    if (col < a.m)
-        for (int r = 0; r < a.m; ++r) a.U[(size_t)r * (size_t)a.ldu + col] = sU[r][col];
+    for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
+        const int r = e / m, c = e - r * m;
+        a.U[(size_t)r * (size_t)a.ldu + c] = sU[r][c];
+    }
 }
 
-__global__ __launch_bounds__(64) void mesh_vjp_kernel(const MeshVjpArgs a) {
+// Forward through every layer to U, then backward layer by layer: each
+// (cell, column) pair recovers its rows of U before the cell (B^H is B's
+// inverse), forms its column's share of the two angle derivatives and moves
+// the adjoint back through the cell.  A cell's 32 columns are one half of a
+// wavefront; their shares are added by a fixed butterfly.
+__global__ __launch_bounds__(kMeshThreads) void mesh_vjp_kernel(const MeshVjpArgs a) {
     __shared__ cplx sU[kMeshMaxModes][kMeshMaxModes];
     __shared__ cplx sG[kMeshMaxModes][kMeshMaxModes];
-    __shared__ double trig[kMeshMaxCells][4];
-    cell_trig(a.angles, a.ncell, trig);
-    const int col = threadIdx.x;
-    const bool act = col < a.m;
-    if (act)
-        for (int r = 0; r < a.m; ++r) {
-            sU[r][col] = cplx{r == col ? 1.0 : 0.0, 0.0};
-            sG[r][col] = a.gU[(size_t)r * (size_t)a.ldg + col];
-        }
-    for (int q = 0; q < a.ncell; ++q) {
-        const int k = a.modes[2 * q], l = a.modes[2 * q + 1];
-        const BS b = cell_from_trig(trig[q]);
-        if (act) {
+    __shared__ MeshShared sh;
+    mesh_setup(a.angles, a.ncell, a.lay, sh);
+    const int m = a.m;
+    for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
+        const int r = e / m, c = e - r * m;
+        sU[r][c] = cplx{r == c ? 1.0 : 0.0, 0.0};
+        sG[r][c] = a.gU[(size_t)r * (size_t)a.ldg + c];
+    }
+    __syncthreads();
+    const int p = threadIdx.x / kMeshColGroup, col = threadIdx.x % kMeshColGroup;
+    for (int L = 0; L < a.lay.nlayers; ++L) {
+        const int beg = sh.start[L], cnt = sh.start[L + 1] - beg;
+        if (p < cnt && col < m) {
+            const int q = sh.order[beg + p];
+            const int k = sh.modes[2 * q], l = sh.modes[2 * q + 1];
+            const BS b = cell_from_trig(sh.trig[q]);
             const cplx uk = sU[k][col], ul = sU[l][col];
             sU[k][col] = cadd(cmul(b.t, uk), cmul(b.mrc, ul));
             sU[l][col] = cadd(cmul(b.r, uk), cmul(b.t, ul));
         }
+        __syncthreads();
     }
-    for (int q = a.ncell - 1; q >= 0; --q) {
-        const int k = a.modes[2 * q], l = a.modes[2 * q + 1];
-        const BS b = cell_from_trig(trig[q]);
+    for (int L = a.lay.nlayers - 1; L >= 0; --L) {
+        const int beg = sh.start[L], cnt = sh.start[L + 1] - beg;
+        const bool act = p < cnt && col < m;
+        const int q = p < cnt ? sh.order[beg + p] : 0;
         double gth = 0.0, gph = 0.0;
         if (act) {
+            const int k = sh.modes[2 * q], l = sh.modes[2 * q + 1];
+            const BS b = cell_from_trig(sh.trig[q]);
             // U_{q-1} = B^H U_q on rows (k, l): B^H = [[t, r*], [-r, t]]
             const cplx uk = sU[k][col], ul = sU[l][col];
             const cplx pk = cadd(cmul(b.t, uk), cmul(cconj(b.r), ul));
@@ -113,7 +139,7 @@ __global__ __launch_bounds__(64) void mesh_vjp_kernel(const MeshVjpArgs a) {
             sU[l][col] = pl;
             const cplx gk = sG[k][col], gl = sG[l][col];
             // dB/dtheta = [[-s, -e^{-i phi} c], [e^{i phi} c, -s]]
-            const double c = trig[q][0], s = trig[q][1], cp = trig[q][2], sp = trig[q][3];
+            const double c = sh.trig[q][0], s = sh.trig[q][1], cp = sh.trig[q][2], sp = sh.trig[q][3];
             const cplx dk_th = cadd(cmul(cplx{-s, 0.0}, pk), cmul(cplx{-cp * c, sp * c}, pl));
             const cplx dl_th = cadd(cmul(cplx{cp * c, sp * c}, pk), cmul(cplx{-s, 0.0}, pl));
             // dB/dphi = [[0, i e^{-i phi} s], [i e^{i phi} s, 0]]
@@ -126,27 +152,52 @@ __global__ __launch_bounds__(64) void mesh_vjp_kernel(const MeshVjpArgs a) {
             sG[k][col] = cadd(cmul(b.t, gk), cmul(cconj(b.r), gl));
             sG[l][col] = cadd(cmul(cplx{-b.r.re, -b.r.im}, gk), cmul(b.t, gl));
         }
-        // fixed-order butterfly over the 64 columns
+        // fixed-order butterfly over the cell's 32 columns (its half wavefront)
 #pragma unroll
-        for (int msk = 32; msk >= 1; msk >>= 1) {
+        for (int msk = kMeshColGroup / 2; msk >= 1; msk >>= 1) {
             gth += __shfl_xor(gth, msk, 64);
             gph += __shfl_xor(gph, msk, 64);
         }
-        if (col == 0) {
+        if (col == 0 && p < cnt) {
             a.gangles[2 * q] = gth;
             a.gangles[2 * q + 1] = gph;
         }
+        __syncthreads();
     }
 }
 
 hipError_t launch_mesh_forward(const MeshArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(mesh_forward_kernel, dim3(1), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(mesh_forward_kernel, dim3(1), dim3(kMeshThreads), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_mesh_vjp(const MeshVjpArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(mesh_vjp_kernel, dim3(1), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(mesh_vjp_kernel, dim3(1), dim3(kMeshThreads), 0, s, a);
     return hipGetLastError();
+}
+
+void mesh_layers(int32_t ncell, const int32_t* modes, MeshLayers& lay) {
+    int last[kMeshMaxModes];
+    for (int i = 0; i < kMeshMaxModes; ++i) last[i] = -1;
+    int layer[kMeshMaxCells];
+    int nl = 0;
+    for (int q = 0; q < ncell; ++q) {
+        const int k = modes[2 * q], l = modes[2 * q + 1];
+        const int L = 1 + (last[k] > last[l] ? last[k] : last[l]);
+        last[k] = last[l] = L;
+        layer[q] = L;
+        if (L + 1 > nl) nl = L + 1;
+        lay.modes[2 * q] = (int8_t)k;
+        lay.modes[2 * q + 1] = (int8_t)l;
+    }
+    lay.nlayers = nl;
+    int fill = 0;
+    for (int L = 0; L < nl; ++L) {
+        lay.start[L] = (int16_t)fill;
+        for (int q = 0; q < ncell; ++q)
+            if (layer[q] == L) lay.order[fill++] = (int16_t)q;
+    }
+    lay.start[nl] = (int16_t)fill;
 }
 
 // ------------------------------------------------------------------- loss

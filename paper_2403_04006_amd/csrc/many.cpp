@@ -44,7 +44,8 @@ struct ManyClass {
 struct ManyEntry {
     std::vector<int64_t> key;
     int mode = 0;                // kModeFwd (forward and extend jobs) or kModeAdj
-    int npat = 0, ntab = 0;
+    int npat = 0, ntab = 0;      // npat: distinct patterns (identical ones are swept once)
+    bool fuse_dred = false;      // adjoint: the final kernel reduces the derivative slots
     size_t mat_elems = 0, partial_doubles = 0, dpat_elems = 0;
     std::vector<ManyClass> classes;
     ChunkPolicy policy;
@@ -60,6 +61,10 @@ struct ManyEntry {
     int32_t* d_class_sd = nullptr;
     cplx* d_trivial = nullptr;
     int64_t* d_dpat_off = nullptr;
+    int32_t* d_dup_off = nullptr;    // copies of every distinct pattern (ManyFinalArgs)
+    int32_t* d_dup_pat = nullptr;
+    int64_t* d_dup_out = nullptr;
+    cplx* d_gsum = nullptr;          // adjoint: summed cotangent per distinct pattern
     cplx* d_mat = nullptr;
     StepEntry* d_tabs = nullptr;
     double* d_partials = nullptr;
@@ -109,11 +114,50 @@ struct PatternSpec {
     int64_t out;
 };
 
-int build_many(pq_ctx* ctx, int mode, int32_t m, const std::vector<PatternSpec>& pats, ManyEntry& E,
+// Identity of a pattern for deduplication: op, then both sides (modes and
+// multiplicities in the caller's order).
+std::vector<int32_t> pattern_key(const PatternSpec& ps) {
+    std::vector<int32_t> k;
+    k.reserve(3 + 2 * (size_t)(ps.rows.count + ps.cols.count));
+    k.push_back(ps.op);
+    k.push_back(ps.rows.count);
+    for (int i = 0; i < ps.rows.count; ++i) { k.push_back(ps.rows.mode[i]); k.push_back(ps.rows.mult[i]); }
+    k.push_back(ps.cols.count);
+    for (int i = 0; i < ps.cols.count; ++i) { k.push_back(ps.cols.mode[i]); k.push_back(ps.cols.mult[i]); }
+    return k;
+}
+
+int build_many(pq_ctx* ctx, int mode, int32_t m, const std::vector<PatternSpec>& all, ManyEntry& E,
                hipStream_t st, const ChunkPolicy& pol) {
     E.mode = mode;
     E.policy = pol;
     const bool adj = mode == kModeAdj;
+    // identical patterns (a sampling loss draws outputs with replacement) are
+    // planned and swept once; the final kernel writes every copy's output and,
+    // in the adjoint, sums the copies' cotangents
+    std::vector<PatternSpec> pats;
+    std::vector<int32_t> dup_off, dup_pat;
+    std::vector<int64_t> dup_out;
+    {
+        std::map<std::vector<int32_t>, int32_t> seen;
+        std::vector<int32_t> dist(all.size());
+        for (size_t k = 0; k < all.size(); ++k) {
+            auto it = seen.emplace(pattern_key(all[k]), (int32_t)pats.size()).first;
+            if (it->second == (int32_t)pats.size()) pats.push_back(all[k]);
+            dist[k] = it->second;
+        }
+        dup_off.assign(pats.size() + 1, 0);
+        for (int32_t d : dist) dup_off[(size_t)d + 1] += 1;
+        for (size_t d = 0; d < pats.size(); ++d) dup_off[d + 1] += dup_off[d];
+        std::vector<int32_t> fill(dup_off.begin(), dup_off.end() - 1);
+        dup_pat.assign(all.size(), 0);
+        dup_out.assign(all.size(), 0);
+        for (size_t k = 0; k < all.size(); ++k) {
+            const int32_t q = fill[dist[k]]++;
+            dup_pat[q] = (int32_t)k;
+            dup_out[q] = all[k].out;
+        }
+    }
     E.npat = (int)pats.size();
     std::vector<BJob> hj(pats.size());
     std::vector<int32_t> hidx, sig_flat, pat_slot(pats.size(), 0), pat_class(pats.size(), -1);
@@ -287,10 +331,18 @@ int build_many(pq_ctx* ctx, int mode, int32_t m, const std::vector<PatternSpec>&
         class_sd.push_back(C.slot_doubles);
     }
 
+    // adjoint: the final kernel adds the derivative slots itself when no
+    // pattern has more than 64 chunks (one stage-1 block each: the same sums)
+    if (adj) {
+        int maxch = 0;
+        for (size_t k = 0; k < pats.size(); ++k)
+            if (pat_class[k] >= 0) maxch = std::max(maxch, (int)hj[k].nchunks);
+        E.fuse_dred = maxch <= 64;
+    }
     // adjoint: reduction items of the derivative slots (see DRedItem)
     std::vector<DRedItem> red1, red2;
     size_t red_part = 0;
-    if (adj) {
+    if (adj && !E.fuse_dred) {
         for (size_t k = 0; k < pats.size(); ++k) {
             if (pat_class[k] < 0) continue;
             const BJob& b = hj[k];
@@ -360,12 +412,16 @@ int build_many(pq_ctx* ctx, int mode, int32_t m, const std::vector<PatternSpec>&
     const size_t oSi = cv.take(sizeof(int32_t) * sz(sc_items.size()));
     const size_t oR1 = cv.take(sizeof(DRedItem) * sz(red1.size()));
     const size_t oR2 = cv.take(sizeof(DRedItem) * sz(red2.size()));
+    const size_t oDuo = cv.take(sizeof(int32_t) * sz(dup_off.size()));
+    const size_t oDup = cv.take(sizeof(int32_t) * sz(dup_pat.size()));
+    const size_t oDut = cv.take(sizeof(int64_t) * sz(dup_out.size()));
     const size_t upload_bytes = cv.off;
     const size_t oMat = cv.take(sizeof(cplx) * sz(mat_elems));
     const size_t oTab = cv.take(sizeof(StepEntry) * 2 * kMaxInner * sz(sigs.size()));
     const size_t oPart = cv.take(sizeof(double) * sz(partial_doubles));
     const size_t oDp = cv.take(sizeof(cplx) * sz(dpat_elems));
     const size_t oRp = cv.take(sizeof(cplx) * sz(red_part));
+    const size_t oGs = cv.take(sizeof(cplx) * sz(adj ? pats.size() : 0));
     if (hipMalloc((void**)&E.dmem, cv.off) != hipSuccess) {
         E.dmem = nullptr;
         return ctx->fail(PQ_ENOMEM, "many: hipMalloc(%zu) failed", cv.off);
@@ -385,6 +441,10 @@ int build_many(pq_ctx* ctx, int mode, int32_t m, const std::vector<PatternSpec>&
     E.d_red1 = (DRedItem*)(E.dmem + oR1);
     E.d_red2 = (DRedItem*)(E.dmem + oR2);
     E.d_red_part = (cplx*)(E.dmem + oRp);
+    E.d_dup_off = (int32_t*)(E.dmem + oDuo);
+    E.d_dup_pat = (int32_t*)(E.dmem + oDup);
+    E.d_dup_out = (int64_t*)(E.dmem + oDut);
+    E.d_gsum = (cplx*)(E.dmem + oGs);
     E.d_mat = (cplx*)(E.dmem + oMat);
     E.d_tabs = (StepEntry*)(E.dmem + oTab);
     E.d_partials = (double*)(E.dmem + oPart);
@@ -407,6 +467,9 @@ int build_many(pq_ctx* ctx, int mode, int32_t m, const std::vector<PatternSpec>&
     put(oSi, sc_items.data(), sizeof(int32_t) * sc_items.size());
     put(oR1, red1.data(), sizeof(DRedItem) * red1.size());
     put(oR2, red2.data(), sizeof(DRedItem) * red2.size());
+    put(oDuo, dup_off.data(), sizeof(int32_t) * dup_off.size());
+    put(oDup, dup_pat.data(), sizeof(int32_t) * dup_pat.size());
+    put(oDut, dup_out.data(), sizeof(int64_t) * dup_out.size());
     return ctx->upload(E.dmem, stage, upload_bytes, st);
 }
 
@@ -471,11 +534,17 @@ int run_many(pq_ctx* ctx, ManyEntry& E, const cplx* U, int64_t ldu, int32_t m, c
     fa.class_sd = E.d_class_sd;
     fa.partials = E.d_partials;
     fa.trivial = E.d_trivial;
+    fa.dup_off = E.d_dup_off;
+    fa.dup_pat = E.d_dup_pat;
+    fa.dup_out = E.d_dup_out;
     fa.npat = E.npat;
     fa.adjoint = E.mode == kModeAdj ? 1 : 0;
+    fa.fuse_dred = E.fuse_dred ? 1 : 0;
     fa.perm = perm;
     fa.amp = amp;
     fa.dpat = E.d_dpat;
+    fa.gperm = gperm;
+    fa.gsum = E.d_gsum;
     rc = ctx->check(launch_many_final(fa, st), "many final");
     if (rc) return rc;
     if (E.mode == kModeAdj) {
@@ -499,7 +568,7 @@ int run_many(pq_ctx* ctx, ManyEntry& E, const cplx* U, int64_t ldu, int32_t m, c
         ga.offsets = E.d_sc_off;
         ga.items = E.d_sc_items;
         ga.dpat = E.d_dpat;
-        ga.gperm = gperm;
+        ga.gperm = E.d_gsum;
         ga.m = m;
         ga.dU = dU;
         ga.lddu = lddu;

@@ -65,11 +65,20 @@ struct ManyFinalArgs {
     const int32_t* class_sd;   // [nclass]: slot doubles of the class
     const double* partials;
     const cplx* trivial;       // [npat]: value of trivial patterns
-    int32_t npat;
+    // copies of every distinct pattern (identical op, rows and columns are
+    // swept once): copy q of pattern p is dup_off[p] <= q < dup_off[p+1], with
+    // its original index dup_pat[q] and output offset dup_out[q]
+    const int32_t* dup_off;    // [npat + 1]
+    const int32_t* dup_pat;
+    const int64_t* dup_out;
+    int32_t npat;              // distinct patterns
     int32_t adjoint;
+    int32_t fuse_dred;         // adjoint: add the derivative slots here (every pattern has <= 64 chunks)
     cplx* perm;                // may be null (forward values)
     cplx* amp;                 // may be null
     cplx* dpat;                // adjoint: per pattern r x nc complex d perm / d B (scaled)
+    const cplx* gperm;         // adjoint: the caller's per-copy cotangents
+    cplx* gsum;                // adjoint: per distinct pattern, the sum of its copies' cotangents
 };
 
 // Reduction of the reverse sweeps' derivative slots in two fixed-order
@@ -97,7 +106,8 @@ struct DRedArgs {
 
 // Scatter of the per-pattern derivatives into dU (conjugate-Wirtinger VJP).
 // For every entry e = a*m + b of dU, items[offsets[e] .. offsets[e+1]) list
-// the (pattern, index into dpat) pairs that touch it, in pattern order.
+// the (distinct pattern, index into dpat) pairs that touch it, in pattern
+// order; gperm holds each distinct pattern's summed cotangent.
 struct GradScatterArgs {
     const int32_t* offsets;    // [m*m + 1]
     const int32_t* items;      // [2 * total]: pattern, then the D index (complex)

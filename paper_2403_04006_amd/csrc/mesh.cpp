@@ -34,7 +34,7 @@ int pq_mesh_unitary(pq_ctx* ctx, int32_t m, int32_t ncell, const int32_t* modes,
     a.ldu = ldu;
     a.m = m;
     a.ncell = ncell;
-    for (int q = 0; q < 2 * ncell; ++q) a.modes[q] = (int8_t)modes[q];
+    mesh_layers(ncell, modes, a.lay);
     return ctx->check(launch_mesh_forward(a, (hipStream_t)stream), "mesh forward");
 }
 
@@ -54,7 +54,7 @@ int pq_mesh_unitary_vjp(pq_ctx* ctx, int32_t m, int32_t ncell, const int32_t* mo
     a.gangles = gangles;
     a.m = m;
     a.ncell = ncell;
-    for (int q = 0; q < 2 * ncell; ++q) a.modes[q] = (int8_t)modes[q];
+    mesh_layers(ncell, modes, a.lay);
     return ctx->check(launch_mesh_vjp(a, (hipStream_t)stream), "mesh vjp");
 }
 

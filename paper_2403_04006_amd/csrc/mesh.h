@@ -10,12 +10,23 @@ namespace pq {
 constexpr int kMeshMaxModes = 32;
 constexpr int kMeshMaxCells = 512;
 
+// Layer schedule of a mesh (built on the host): cells are grouped into layers
+// of cells on disjoint mode pairs, each cell in the layer after the last one
+// that touched either of its modes.  Cells of one layer commute, so a layer
+// is applied in one parallel step; cell order along every mode is kept.
+struct MeshLayers {
+    int32_t nlayers;
+    int16_t order[kMeshMaxCells];          // cells sorted by layer
+    int16_t start[kMeshMaxCells + 1];      // layer L holds order[start[L] .. start[L+1])
+    int8_t modes[2 * kMeshMaxCells];       // per cell (original index): k, l
+};
+
 struct MeshArgs {
     const double* angles;        // device, 2 * ncell (theta, phi)
     cplx* U;                     // device, m x m
     int64_t ldu;
     int32_t m, ncell;
-    int8_t modes[2 * kMeshMaxCells];
+    MeshLayers lay;
 };
 
 struct MeshVjpArgs {
@@ -24,8 +35,15 @@ struct MeshVjpArgs {
     int64_t ldg;
     double* gangles;             // device, 2 * ncell
     int32_t m, ncell;
-    int8_t modes[2 * kMeshMaxCells];
+    MeshLayers lay;
 };
+
+// Threads of the mesh kernels: one per (cell of a layer, column); a layer
+// holds at most kMeshMaxModes / 2 cells.
+constexpr int kMeshColGroup = 32;
+constexpr int kMeshThreads = (kMeshMaxModes / 2) * kMeshColGroup;
+
+void mesh_layers(int32_t ncell, const int32_t* modes, MeshLayers& lay);
 
 struct NllArgs {
     const cplx* perm;

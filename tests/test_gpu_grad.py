@@ -226,3 +226,22 @@ def test_wide_pattern_with_repeats_is_rejected(eng):
     T[30] = 2
     with pytest.raises(pq.PqError):
         eng.perm_grad(dev(U), [S], [T], torch.ones(1, dtype=torch.complex128))
+
+
+def test_repeated_patterns_are_swept_once_and_summed(eng):
+    # the same pattern three times (with other patterns between its copies):
+    # identical patterns are swept once, their cotangents summed in pattern
+    # order, and every copy's forward value is written
+    m = 9
+    U = workloads.haar(m, 77)
+    rng = np.random.default_rng(77)
+    base = [(workloads.random_occupations(rng, m, n, cap=2), workloads.random_occupations(rng, m, n, cap=2))
+            for n in (5, 6, 4)]
+    order = [0, 1, 0, 2, 1, 0]
+    Ss = [base[i][0] for i in order]
+    Ts = [base[i][1] for i in order]
+    g = [complex(rng.standard_normal(), rng.standard_normal()) for _ in order]
+    check(eng, U, Ss, Ts, g)
+    _, perm = eng.perm_grad(dev(U), Ss, Ts, torch.from_numpy(np.asarray(g, dtype=np.complex128)))
+    perm = perm.cpu().numpy()
+    assert perm[0] == perm[2] == perm[5] and perm[1] == perm[4]

@@ -236,3 +236,24 @@ def test_argument_errors(eng):
     b, _ = eng.perm_many(U, jobs)
     torch.cuda.synchronize()
     assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
+
+
+def test_duplicate_jobs_write_every_output(eng):
+    # identical PERM and EXTEND_ROW jobs at different output offsets
+    m = 10
+    U = workloads.haar(m, 55)
+    S = np.array([1, 0, 2, 0, 1, 0, 0, 1, 0, 0], np.int32)
+    T = np.array([0, 2, 0, 1, 0, 1, 1, 0, 0, 0], np.int32)
+    cols = [0, 2, 2, 4, 7]
+    rows = [1, 1, 3, 6]
+    ext = extend_job(rows, cols, 0)
+    jobs = [dict(perm_job(S, T), out=0), dict(ext, out=1), dict(perm_job(S, T), out=1 + m),
+            dict(ext, out=2 + m), dict(perm_job(T, S), out=2 + 2 * m)]
+    perm, amp = eng.perm_many(dev(U), jobs, n_out=3 + 2 * m)
+    perm = perm.cpu().numpy()
+    ref = oracle.perm_mult(U, S, T)
+    assert rel(perm[0], ref) < 1e-12 and perm[0] == perm[1 + m]
+    assert np.array_equal(perm[1:1 + m], perm[2 + m:2 + 2 * m])
+    want = oracle.extend_row(U, rows, cols)
+    assert_entries_close(perm[1:1 + m], want, 1e-10, extend_floor(U, ext), "extend copy")
+    assert rel(perm[2 + 2 * m], oracle.perm_mult(U, T, S)) < 1e-12
