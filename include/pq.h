@@ -95,6 +95,30 @@ int pq_perm(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m,
             pq_c128* perm, pq_c128* amp, void* stream);
 
 /*
+ * pq_perm_noalloc -- pq_perm for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, and harnesses that
+ * forbid allocation.  Same arguments, planning, errors and results as
+ * pq_perm (the same kernels in the same launch geometry), but the launch
+ * sequence's scratch (compact matrix, +-2B rows, step tables, workgroup
+ * partials) is a static device array of PQ_NOALLOC_SCRATCH_BYTES per GPU,
+ * resolved by pq_create; the call itself allocates nothing (no hipMalloc,
+ * hipFree or allocating library routine) and records no profiling events.
+ *   - A permanent whose launch needs more scratch than that returns
+ *     PQ_ERANGE (outputs untouched); pq_perm handles it.  Every binary
+ *     (collision-free) permanent up to n = 48 fits; large mixed-radix ones
+ *     with 4096-state step tables and 40 distinct columns may not.
+ *   - Every call on one GPU, from every ctx, shares that GPU's array: calls
+ *     whose GPU work overlaps (other streams, other ctxs, other threads) race
+ *     and give wrong results.  Calls ordered on one stream are safe; nothing
+ *     in the array needs to start at zero.
+ *   - PQ_EDEVICE if the array's address could not be resolved on this device.
+ */
+#define PQ_NOALLOC_SCRATCH_BYTES (160u * 1024u)
+int pq_perm_noalloc(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m,
+                    const int32_t* S, const int32_t* T,
+                    pq_c128* perm, pq_c128* amp, void* stream);
+
+/*
  * Batched jobs on one interferometer U (uneven sizes).  Jobs use the sparse
  * form: distinct row modes with their multiplicities (the output side) and
  * distinct column modes with theirs (the input side).

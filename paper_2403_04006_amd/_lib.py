@@ -19,6 +19,7 @@ PQ_OP_PERM, PQ_OP_EXTEND_ROW = 0, 1
 PQ_MAX_N = 48
 PQ_GRAD_MAX_DIM = 32
 PQ_ALL_MAX_OUTPUTS = 1 << 31
+PQ_NOALLOC_SCRATCH_BYTES = 160 * 1024
 
 
 class pq_c128(ctypes.Structure):
@@ -66,6 +67,7 @@ _SIGNATURES = {
     "pq_strerror": ([ctypes.c_int], ctypes.c_char_p),
     "pq_last_error": ([_VP], ctypes.c_char_p),
     "pq_perm": ([_VP, _VP, ctypes.c_int64, ctypes.c_int32, _I32P, _I32P, _VP, _VP, _VP], ctypes.c_int),
+    "pq_perm_noalloc": ([_VP, _VP, ctypes.c_int64, ctypes.c_int32, _I32P, _I32P, _VP, _VP, _VP], ctypes.c_int),
     "pq_perm_batched": ([_VP, _VP, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(pq_job), ctypes.c_int32,
                          _VP, _VP, _VP], ctypes.c_int),
     "pq_perm_many": ([_VP, _VP, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(pq_job), ctypes.c_int32,

@@ -42,6 +42,12 @@ int pq_create(pq_ctx** out, int hip_device) {
     if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess) { delete c; return PQ_EDEVICE; }
     c->num_cu = prop.multiProcessorCount;
     c->clock_khz = prop.clockRate;
+    {
+        // the allocation-free entry point's scratch address on this device
+        // (a failure here only disables pq_perm_noalloc, which then reports it)
+        DeviceGuard guard(hip_device);
+        (void)noalloc_init(hip_device);
+    }
     *out = c;
     return PQ_OK;
 }

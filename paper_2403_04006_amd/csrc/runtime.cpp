@@ -178,27 +178,32 @@ int timed_sweep(pq_ctx* ctx, int kind, int nc, const GlynnArgs& a, int grid, hip
     return PQ_OK;
 }
 
-int run_single(pq_ctx* ctx, const Plan& p, const cplx* U, int64_t ldu, cplx* perm, cplx* amp,
-               hipStream_t st) {
-    const Geometry geo = sweep_geometry(ctx, p);
+SingleLayout single_layout(pq_ctx* ctx, const Plan& p) {
+    SingleLayout L;
+    L.geo = sweep_geometry(ctx, p);
     const int r = p.r, nc = p.nc;
+    const size_t ntab = p.binary ? 0 : (size_t)p.m_inner;
     Carve cv;
-    const size_t oB = cv.take(sizeof(cplx) * r * nc);
-    const size_t oR = cv.take(sizeof(cplx) * r * 2 * nc);
-    const size_t oBase = cv.take(sizeof(cplx) * nc);
-    const size_t oTf = cv.take(sizeof(StepEntry) * (size_t)p.m_inner);
-    const size_t oTb = cv.take(sizeof(StepEntry) * (size_t)p.m_inner);
-    const size_t oP = cv.take(sizeof(double) * 4 * (size_t)geo.grid);
-    char* ws = (char*)ctx->workspace(cv.off);
-    if (!ws) return PQ_ENOMEM;
+    L.oB = cv.take(sizeof(cplx) * r * nc);
+    L.oR = cv.take(sizeof(cplx) * r * 2 * nc);
+    L.oBase = cv.take(sizeof(cplx) * nc);
+    L.oTf = cv.take(sizeof(StepEntry) * ntab);
+    L.oTb = cv.take(sizeof(StepEntry) * ntab);
+    L.oP = cv.take(sizeof(double) * 4 * (size_t)L.geo.grid);
+    L.bytes = cv.off;
+    return L;
+}
 
+int run_single_at(pq_ctx* ctx, const Plan& p, const SingleLayout& L, char* ws, const cplx* U, int64_t ldu,
+                  cplx* perm, cplx* amp, hipStream_t st, bool timed) {
+    const int r = p.r, nc = p.nc;
     PrepArgs pa;
     memset(&pa, 0, sizeof(pa));
     pa.U = U;
     pa.ldu = ldu;
-    pa.B = (cplx*)(ws + oB);
-    pa.rows2 = (cplx*)(ws + oR);
-    pa.base = (cplx*)(ws + oBase);
+    pa.B = (cplx*)(ws + L.oB);
+    pa.rows2 = (cplx*)(ws + L.oR);
+    pa.base = (cplx*)(ws + L.oBase);
     pa.r = r;
     pa.nc = nc;
     pa.transposed = p.transposed;
@@ -212,11 +217,11 @@ int run_single(pq_ctx* ctx, const Plan& p, const cplx* U, int64_t ldu, cplx* per
     ga.B = pa.B;
     ga.rows2 = pa.rows2;
     ga.base = pa.base;
-    ga.tab_fwd = (const StepEntry*)(ws + oTf);
-    ga.tab_bwd = (const StepEntry*)(ws + oTb);
-    ga.partials = (double*)(ws + oP);
+    ga.tab_fwd = (const StepEntry*)(ws + L.oTf);
+    ga.tab_bwd = (const StepEntry*)(ws + L.oTb);
+    ga.partials = (double*)(ws + L.oP);
     ga.time_states = p.time_states;
-    ga.waves = geo.waves;
+    ga.waves = L.geo.waves;
     ga.n_lane = p.n_lane;
     ga.lane_states = p.lane_states;
     ga.n_time = p.n_time;
@@ -230,8 +235,8 @@ int run_single(pq_ctx* ctx, const Plan& p, const cplx* U, int64_t ldu, cplx* per
     if (!p.binary) {
         TableArgs ta;
         memset(&ta, 0, sizeof(ta));
-        ta.tab_fwd = (StepEntry*)(ws + oTf);
-        ta.tab_bwd = (StepEntry*)(ws + oTb);
+        ta.tab_fwd = (StepEntry*)(ws + L.oTf);
+        ta.tab_bwd = (StepEntry*)(ws + L.oTb);
         ta.n_inner = p.n_inner;
         ta.m_inner = p.m_inner;
         ta.nc = nc;
@@ -239,17 +244,26 @@ int run_single(pq_ctx* ctx, const Plan& p, const cplx* U, int64_t ldu, cplx* per
         rc = ctx->check(launch_table(ta, st), "table");
         if (rc) return rc;
     }
-    rc = timed_sweep(ctx, sweep_kind(p), nc, ga, geo.grid, st);
+    if (timed) rc = timed_sweep(ctx, sweep_kind(p), nc, ga, L.geo.grid, st);
+    else rc = ctx->check(launch_glynn(sweep_kind(p), nc, ga, L.geo.grid, st), "sweep");
     if (rc) return rc;
 
     FinalArgs fa;
     fa.partials = ga.partials;
-    fa.count = geo.grid;
+    fa.count = L.geo.grid;
     fa.scale = p.scale;
     fa.norm = p.norm;
     fa.perm = perm;
     fa.amp = amp;
     return ctx->check(launch_final(fa, st), "final");
+}
+
+int run_single(pq_ctx* ctx, const Plan& p, const cplx* U, int64_t ldu, cplx* perm, cplx* amp,
+               hipStream_t st) {
+    const SingleLayout L = single_layout(ctx, p);
+    char* ws = (char*)ctx->workspace(L.bytes);
+    if (!ws) return PQ_ENOMEM;
+    return run_single_at(ctx, p, L, ws, U, ldu, perm, amp, st, true);
 }
 
 }  // namespace pq

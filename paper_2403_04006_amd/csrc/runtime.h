@@ -127,8 +127,27 @@ Geometry sweep_geometry(pq_ctx* ctx, const Plan& p);
 // Launch a sweep, bracketed by timing events when profiling is on.
 int timed_sweep(pq_ctx* ctx, int kind, int nc, const GlynnArgs& a, int grid, hipStream_t st);
 
-// Full single-permanent sequence: prep, (table), sweep, final.
+// Device scratch of one permanent's launch sequence: compact matrix, +-2B
+// rows, base sums, the two step tables (mixed radices only) and the
+// workgroup partials, at 256-byte aligned offsets.
+struct SingleLayout {
+    Geometry geo;
+    size_t oB = 0, oR = 0, oBase = 0, oTf = 0, oTb = 0, oP = 0;
+    size_t bytes = 0;
+};
+SingleLayout single_layout(pq_ctx* ctx, const Plan& p);
+
+// Full single-permanent sequence (prep, table, sweep, final) on the scratch
+// `ws` laid out by `L`; `timed` brackets the sweep with profiling events.
+int run_single_at(pq_ctx* ctx, const Plan& p, const SingleLayout& L, char* ws, const cplx* U, int64_t ldu,
+                  cplx* perm, cplx* amp, hipStream_t st, bool timed);
+
+// The same on the ctx workspace (grown on demand).
 int run_single(pq_ctx* ctx, const Plan& p, const cplx* U, int64_t ldu, cplx* perm, cplx* amp,
                hipStream_t st);
+
+// Allocation-free entry point's set-up: resolve the device address of its
+// static scratch on the current device (once per device).  PQ_OK or an error.
+int noalloc_init(int device);
 
 }  // namespace pq
