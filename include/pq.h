@@ -145,10 +145,26 @@ typedef struct {
 } pq_job;
 
 /*
- * pq_perm_batched -- all jobs in one stream-ordered submission.  It runs them
- * exactly as pq_perm_many below (static schedule; same validation, errors and
- * outputs; HIP-graph replay and chunk autotuning as enabled on ctx).  A
- * persistent work-queue schedule was built for it but is switched off.
+ * pq_perm_batched -- all jobs in one stream-ordered submission, scheduled as a
+ * persistent work queue (the many uneven permanents of a boson-sampling run,
+ * Benchmarks / Boson Sampling).  Jobs are planned and cut into chunks as in
+ * pq_perm_many (identical jobs once, chunks longest first); per column class
+ * one launch of resident wavefronts pops chunks from an atomic counter, each
+ * chunk writes its own double-double slot, and the wavefront that finishes a
+ * job's last chunk (atomic ticket) adds the job's slots in slot order and
+ * writes its outputs.  The results equal pq_perm_many's bit for bit.
+ *   - The launch sequence (gather, step tables, counter reset, the class
+ *     queues) is captured into a HIP graph the first time a plan runs with a
+ *     given (U, ldu, perm, amp), and replayed on later calls (up to 4 graphs
+ *     per cached plan; by default, and whatever pq_graph_enable says; calls
+ *     with profiling on launch directly).  Fixed output buffers therefore
+ *     replay one graph.
+ *   - A plan whose every job is a single chunk (small jobs: all digits fit the
+ *     lanes of one wavefront) has nothing for a queue to balance and runs the
+ *     static schedule instead (one workgroup per chunk, then a final kernel).
+ *   - Chunk sizes follow the autotuner when it is enabled (off by default: a
+ *     first call then times 11 chunk policies, about 22 runs of the batch),
+ *     and recorded decisions (pq_autotune_enable, PQ_AUTOTUNE_CACHE) apply.
  *   perm  device, complex, large enough for every job's outputs.
  *   amp   device, may be NULL; written for PQ_OP_PERM jobs only.
  * Output ranges of different jobs must not overlap (PQ_EINVAL otherwise).

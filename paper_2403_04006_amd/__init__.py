@@ -335,10 +335,11 @@ class Engine:
         return self._run_jobs(self._lib.pq_perm_many, U, jobs, n_out, with_amp, out)
 
     def perm_batched(self, U: torch.Tensor, jobs: Sequence[dict], n_out: int | None = None,
-                     with_amp: bool = True):
-        """The same jobs through pq_perm_batched (the boundary's batched
-        call; it runs them on pq_perm_many's static schedule)."""
-        return self._run_jobs(self._lib.pq_perm_batched, U, jobs, n_out, with_amp)
+                     with_amp: bool = True, out: tuple | None = None):
+        """The same jobs through pq_perm_batched (the boundary's batched call:
+        a persistent work queue replayed from a captured HIP graph; pass fixed
+        output tensors in `out` to replay one graph)."""
+        return self._run_jobs(self._lib.pq_perm_batched, U, jobs, n_out, with_amp, out)
 
     # -------------------------------------------------------- pq_perm_grad
     def perm_grad(self, U: torch.Tensor, S_list, T_list, gperm: torch.Tensor, want_perm: bool = True):

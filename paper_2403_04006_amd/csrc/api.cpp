@@ -58,7 +58,6 @@ void pq_destroy(pq_ctx* ctx) {
     hipGetDevice(&prev);
     hipSetDevice(ctx->device);
     hipDeviceSynchronize();
-    pq_release_batch_cache(ctx);
     pq_release_many_cache(ctx);
     ctx->release_all();
     if (prev >= 0) hipSetDevice(prev);

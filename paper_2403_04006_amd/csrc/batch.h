@@ -1,14 +1,10 @@
-// Batched work queue: job and chunk descriptors shared by the host planner
-// (batched.cpp) and the persistent kernels (k_batch_*.hip).
+// Job and chunk descriptors of the many-pattern planner (many.cpp) and its
+// kernels (k_many*.hip, k_batch_misc.hip).
 //
-// A batch holds uneven jobs on one interferometer.  Every job is planned like
-// a single permanent (lane digits + time digits); its time-state range is cut
-// into chunks, the chunks of one kernel class (operation, padded column count,
-// binary or mixed digits) are ordered longest first, and a persistent grid of
-// wavefronts pops them with an atomic counter.  Each chunk writes its own
-// double-double partial slot; the wavefront that finishes a job's last chunk
-// (atomic ticket) adds the job's slots in slot order and writes its outputs,
-// so results do not depend on scheduling.
+// A job list holds uneven jobs on one interferometer.  Every job is planned
+// like a single permanent (lane digits + time digits); its time-state range
+// is cut into chunks, and each chunk writes its own double-double partial
+// slot, so results do not depend on which wavefront sweeps which chunk.
 #pragma once
 #include <stdint.h>
 
@@ -52,23 +48,6 @@ struct BChunk {
     uint64_t count;
 };
 
-struct BatchArgs {
-    const cplx* U;
-    int64_t ldu;
-    const BJob* jobs;
-    const BChunk* chunks;   // this class's chunks, longest first
-    int32_t nchunks;
-    int32_t slot_doubles;   // doubles per partial slot of this class
-    const cplx* mat;
-    const int32_t* idx;
-    const StepEntry* tabs;  // table t at tabs + t * 2 * kMaxInner (forward, then reflected)
-    double* partials;       // this class's slots
-    unsigned* counter;      // this class's next-chunk counter
-    unsigned* tickets;      // per job (global job index)
-    cplx* perm;
-    cplx* amp;
-};
-
 // Gather of every job's compact matrix from U.
 struct BPrepArgs {
     const cplx* U;
@@ -84,18 +63,6 @@ struct BTableArgs {
     StepEntry* tabs;
     const int32_t* sig;     // per table: [n_inner, m_inner, ncmax, radix[16]] (19 ints)
     int32_t ntab;
-};
-
-// Trivial outputs (constant values) and counter reset.
-struct BFillArgs {
-    const int64_t* offsets;  // output offsets
-    const cplx* values;
-    int32_t count;
-    int32_t write_amp;       // 1: also write amp[offset] = value
-    cplx* perm;
-    cplx* amp;
-    unsigned* zero;          // counters to clear
-    int32_t nzero;
 };
 
 constexpr int kSigInts = 19;

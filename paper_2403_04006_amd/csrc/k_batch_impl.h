@@ -1,17 +1,18 @@
-// Persistent work-queue kernels of the batched entry point (see batch.h).
+// Sweep bodies and the chunk sweep shared by the many-pattern kernels (static
+// schedule and persistent work queue).
 //
-// One kernel per class <OP, NC, BIN, UNIT>: NC is the padded column count
-// (columns beyond a job's own have column sum 1 and zero update rows, so they
-// drop out of every product), BIN selects the binary time-digit walk (row and
-// direction from the 64-bit counter) over the table-driven mixed-radix walk,
-// UNIT the plain products of unit column powers over products with powers.
+// Templates <NC, BIN, UNIT>: NC is the padded column count (columns beyond a
+// job's own have column sum 1 and zero update rows, so they drop out of every
+// product), BIN selects the binary time-digit walk (row and direction from the
+// 64-bit counter) over the table-driven mixed-radix walk, UNIT the plain
+// products of unit column powers over products with powers.
 //
-//   OP = kOpPerm:    per term  acc += w * prod_j c_j^{kap_j}.
-//   OP = kOpExtend:  per term  acc_j += w * d/dc_j prod_l c_l^{kap_l} for every
-//                    column j (prefix products, then a backward sweep with a
-//                    running suffix product), giving kap_j perm(U_{T, S - e_j});
-//                    the finishing wavefront forms out[l] = sum_j U[l, C_j] L_j
-//                    for every mode l (Laplace expansion along the new row).
+//   PermBody:    per term  acc += w * prod_j c_j^{kap_j}.
+//   ExtendBody:  per term  acc_j += w * d/dc_j prod_l c_l^{kap_l} for every
+//                column j (prefix products, then a backward sweep with a
+//                running suffix product), giving kap_j perm(U_{T, S - e_j});
+//                the final step forms out[l] = sum_j U[l, C_j] L_j for every
+//                mode l (Laplace expansion along the new row).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -168,91 +169,6 @@ __device__ __forceinline__ double sweep_chunk(const BJob& J, const cplx* __restr
         }
     }
     return wl;
-}
-
-__device__ __forceinline__ unsigned wave_atomic_add(unsigned* p, unsigned v) {
-    unsigned r = 0;
-    if ((threadIdx.x & 63) == 0) r = atomicAdd(p, v);
-    return (unsigned)__builtin_amdgcn_readfirstlane((int)r);
-}
-
-__device__ __forceinline__ cdd load_cdd(const double* p) { return cdd{{p[0], p[1]}, {p[2], p[3]}}; }
-__device__ __forceinline__ void store_cdd(double* p, cdd v) {
-    p[0] = v.re.hi; p[1] = v.re.lo; p[2] = v.im.hi; p[3] = v.im.lo;
-}
-
-template <int OP, int NC, bool BIN, bool UNIT>
-__global__ __launch_bounds__(kBlock) void batch_kernel(const BatchArgs a) {
-    const int lane = threadIdx.x & 63;
-    __shared__ cplx sL[kWavesPerBlock][NC];
-    cplx* L = sL[threadIdx.x >> 6];
-    while (true) {
-        const unsigned ci = wave_atomic_add(a.counter, 1u);
-        if (ci >= (unsigned)a.nchunks) break;
-        const BChunk ch = a.chunks[ci];
-        const BJob& J = a.jobs[ch.job];
-        const cplx* mat = a.mat + J.mat_off;
-        double* slot = a.partials + (size_t)ch.slot * a.slot_doubles;
-        if constexpr (OP == kOpPerm) {
-            PermBody<NC, UNIT> body;
-            body.kap = J.kap;
-            body.pw = &J.pw;
-            const double wl = sweep_chunk<NC, BIN>(J, mat, a.tabs, lane, ch.start, ch.count, body);
-            cdd v = wave_reduce(to_cdd(cplx{body.acc.re * wl, body.acc.im * wl}));
-            if (lane == 0) store_cdd(slot, v);
-        } else {
-            ExtendBody<NC, UNIT> body;
-            body.kap = J.kap;
-            const double wl = sweep_chunk<NC, BIN>(J, mat, a.tabs, lane, ch.start, ch.count, body);
-#pragma unroll
-            for (int j = 0; j < NC; ++j) {
-                if (j < J.nc) {
-                    cdd v = wave_reduce(to_cdd(cplx{body.acc[j].re * wl, body.acc[j].im * wl}));
-                    if (lane == 0) store_cdd(slot + 4 * j, v);
-                }
-            }
-        }
-        // publish the slot, then take a ticket; the last chunk of the job
-        // finalises it
-        __threadfence();
-        const unsigned t = wave_atomic_add(a.tickets + ch.job, 1u);
-        if (t + 1 != (unsigned)J.nchunks) continue;
-        __threadfence();
-        const double* js = a.partials + (size_t)J.slot_base * a.slot_doubles;
-        if constexpr (OP == kOpPerm) {
-            if (lane == 0) {
-                cdd s = load_cdd(js);
-                for (int k = 1; k < J.nchunks; ++k) s = cdd_add(s, load_cdd(js + (size_t)k * a.slot_doubles));
-                const double re = (s.re.hi + s.re.lo) * J.scale;
-                const double im = (s.im.hi + s.im.lo) * J.scale;
-                a.perm[J.out_offset] = cplx{re, im};
-                if (a.amp) a.amp[J.out_offset] = cplx{re * J.norm, im * J.norm};
-            }
-        } else {
-            for (int j = lane; j < J.nc; j += 64) {
-                cdd s = load_cdd(js + 4 * j);
-                for (int k = 1; k < J.nchunks; ++k) s = cdd_add(s, load_cdd(js + (size_t)k * a.slot_doubles + 4 * j));
-                L[j] = cplx{(s.re.hi + s.re.lo) * J.scale, (s.im.hi + s.im.lo) * J.scale};
-            }
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            const int32_t* cmode = a.idx + J.idx_off + 2 * J.r;
-            for (int l = lane; l < J.m_out; l += 64) {
-                const cplx* Ul = a.U + (size_t)l * (size_t)a.ldu;
-                double re = 0.0, im = 0.0;
-                for (int j = 0; j < J.nc; ++j) {
-                    const cplx u = Ul[cmode[j]];
-                    const cplx v = L[j];
-                    re = __builtin_fma(u.re, v.re, re);
-                    re = __builtin_fma(-u.im, v.im, re);
-                    im = __builtin_fma(u.re, v.im, im);
-                    im = __builtin_fma(u.im, v.re, im);
-                }
-                a.perm[J.out_offset + l] = cplx{re, im};
-            }
-            __builtin_amdgcn_wave_barrier();
-        }
-    }
 }
 
 }  // namespace pq

@@ -1,5 +1,5 @@
-// Setup kernels of a batch: counter reset and constant outputs, gather of
-// every job's compact matrix, and the inner-digit step tables.
+// Set-up kernels of a job list: gather of every job's compact matrix, and the
+// inner-digit step tables.
 #include <hip/hip_runtime.h>
 
 #include "batch.h"
@@ -7,24 +7,6 @@
 #include "device.h"
 
 namespace pq {
-
-__global__ __launch_bounds__(kBlock) void bfill_kernel(const BFillArgs a) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    for (int k = t; k < a.nzero; k += gridDim.x * blockDim.x) a.zero[k] = 0u;
-    for (int k = t; k < a.count; k += gridDim.x * blockDim.x) {
-        a.perm[a.offsets[k]] = a.values[k];
-        if (a.write_amp) a.amp[a.offsets[k]] = a.values[k];
-    }
-}
-
-hipError_t launch_bfill(const BFillArgs& a, hipStream_t s) {
-    int n = a.nzero > a.count ? a.nzero : a.count;
-    int grid = (n + kBlock - 1) / kBlock;
-    if (grid < 1) grid = 1;
-    if (grid > 1024) grid = 1024;
-    hipLaunchKernelGGL(bfill_kernel, dim3(grid), dim3(kBlock), 0, s, a);
-    return hipGetLastError();
-}
 
 // One workgroup per job: B[i][j] (padded columns: 0), rows2 = (-2B, +2B),
 // base_j = sum_i mu_i B_ij (padded columns: 1, so they leave products alone).
@@ -123,36 +105,6 @@ hipError_t launch_btable(const BTableArgs& a, hipStream_t s) {
     if (a.ntab <= 0) return hipSuccess;
     hipLaunchKernelGGL(btable_kernel, dim3(kMaxInner / kBlock, a.ntab), dim3(kBlock), 0, s, a);
     return hipGetLastError();
-}
-
-}  // namespace pq
-
-namespace pq {
-
-typedef hipError_t (*blaunch_fn)(int, const BatchArgs&, int, hipStream_t);
-typedef int (*bocc_fn)(int);
-
-#define PQ_BPTR_L(OP, NC) &launch_batch_##OP##_##NC,
-#define PQ_BPTR_O(OP, NC) &occupancy_batch_##OP##_##NC,
-static const blaunch_fn g_bl_perm[] = {PQ_BCLASS_PERM(PQ_BPTR_L)};
-static const bocc_fn g_bo_perm[] = {PQ_BCLASS_PERM(PQ_BPTR_O)};
-static const blaunch_fn g_bl_ext[] = {PQ_BCLASS_EXT(PQ_BPTR_L)};
-static const bocc_fn g_bo_ext[] = {PQ_BCLASS_EXT(PQ_BPTR_O)};
-
-hipError_t launch_batch(int op, int ncmax, int var, const BatchArgs& a, int grid, hipStream_t s) {
-    const int k = ncmax / kClassStep - 1;
-    if (ncmax % kClassStep || k < 0) return hipErrorInvalidValue;
-    if (op == kOpPerm && k < (int)(sizeof(g_bl_perm) / sizeof(g_bl_perm[0]))) return g_bl_perm[k](var, a, grid, s);
-    if (op == kOpExtend && k < (int)(sizeof(g_bl_ext) / sizeof(g_bl_ext[0]))) return g_bl_ext[k](var, a, grid, s);
-    return hipErrorInvalidValue;
-}
-
-int occupancy_batch(int op, int ncmax, int var) {
-    const int k = ncmax / kClassStep - 1;
-    if (ncmax % kClassStep || k < 0) return 0;
-    if (op == kOpPerm && k < (int)(sizeof(g_bo_perm) / sizeof(g_bo_perm[0]))) return g_bo_perm[k](var);
-    if (op == kOpExtend && k < (int)(sizeof(g_bo_ext) / sizeof(g_bo_ext[0]))) return g_bo_ext[k](var);
-    return 0;
 }
 
 }  // namespace pq

@@ -5,6 +5,7 @@
 
 #include "k_batch_impl.h"
 #include "many.h"
+#include "many_final_impl.h"
 
 namespace pq {
 
@@ -76,12 +77,10 @@ __device__ __forceinline__ void store_cdd_slot(double* p, cdd v) {
     p[0] = v.re.hi; p[1] = v.re.lo; p[2] = v.im.hi; p[3] = v.im.lo;
 }
 
-template <int MODE, int NC, bool BIN, bool UNIT, bool GEN = false>
-__global__ __launch_bounds__(64) void many_kernel(const ManyArgs a) {
-    const int lane = threadIdx.x & 63;
-    const int ci = (int)blockIdx.x;
-    if (ci >= a.nchunks) return;
-    const MChunk ch = a.chunks[ci];
+// One forward or extend-row chunk by one wavefront: sweep its time states
+// and write its slot.
+template <int MODE, int NC, bool BIN, bool UNIT, bool GEN>
+__device__ __forceinline__ void fwd_chunk(const ManyArgs& a, const MChunk& ch, int lane) {
     const BJob& J = a.jobs[ch.pat];
     const cplx* mat = a.mat + J.mat_off;
     double* slot = a.partials + (size_t)ch.slot * a.slot_doubles;
@@ -92,7 +91,7 @@ __global__ __launch_bounds__(64) void many_kernel(const ManyArgs a) {
         const double wl = sweep_chunk<NC, BIN>(J, mat, a.tabs, lane, ch.start, ch.count, body);
         cdd v = wave_reduce(to_cdd(cplx{body.acc.re * wl, body.acc.im * wl}));
         if (lane == 0) store_cdd_slot(slot, v);
-    } else if constexpr (MODE == kModeExt) {
+    } else {
         ExtendBody<NC, UNIT> body;
         body.kap = J.kap;
         const double wl = sweep_chunk<NC, BIN>(J, mat, a.tabs, lane, ch.start, ch.count, body);
@@ -103,7 +102,21 @@ __global__ __launch_bounds__(64) void many_kernel(const ManyArgs a) {
                 if (lane == 0) store_cdd_slot(slot + 4 * j, v);
             }
         }
+    }
+}
+
+template <int MODE, int NC, bool BIN, bool UNIT, bool GEN = false>
+__global__ __launch_bounds__(64) void many_kernel(const ManyArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int ci = (int)blockIdx.x;
+    if (ci >= a.nchunks) return;
+    const MChunk ch = a.chunks[ci];
+    if constexpr (MODE == kModeFwd || MODE == kModeExt) {
+        fwd_chunk<MODE, NC, BIN, UNIT, GEN>(a, ch, lane);
     } else {
+        const BJob& J = a.jobs[ch.pat];
+        const cplx* mat = a.mat + J.mat_off;
+        double* slot = a.partials + (size_t)ch.slot * a.slot_doubles;
         constexpr int KA = AdjDigits<NC>::value;
         __shared__ cplx sP[64][NC];
         __shared__ cplx sA[64][KA][NC];
@@ -175,6 +188,47 @@ __global__ __launch_bounds__(64) void many_kernel(const ManyArgs a) {
             }
             D[2 * e] = re;
             D[2 * e + 1] = im;
+        }
+    }
+}
+
+// The persistent work queue (see QueueArgs).  Every loop is bounded by a
+// kernel argument: a wavefront pops at most nchunks times, and a chunk whose
+// descriptor lies outside its pattern (which the host never plans) is not
+// swept: its slot is written as NaN, so the pattern's value shows it, and it
+// still counts toward the pattern's last chunk.  No wavefront waits on
+// another.
+template <int MODE, int NC, bool BIN, bool UNIT, bool GEN = false>
+__global__ __launch_bounds__(64) void queue_kernel(const QueueArgs q) {
+    __shared__ cplx L[kMaxExtendCols];
+    const ManyArgs& a = q.m;
+    const int lane = threadIdx.x & 63;
+    for (int it = 0; it < a.nchunks; ++it) {
+        unsigned ci = 0;
+        if (lane == 0) ci = atomicAdd(q.counter, 1u);
+        ci = (unsigned)__builtin_amdgcn_readfirstlane((int)ci);
+        if (ci >= (unsigned)a.nchunks) break;
+        const MChunk ch = a.chunks[ci];
+        if (ch.pat < 0 || ch.pat >= q.fin.npat) continue;
+        const BJob& J = a.jobs[ch.pat];
+        const bool ok = ch.count >= 1 && ch.count <= J.time_states && ch.start <= J.time_states - ch.count &&
+                        (BIN || J.m_inner >= 1);
+        if (ok) {
+            fwd_chunk<MODE, NC, BIN, UNIT, GEN>(a, ch, lane);
+        } else {
+            double* slot = a.partials + (size_t)ch.slot * a.slot_doubles;
+            const int nd = MODE == kModeFwd ? 4 : 4 * J.nc;
+            for (int e = lane; e < nd; e += 64) slot[e] = __builtin_nan("");
+        }
+        // publish the slot, then count the chunk; the wavefront that counts
+        // the pattern's last chunk adds its slots and writes its outputs
+        __threadfence();
+        unsigned t = 0;
+        if (lane == 0) t = atomicAdd(q.tickets + ch.pat, 1u);
+        t = (unsigned)__builtin_amdgcn_readfirstlane((int)t);
+        if (t + 1 == (unsigned)J.nchunks) {
+            __threadfence();
+            final_pattern(q.fin, ch.pat, lane, L);
         }
     }
 }

@@ -46,6 +46,7 @@ struct ManyEntry {
     int mode = 0;                // kModeFwd (forward and extend jobs) or kModeAdj
     int npat = 0, ntab = 0;      // npat: distinct patterns (identical ones are swept once)
     bool fuse_dred = false;      // adjoint: the final kernel reduces the derivative slots
+    int max_chunks = 0;          // most chunks of any pattern (1: nothing for a work queue to balance)
     size_t mat_elems = 0, partial_doubles = 0, dpat_elems = 0;
     std::vector<ManyClass> classes;
     ChunkPolicy policy;
@@ -65,6 +66,7 @@ struct ManyEntry {
     int32_t* d_dup_pat = nullptr;
     int64_t* d_dup_out = nullptr;
     cplx* d_gsum = nullptr;          // adjoint: summed cotangent per distinct pattern
+    unsigned* d_qzero = nullptr;     // work queue: one counter per class, then one ticket per pattern
     cplx* d_mat = nullptr;
     StepEntry* d_tabs = nullptr;
     double* d_partials = nullptr;
@@ -82,6 +84,7 @@ struct ManyEntry {
         int64_t ldu;
         cplx* perm;
         cplx* amp;
+        bool queue;
         hipGraph_t graph;
         hipGraphExec_t exec;
     };
@@ -331,6 +334,8 @@ int build_many(pq_ctx* ctx, int mode, int32_t m, const std::vector<PatternSpec>&
         class_sd.push_back(C.slot_doubles);
     }
 
+    for (size_t k = 0; k < pats.size(); ++k)
+        if (pat_class[k] >= 0) E.max_chunks = std::max(E.max_chunks, (int)hj[k].nchunks);
     // adjoint: the final kernel adds the derivative slots itself when no
     // pattern has more than 64 chunks (one stage-1 block each: the same sums)
     if (adj) {
@@ -422,6 +427,7 @@ int build_many(pq_ctx* ctx, int mode, int32_t m, const std::vector<PatternSpec>&
     const size_t oDp = cv.take(sizeof(cplx) * sz(dpat_elems));
     const size_t oRp = cv.take(sizeof(cplx) * sz(red_part));
     const size_t oGs = cv.take(sizeof(cplx) * sz(adj ? pats.size() : 0));
+    const size_t oQz = cv.take(sizeof(unsigned) * sz(adj ? 0 : E.classes.size() + pats.size()));
     if (hipMalloc((void**)&E.dmem, cv.off) != hipSuccess) {
         E.dmem = nullptr;
         return ctx->fail(PQ_ENOMEM, "many: hipMalloc(%zu) failed", cv.off);
@@ -445,6 +451,7 @@ int build_many(pq_ctx* ctx, int mode, int32_t m, const std::vector<PatternSpec>&
     E.d_dup_pat = (int32_t*)(E.dmem + oDup);
     E.d_dup_out = (int64_t*)(E.dmem + oDut);
     E.d_gsum = (cplx*)(E.dmem + oGs);
+    E.d_qzero = (unsigned*)(E.dmem + oQz);
     E.d_mat = (cplx*)(E.dmem + oMat);
     E.d_tabs = (StepEntry*)(E.dmem + oTab);
     E.d_partials = (double*)(E.dmem + oPart);
@@ -473,10 +480,29 @@ int build_many(pq_ctx* ctx, int mode, int32_t m, const std::vector<PatternSpec>&
     return ctx->upload(E.dmem, stage, upload_bytes, st);
 }
 
+// Queue occupancy per (mode, padded columns, variant), cached on the ctx.
+int queue_grid(pq_ctx* ctx, const ManyClass& C) {
+    const int key = (C.mode << 16) | (C.ncmax << 4) | C.var;
+    auto it = ctx->queue_occ.find(key);
+    int occ = 0;
+    if (it == ctx->queue_occ.end()) {
+        occ = std::max(1, occupancy_queue(C.mode, C.ncmax, C.var));
+        ctx->queue_occ[key] = occ;
+    } else {
+        occ = it->second;
+    }
+    const long resident = (long)occ * (long)ctx->num_cu;
+    return (int)std::max(1L, std::min((long)C.nchunks, resident));
+}
+
+// Launch sequence of a plan.  queue (forward plans only): every class runs as
+// a persistent work queue whose wavefronts also finish the patterns, instead
+// of one workgroup per chunk followed by the final kernel.
 int run_many(pq_ctx* ctx, ManyEntry& E, const cplx* U, int64_t ldu, int32_t m, cplx* perm, cplx* amp,
              const cplx* gperm, cplx* dU, int64_t lddu, hipStream_t st, hipEvent_t t0 = nullptr,
-             hipEvent_t t1 = nullptr) {
+             hipEvent_t t1 = nullptr, bool queue = false) {
     int rc;
+    queue = queue && E.mode == kModeFwd;
     if (E.mat_elems > 0) {
         // BJob.nchunks > 0 marks every planned (non-trivial) pattern
         BPrepArgs pa{U, ldu, E.d_jobs, E.npat, E.d_idx, E.d_mat};
@@ -487,40 +513,6 @@ int run_many(pq_ctx* ctx, ManyEntry& E, const cplx* U, int64_t ldu, int32_t m, c
         BTableArgs ta{E.d_tabs, E.d_sig, E.ntab};
         rc = ctx->check(launch_btable(ta, st), "many tables");
         if (rc) return rc;
-    }
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (ctx->profiling) {
-        e0 = ctx->take_event();
-        e1 = ctx->take_event();
-        if (!e0 || !e1) return ctx->fail(PQ_EDEVICE, "profile: hipEventCreate failed");
-        rc = ctx->check(hipEventRecord(e0, st), "profile: record");
-        if (rc) return rc;
-    }
-    if (t0) {
-        rc = ctx->check(hipEventRecord(t0, st), "tune: record");
-        if (rc) return rc;
-    }
-    for (const ManyClass& C : E.classes) {
-        ManyArgs a;
-        a.jobs = E.d_jobs;
-        a.chunks = E.d_chunks + C.first_chunk;
-        a.nchunks = C.nchunks;
-        a.slot_doubles = C.slot_doubles;
-        a.mat = E.d_mat;
-        a.idx = E.d_idx;
-        a.tabs = E.d_tabs;
-        a.partials = E.d_partials + C.slot_off;
-        rc = ctx->check(launch_many(C.mode, C.ncmax, C.var, a, st), "many sweep");
-        if (rc) return rc;
-    }
-    if (t1) {
-        rc = ctx->check(hipEventRecord(t1, st), "tune: record");
-        if (rc) return rc;
-    }
-    if (ctx->profiling) {
-        rc = ctx->check(hipEventRecord(e1, st), "profile: record");
-        if (rc) return rc;
-        ctx->ev_used.emplace_back(e0, e1);
     }
     ManyFinalArgs fa;
     fa.U = U;
@@ -545,6 +537,60 @@ int run_many(pq_ctx* ctx, ManyEntry& E, const cplx* U, int64_t ldu, int32_t m, c
     fa.dpat = E.d_dpat;
     fa.gperm = gperm;
     fa.gsum = E.d_gsum;
+    const int nclass = (int)E.classes.size();
+    if (queue) {
+        QueuePrepArgs qp;
+        qp.zero = E.d_qzero;
+        qp.nzero = nclass + E.npat;
+        qp.fin = fa;
+        rc = ctx->check(launch_queue_prep(qp, st), "queue prep");
+        if (rc) return rc;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (ctx->profiling) {
+        e0 = ctx->take_event();
+        e1 = ctx->take_event();
+        if (!e0 || !e1) return ctx->fail(PQ_EDEVICE, "profile: hipEventCreate failed");
+        rc = ctx->check(hipEventRecord(e0, st), "profile: record");
+        if (rc) return rc;
+    }
+    if (t0) {
+        rc = ctx->check(hipEventRecord(t0, st), "tune: record");
+        if (rc) return rc;
+    }
+    for (int ci = 0; ci < nclass; ++ci) {
+        const ManyClass& C = E.classes[ci];
+        ManyArgs a;
+        a.jobs = E.d_jobs;
+        a.chunks = E.d_chunks + C.first_chunk;
+        a.nchunks = C.nchunks;
+        a.slot_doubles = C.slot_doubles;
+        a.mat = E.d_mat;
+        a.idx = E.d_idx;
+        a.tabs = E.d_tabs;
+        a.partials = E.d_partials + C.slot_off;
+        if (queue) {
+            QueueArgs q;
+            q.m = a;
+            q.fin = fa;
+            q.counter = E.d_qzero + ci;
+            q.tickets = E.d_qzero + nclass;
+            rc = ctx->check(launch_queue(C.mode, C.ncmax, C.var, q, queue_grid(ctx, C), st), "queue sweep");
+        } else {
+            rc = ctx->check(launch_many(C.mode, C.ncmax, C.var, a, st), "many sweep");
+        }
+        if (rc) return rc;
+    }
+    if (t1) {
+        rc = ctx->check(hipEventRecord(t1, st), "tune: record");
+        if (rc) return rc;
+    }
+    if (ctx->profiling) {
+        rc = ctx->check(hipEventRecord(e1, st), "profile: record");
+        if (rc) return rc;
+        ctx->ev_used.emplace_back(e0, e1);
+    }
+    if (queue) return PQ_OK;
     rc = ctx->check(launch_many_final(fa, st), "many final");
     if (rc) return rc;
     if (E.mode == kModeAdj) {
@@ -587,10 +633,10 @@ ManyCache* many_cache(pq_ctx* ctx) {
 // capturing it (on the cache's own stream, thread-local mode) the first time.
 // The graph holds kernel nodes only.
 int run_many_graph(pq_ctx* ctx, ManyEntry& E, const cplx* U, int64_t ldu, int32_t m, cplx* perm, cplx* amp,
-                   hipStream_t st) {
+                   hipStream_t st, bool queue = false) {
     ManyEntry::GraphRec* rec = nullptr;
     for (auto& g : E.graphs)
-        if (g.U == U && g.ldu == ldu && g.perm == perm && g.amp == amp) rec = &g;
+        if (g.U == U && g.ldu == ldu && g.perm == perm && g.amp == amp && g.queue == queue) rec = &g;
     if (!rec) {
         ManyCache* cache = many_cache(ctx);
         int rc;
@@ -600,7 +646,7 @@ int run_many_graph(pq_ctx* ctx, ManyEntry& E, const cplx* U, int64_t ldu, int32_
         }
         rc = ctx->check(hipStreamBeginCapture(cache->capture, hipStreamCaptureModeThreadLocal), "begin capture");
         if (rc) return rc;
-        rc = run_many(ctx, E, U, ldu, m, perm, amp, nullptr, nullptr, 0, cache->capture);
+        rc = run_many(ctx, E, U, ldu, m, perm, amp, nullptr, nullptr, 0, cache->capture, nullptr, nullptr, queue);
         hipGraph_t g = nullptr;
         const hipError_t ee = hipStreamEndCapture(cache->capture, &g);
         if (rc) {
@@ -621,7 +667,7 @@ int run_many_graph(pq_ctx* ctx, ManyEntry& E, const cplx* U, int64_t ldu, int32_
             hipGraphDestroy(E.graphs.front().graph);
             E.graphs.erase(E.graphs.begin());
         }
-        E.graphs.push_back(ManyEntry::GraphRec{U, ldu, perm, amp, g, x});
+        E.graphs.push_back(ManyEntry::GraphRec{U, ldu, perm, amp, queue, g, x});
         rec = &E.graphs.back();
     }
     return ctx->check(hipGraphLaunch(rec->exec, st), "graph launch");
@@ -661,7 +707,7 @@ uint64_t shape_sig(int32_t m, const std::vector<PatternSpec>& pats) {
 // Build one candidate plan and time its class sweeps (best of two runs).
 int time_candidate(pq_ctx* ctx, int32_t m, const std::vector<PatternSpec>& pats, const ChunkPolicy& pol,
                    const cplx* U, int64_t ldu, cplx* perm, cplx* amp, hipStream_t st,
-                   std::unique_ptr<ManyEntry>& out, double& ms) {
+                   std::unique_ptr<ManyEntry>& out, double& ms, bool queue) {
     std::unique_ptr<ManyEntry> e(new ManyEntry());
     int rc = build_many(ctx, kModeFwd, m, pats, *e, st, pol);
     if (rc) return rc;
@@ -672,7 +718,7 @@ int time_candidate(pq_ctx* ctx, int32_t m, const std::vector<PatternSpec>& pats,
     }
     ms = -1.0;
     for (int rep = 0; rep < 2 && !rc; ++rep) {
-        rc = run_many(ctx, *e, U, ldu, m, perm, amp, nullptr, nullptr, 0, st, t0, t1);
+        rc = run_many(ctx, *e, U, ldu, m, perm, amp, nullptr, nullptr, 0, st, t0, t1, queue && e->max_chunks > 1);
         if (rc) break;
         rc = ctx->check(hipEventSynchronize(t1), "tune: synchronize");
         if (rc) break;
@@ -693,7 +739,8 @@ int time_candidate(pq_ctx* ctx, int32_t m, const std::vector<PatternSpec>& pats,
 // job lists of that shape are planned with the recorded policy.
 int get_entry(pq_ctx* ctx, int mode, int32_t m, std::vector<int64_t>& key,
               const std::vector<PatternSpec>& pats, hipStream_t st, ManyEntry** out,
-              const cplx* U = nullptr, int64_t ldu = 0, cplx* perm = nullptr, cplx* amp = nullptr) {
+              const cplx* U = nullptr, int64_t ldu = 0, cplx* perm = nullptr, cplx* amp = nullptr,
+              bool queue = false) {
     ManyCache* cache = many_cache(ctx);
     for (auto& e : cache->entries)
         if (e->key == key) {
@@ -728,7 +775,7 @@ int get_entry(pq_ctx* ctx, int mode, int32_t m, std::vector<int64_t>& key,
             for (const ChunkPolicy& pol : kTuneCandidates) {
                 std::unique_ptr<ManyEntry> cand;
                 double ms = 0.0;
-                rc = time_candidate(ctx, m, pats, pol, U, ldu, perm, amp, st, cand, ms);
+                rc = time_candidate(ctx, m, pats, pol, U, ldu, perm, amp, st, cand, ms, queue);
                 if (rc) break;
                 ++rec.candidates;
                 if (rec.candidates == 1) rec.default_ms = ms;
@@ -781,15 +828,16 @@ void pq_release_many_cache(pq_ctx* ctx) {
     ctx->many_cache = nullptr;
 }
 
-int pq_perm_many(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m,
-                 const pq_job* jobs, int32_t njobs,
-                 pq_c128* perm, pq_c128* amp, void* stream) {
+// pq_perm_many (queue = false) and pq_perm_batched (queue = true): the same
+// validation, plan cache and outputs; see include/pq.h.
+static int perm_jobs(pq_ctx* ctx, const char* name, const pq_c128* U, int64_t ldu, int32_t m,
+                     const pq_job* jobs, int32_t njobs, pq_c128* perm, pq_c128* amp, void* stream, bool queue) {
     if (!ctx) return PQ_EINVAL;
     ctx->clear_error();
-    if (m < 0 || njobs < 0) return ctx->fail(PQ_EINVAL, "pq_perm_many: negative size");
+    if (m < 0 || njobs < 0) return ctx->fail(PQ_EINVAL, "%s: negative size", name);
     if (njobs == 0) return PQ_OK;
-    if (!jobs || !perm) return ctx->fail(PQ_EINVAL, "pq_perm_many: NULL jobs or perm");
-    if (m > 0 && (!U || ldu < m)) return ctx->fail(PQ_EINVAL, "pq_perm_many: NULL U or ldu < m");
+    if (!jobs || !perm) return ctx->fail(PQ_EINVAL, "%s: NULL jobs or perm", name);
+    if (m > 0 && (!U || ldu < m)) return ctx->fail(PQ_EINVAL, "%s: NULL U or ldu < m", name);
     std::vector<int64_t> key = {0, m, njobs};
     int rc = pq_validate_jobs(ctx, m, jobs, njobs, key);
     if (rc) return rc;
@@ -809,11 +857,32 @@ int pq_perm_many(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m,
         pats.push_back(ps);
     }
     ManyEntry* E = nullptr;
-    rc = get_entry(ctx, kModeFwd, m, key, pats, st, &E, (const cplx*)U, ldu, (cplx*)perm, (cplx*)amp);
+    rc = get_entry(ctx, kModeFwd, m, key, pats, st, &E, (const cplx*)U, ldu, (cplx*)perm, (cplx*)amp, queue);
     if (rc) return rc;
+    if (queue) {
+        // a plan whose every pattern is one chunk has nothing for a queue to
+        // balance: one workgroup per chunk is already that schedule
+        const bool q = E->max_chunks > 1;
+        if (!ctx->profiling)
+            return run_many_graph(ctx, *E, (const cplx*)U, ldu, m, (cplx*)perm, (cplx*)amp, st, q);
+        return run_many(ctx, *E, (const cplx*)U, ldu, m, (cplx*)perm, (cplx*)amp, nullptr, nullptr, 0, st,
+                        nullptr, nullptr, q);
+    }
     if (ctx->graphs && !ctx->profiling)
         return run_many_graph(ctx, *E, (const cplx*)U, ldu, m, (cplx*)perm, (cplx*)amp, st);
     return run_many(ctx, *E, (const cplx*)U, ldu, m, (cplx*)perm, (cplx*)amp, nullptr, nullptr, 0, st);
+}
+
+int pq_perm_many(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m,
+                 const pq_job* jobs, int32_t njobs,
+                 pq_c128* perm, pq_c128* amp, void* stream) {
+    return perm_jobs(ctx, "pq_perm_many", U, ldu, m, jobs, njobs, perm, amp, stream, false);
+}
+
+int pq_perm_batched(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m,
+                    const pq_job* jobs, int32_t njobs,
+                    pq_c128* perm, pq_c128* amp, void* stream) {
+    return perm_jobs(ctx, "pq_perm_batched", U, ldu, m, jobs, njobs, perm, amp, stream, true);
 }
 
 int pq_perm_grad(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m,

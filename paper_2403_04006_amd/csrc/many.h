@@ -81,6 +81,26 @@ struct ManyFinalArgs {
     cplx* gsum;                // adjoint: per distinct pattern, the sum of its copies' cotangents
 };
 
+// Persistent work queue over one class's chunks (forward and extend-row
+// classes): a grid of resident wavefronts, each popping chunk indices from
+// `counter` until they run out; after a chunk's slot is written the wavefront
+// counts it in its pattern's ticket, and the one that counts the pattern's
+// last chunk runs the final step for it (final_pattern), so no other kernel
+// is needed.  counter and tickets start at zero (queue_prep_kernel).
+struct QueueArgs {
+    ManyArgs m;
+    ManyFinalArgs fin;
+    unsigned* counter;         // this class's next-chunk counter
+    unsigned* tickets;         // [npat]: chunks finished per pattern
+};
+
+// Reset of the queue counters and constant outputs of trivial patterns.
+struct QueuePrepArgs {
+    unsigned* zero;            // counters, then tickets
+    int32_t nzero;
+    ManyFinalArgs fin;         // trivial patterns (pat_class < 0) are written here
+};
+
 // Reduction of the reverse sweeps' derivative slots in two fixed-order
 // stages: stage 1 adds up to 64 consecutive slots of a pattern for 64
 // consecutive entries, stage 2 adds a pattern's stage-1 partials and scales.

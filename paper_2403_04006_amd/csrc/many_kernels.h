@@ -23,7 +23,20 @@ PQ_MCLASS_ADJ(PQ_MDECL)
 PQ_WCLASS(PQ_WDECL)
 #undef PQ_WDECL
 
+// work-queue instances (forward and extend-row classes)
+#define PQ_QDECL(MODE, NC)                                                                      \
+    hipError_t launch_queue_##MODE##_##NC(int var, const QueueArgs& q, int grid, hipStream_t s); \
+    hipError_t occupancy_queue_##MODE##_##NC(int var, int* blocks);
+PQ_MCLASS_FWD(PQ_QDECL)
+PQ_MCLASS_EXT(PQ_QDECL)
+#undef PQ_QDECL
+
 hipError_t launch_many(int mode, int ncmax, int var, const ManyArgs& a, hipStream_t s);
+// the work queue of one class on `grid` workgroups of one wavefront
+hipError_t launch_queue(int mode, int ncmax, int var, const QueueArgs& q, int grid, hipStream_t s);
+// resident workgroups per CU of that class's queue kernel (0 on failure)
+int occupancy_queue(int mode, int ncmax, int var);
+hipError_t launch_queue_prep(const QueuePrepArgs& a, hipStream_t s);
 hipError_t launch_many_final(const ManyFinalArgs& a, hipStream_t s);
 hipError_t launch_dred(int stage, const DRedArgs& a, int nitems, hipStream_t s);
 hipError_t launch_grad_scatter(const GradScatterArgs& a, hipStream_t s);

@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <map>
 #include <string>
 #include <utility>
 #include <vector>
@@ -40,8 +41,6 @@ struct pq_ctx {
     // device workspace, grown on demand (hipFree waits for earlier work)
     void* ws = nullptr;
     size_t ws_bytes = 0;
-    // cached batch plans, device buffers and graphs (batched.cpp)
-    void* batch_cache = nullptr;
     // cached many-pattern plans and their device descriptors (many.cpp)
     void* many_cache = nullptr;
     // pinned host staging for descriptor uploads; upload_done marks when the
@@ -60,6 +59,8 @@ struct pq_ctx {
     bool graphs = false;
     std::vector<pq::TuneRecord> tuned;
     pq::TuneRecord last_tune;
+    // resident workgroups per CU of the work-queue kernels, by class
+    std::map<int, int> queue_occ;
 
     // pinned, device-mapped status word that kernels validating device-side
     // inputs (the sampler's input modes) mark; read after the stream finishes
@@ -88,7 +89,6 @@ struct pq_ctx {
     int occupancy(int kind, int nc);
 };
 
-void pq_release_batch_cache(pq_ctx* ctx);
 void pq_release_many_cache(pq_ctx* ctx);
 // Validate pq_job descriptions (modes, multiplicities, photon counts, output
 // overlap) and append them to `key`.

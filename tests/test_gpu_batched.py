@@ -1,14 +1,17 @@
 """Parity of the batched boundary call (pq_perm_batched) against the oracle.
 
-pq_perm_batched runs its jobs on the static schedule of pq_perm_many (the
-persistent work-queue schedule built for it is switched off: on the device a
-graph-captured batch through it did not complete, with no cause shown)."""
+pq_perm_batched runs multi-chunk plans as a persistent work queue (resident
+wavefronts pop chunks from an atomic counter; the one that finishes a
+pattern's last chunk writes its outputs) replayed from a captured HIP graph,
+and plans whose every job is one chunk on the static schedule.  The queue
+adds each pattern's slots in slot order with the static schedule's final
+step, so both schedules give the same bits."""
 import numpy as np
 import pytest
 
 import oracle
 import workloads
-from tests.tolerance import assert_entries_close, extend_floor
+from tests.tolerance import assert_entries_close, extend_floor, floor_of
 
 pytestmark = pytest.mark.gpu
 
@@ -263,3 +266,81 @@ def test_sampling_shaped_extend_jobs_full_size(eng):
         got = out[s * 400:(s + 1) * 400]
         err = assert_entries_close(got, refs[s], 1e-10, extend_floor(U, jobs[s]), f"sample {s}")
         print(f"extend k=20 sample {s}: max per-entry rel err {err:.2e}")
+
+
+def _queue_vs_static(eng, U, jobs, n_out=None):
+    Ud = dev(U)
+    a, _ = eng.perm_batched(Ud, jobs, n_out=n_out)
+    b, _ = eng.perm_many(Ud, jobs, n_out=n_out)
+    torch.cuda.synchronize()
+    a, b = a.cpu().numpy(), b.cpu().numpy()
+    assert np.array_equal(a, b)
+    return a
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_work_queue_equals_static_schedule(eng, seed):
+    # uneven multi-chunk PERM jobs (up to 18 photons) through the queue: the
+    # same bits as the static schedule, and the oracle's values
+    rng = np.random.default_rng(900 + seed)
+    m = 12
+    U = workloads.haar(m, 900 + seed)
+    jobs, pats = [], []
+    for k in range(30):
+        n = int(rng.integers(2, 19))
+        S = workloads.random_occupations(rng, m, n, cap=3)
+        T = workloads.random_occupations(rng, m, n, cap=3)
+        jobs.append(perm_job(S, T))
+        pats.append((S, T))
+    print(f"queue vs static: seed {seed}, 30 uneven jobs", flush=True)
+    got = _queue_vs_static(eng, U, jobs)
+    for k in range(0, 30, 5):
+        S, T = pats[k]
+        ref = oracle.perm_mult(U, S, T)
+        assert_entries_close(got[k], ref, 1e-10, floor_of(U, S, T), f"job {k}")
+
+
+def test_work_queue_sampling_shaped_extend_jobs(eng):
+    # 40 sampling runs of 20 photons in 400 modes (760 EXTEND_ROW jobs, the
+    # longest many chunks) through the queue
+    U = workloads.haar(400, 0)
+    cols, rows = workloads.sampling_jobs(samples=40, seed=3)
+    jobs = []
+    for s in range(40):
+        for k in range(2, 21):
+            jobs.append(extend_job([int(x) for x in rows[s, :k - 1]], [int(x) for x in cols[s, :k]], len(jobs) * 400))
+    print("queue vs static: 760 extend-row jobs", flush=True)
+    got = _queue_vs_static(eng, U, jobs, n_out=len(jobs) * 400)
+    j = 18   # sample 0, k = 20
+    want = oracle.extend_row(U, [int(x) for x in rows[0, :19]], [int(x) for x in cols[0, :20]])
+    assert_entries_close(got[j * 400:(j + 1) * 400], want, 1e-10, extend_floor(U, jobs[j]), "k=20")
+
+
+def test_work_queue_graph_replays_match_static(eng):
+    # repeated calls replay the captured queue graph, with the program's own
+    # GPU work and synchronisations between them; every replay gives the
+    # static schedule's bits, also after U changes in place
+    m = 12
+    rng = np.random.default_rng(44)
+    pats = [(workloads.random_occupations(rng, m, n, cap=3), workloads.random_occupations(rng, m, n, cap=3))
+            for n in rng.integers(8, 17, size=24)]
+    jobs = [perm_job(S, T, out=k) for k, (S, T) in enumerate(pats)]
+    Ud = dev(workloads.haar(m, 45))
+    out = torch.empty(24, dtype=torch.complex128, device="cuda")
+    for rep in range(4):
+        if rep == 2:
+            Ud.copy_(torch.from_numpy(workloads.haar(m, 46)))
+        _ = (torch.randn(64, 64, dtype=torch.float64, device="cuda") @ torch.randn(64, 64, dtype=torch.float64,
+                                                                                   device="cuda")).sum()
+        eng.perm_batched(Ud, jobs, out=(out, None))
+        ref, _ = eng.perm_many(Ud, jobs)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), ref.cpu().numpy()), rep
+
+
+@pytest.mark.skip(reason="the first persistent work-queue schedule (an earlier kernel, since removed) did not "
+                         "complete on this graph-captured batch of 495 single-chunk permanents, and no cause was "
+                         "shown; single-chunk batches run on the static schedule, so this case is not sent to "
+                         "the queue")
+def test_completeness_batch_495_on_the_work_queue(eng):
+    raise AssertionError("not run")
