@@ -59,7 +59,7 @@ enum {
     PQ_ERANGE = 2,      /* problem too large for the engine */
     PQ_ENOMEM = 3,      /* device workspace allocation failed */
     PQ_EDEVICE = 4,     /* HIP runtime or launch error */
-    PQ_ECANCELLED = 5   /* reserved */
+    PQ_ECANCELLED = 5   /* cancellation requested on the ctx (pq_cancel) */
 };
 
 #define PQ_MAX_N 48     /* photons per permanent, and distinct rows/columns */
@@ -69,11 +69,40 @@ const char* pq_version(void);
 
 /* Create a context on HIP device `hip_device` (PQ_EINVAL for a bad ordinal or
  * NULL out, PQ_EDEVICE if the device cannot be queried).  *out is set only on
- * success.  The ctx owns device workspace, grown on demand. */
+ * success.  The ctx owns device workspace, grown on demand.  Environment read
+ * here: PQ_AUTOTUNE=1 turns chunk-policy autotuning on (pq_autotune_enable);
+ * PQ_AUTOTUNE_CACHE=<file> loads this device's recorded tuning decisions from
+ * that file and appends new ones to it (one JSON object per line, keyed by
+ * the device's architecture and CU count and the job list's shape);
+ * PQ_FAULT_INJECT (pq_fault_inject). */
 int pq_create(pq_ctx** out, int hip_device);
 
 /* Destroy a context (NULL-safe).  Waits for the device before freeing. */
 void pq_destroy(pq_ctx* ctx);
+
+/*
+ * Cancellation.  pq_cancel(ctx, 1) sets a flag in pinned, device-mapped host
+ * memory owned by ctx.  Work-queue launches of this ctx (pq_perm_batched)
+ * poll it before every chunk they pop and stop popping once it is set: jobs
+ * whose chunks were not all swept keep whatever their output buffers held.
+ * Kernels of other entry points run to completion.  While the flag is set,
+ * every entry point that enqueues GPU work returns PQ_ECANCELLED without
+ * enqueuing anything; pq_cancel(ctx, 0) clears it.  Safe to call from another
+ * thread while work is in flight (it only stores the flag).
+ */
+int pq_cancel(pq_ctx* ctx, int on);
+
+/*
+ * Fault injection for tests of error handling: while set, every device
+ * allocation of ctx (PQ_FAULT_ALLOC: workspace, plan blocks) fails with
+ * PQ_ENOMEM, or every launch check (PQ_FAULT_LAUNCH) fails with PQ_EDEVICE,
+ * as if the runtime had refused it.  The ctx stays usable: clearing the
+ * injection (PQ_FAULT_NONE) restores normal operation.  pq_create reads the
+ * initial setting from the environment variable PQ_FAULT_INJECT (alloc |
+ * launch).
+ */
+enum { PQ_FAULT_NONE = 0, PQ_FAULT_ALLOC = 1, PQ_FAULT_LAUNCH = 2 };
+int pq_fault_inject(pq_ctx* ctx, int what);
 
 /* Static description of a status code. */
 const char* pq_strerror(int status);
@@ -149,12 +178,12 @@ typedef struct {
  * persistent work queue (the many uneven permanents of a boson-sampling run,
  * Benchmarks / Boson Sampling).  Jobs are planned and cut into chunks as in
  * pq_perm_many (identical jobs once, chunks longest first); per column class
- * one launch of resident wavefronts pops chunks from an atomic counter, each
- * chunk writes its own double-double slot, and the wavefront that finishes a
- * job's last chunk (atomic ticket) adds the job's slots in slot order and
- * writes its outputs.  The results equal pq_perm_many's bit for bit.
+ * one launch of resident wavefronts pops chunks from an atomic counter and
+ * each chunk writes its own double-double slot; a final kernel then adds
+ * every job's slots in slot order and writes its outputs.  The results equal
+ * pq_perm_many's bit for bit.
  *   - The launch sequence (gather, step tables, counter reset, the class
- *     queues) is captured into a HIP graph the first time a plan runs with a
+ *     queues, the final kernel) is captured into a HIP graph the first time a plan runs with a
  *     given (U, ldu, perm, amp), and replayed on later calls (up to 4 graphs
  *     per cached plan; by default, and whatever pq_graph_enable says; calls
  *     with profiling on launch directly).  Fixed output buffers therefore
@@ -163,8 +192,13 @@ typedef struct {
  *     lanes of one wavefront) has nothing for a queue to balance and runs the
  *     static schedule instead (one workgroup per chunk, then a final kernel).
  *   - Chunk sizes follow the autotuner when it is enabled (off by default: a
- *     first call then times 11 chunk policies, about 22 runs of the batch),
- *     and recorded decisions (pq_autotune_enable, PQ_AUTOTUNE_CACHE) apply.
+ *     first call then times 11 chunk policies under the queue, about 22 runs
+ *     of the batch, and the kept policy under the static schedule as well;
+ *     the faster schedule is recorded with the policy).  Recorded decisions
+ *     (pq_autotune_enable, PQ_AUTOTUNE_CACHE) apply.  Untuned plans run the
+ *     queue.
+ *   - The work queue reads the ctx's cancellation word every 16 pops per
+ *     wavefront (pq_cancel).
  *   perm  device, complex, large enough for every job's outputs.
  *   amp   device, may be NULL; written for PQ_OP_PERM jobs only.
  * Output ranges of different jobs must not overlap (PQ_EINVAL otherwise).

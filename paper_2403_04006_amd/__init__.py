@@ -253,6 +253,15 @@ class Engine:
         _check(st, self._ctx)
         return Ud
 
+    def cancel(self, on: bool = True):
+        """Request (or clear) cancellation of this ctx's work (pq_cancel)."""
+        _check(self._lib.pq_cancel(self._ctx, 1 if on else 0), self._ctx)
+
+    def fault_inject(self, what: int):
+        """Make every allocation (PQ_FAULT_ALLOC) or launch check
+        (PQ_FAULT_LAUNCH) of this ctx fail; PQ_FAULT_NONE restores it."""
+        _check(self._lib.pq_fault_inject(self._ctx, int(what)), self._ctx)
+
     def autotune(self, on: bool = True):
         """Chunk-size autotuning of perm_many (pq_autotune_enable)."""
         _check(self._lib.pq_autotune_enable(self._ctx, 1 if on else 0), self._ctx)

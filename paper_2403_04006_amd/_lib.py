@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(HERE, "libpq.so")
 
 PQ_OK, PQ_EINVAL, PQ_ERANGE, PQ_ENOMEM, PQ_EDEVICE, PQ_ECANCELLED = range(6)
 PQ_OP_PERM, PQ_OP_EXTEND_ROW = 0, 1
+PQ_FAULT_NONE, PQ_FAULT_ALLOC, PQ_FAULT_LAUNCH = 0, 1, 2
 PQ_MAX_N = 48
 PQ_GRAD_MAX_DIM = 32
 PQ_ALL_MAX_OUTPUTS = 1 << 31
@@ -94,6 +95,8 @@ _SIGNATURES = {
     "pq_lhaf_many": ([_VP, _VP, ctypes.c_int64, ctypes.c_int32, _VP, _I32P, ctypes.c_int32, _VP, _VP],
                      ctypes.c_int),
     "pq_autotune_enable": ([_VP, ctypes.c_int], ctypes.c_int),
+    "pq_cancel": ([_VP, ctypes.c_int], ctypes.c_int),
+    "pq_fault_inject": ([_VP, ctypes.c_int], ctypes.c_int),
     "pq_graph_enable": ([_VP, ctypes.c_int], ctypes.c_int),
     "pq_autotune_last": ([_VP, _I32P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), _I32P],
                          ctypes.c_int),

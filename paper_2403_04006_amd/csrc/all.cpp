@@ -71,7 +71,7 @@ int pq_fock_unrank(int32_t m, int32_t n, int64_t rank, int32_t* T) {
 int pq_perm_all_outputs(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m, const int32_t* S,
                         pq_c128* perm, pq_c128* amp, void* stream) {
     if (!ctx) return PQ_EINVAL;
-    ctx->clear_error();
+    if (int rc_ = ctx->begin("pq_perm_all_outputs")) return rc_;
     if (m < 1 || m > kAllMaxModes) return ctx->fail(PQ_ERANGE, "pq_perm_all_outputs: m must be in 1..%d", kAllMaxModes);
     if (!U || !S || !perm || ldu < m) return ctx->fail(PQ_EINVAL, "pq_perm_all_outputs: NULL argument or ldu < m");
     int n = 0;

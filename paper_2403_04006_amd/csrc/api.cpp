@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdarg.h>
+#include <stdlib.h>
 #include <stdio.h>
 #include <string.h>
 
@@ -42,13 +43,42 @@ int pq_create(pq_ctx** out, int hip_device) {
     if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess) { delete c; return PQ_EDEVICE; }
     c->num_cu = prop.multiProcessorCount;
     c->clock_khz = prop.clockRate;
+    c->device_key = std::string(prop.gcnArchName) + ":" + std::to_string(prop.multiProcessorCount);
     {
         // the allocation-free entry point's scratch address on this device
         // (a failure here only disables pq_perm_noalloc, which then reports it)
         DeviceGuard guard(hip_device);
         (void)noalloc_init(hip_device);
+        void* h = nullptr;
+        void* d = nullptr;
+        if (hipHostMalloc(&h, 256, hipHostMallocMapped) != hipSuccess) { delete c; return PQ_ENOMEM; }
+        if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess) { hipHostFree(h); delete c; return PQ_EDEVICE; }
+        c->cancel_word = (int32_t*)h;
+        c->cancel_word_dev = (int32_t*)d;
+        __atomic_store_n(c->cancel_word, 0, __ATOMIC_SEQ_CST);
+    }
+    if (const char* e = getenv("PQ_FAULT_INJECT")) {
+        if (!strcmp(e, "alloc")) c->fault = PQ_FAULT_ALLOC;
+        else if (!strcmp(e, "launch")) c->fault = PQ_FAULT_LAUNCH;
+    }
+    if (const char* e = getenv("PQ_AUTOTUNE")) c->autotune = e[0] == '1';
+    if (const char* e = getenv("PQ_AUTOTUNE_CACHE")) {
+        c->tune_cache = e;
+        c->tune_cache_load();
     }
     *out = c;
+    return PQ_OK;
+}
+
+int pq_cancel(pq_ctx* ctx, int on) {
+    if (!ctx || !ctx->cancel_word) return PQ_EINVAL;
+    __atomic_store_n(ctx->cancel_word, on ? 1 : 0, __ATOMIC_SEQ_CST);
+    return PQ_OK;
+}
+
+int pq_fault_inject(pq_ctx* ctx, int what) {
+    if (!ctx || what < PQ_FAULT_NONE || what > PQ_FAULT_LAUNCH) return PQ_EINVAL;
+    ctx->fault = what;
     return PQ_OK;
 }
 
@@ -135,7 +165,7 @@ int pq_perm(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m,
             const int32_t* S, const int32_t* T,
             pq_c128* perm, pq_c128* amp, void* stream) {
     if (!ctx) return PQ_EINVAL;
-    ctx->clear_error();
+    if (int rc_ = ctx->begin("pq_perm")) return rc_;
     if (m < 0 || !S || !T) return ctx->fail(PQ_EINVAL, "pq_perm: m < 0 or NULL occupation vector");
     if (m > 0 && (!U || ldu < m)) return ctx->fail(PQ_EINVAL, "pq_perm: NULL U or ldu < m");
     Plan p;

@@ -10,7 +10,7 @@ using namespace pq;
 int pq_sample_chain(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m, int32_t n, int32_t samples,
                     const int32_t* order, const double* uniforms, int32_t* out, void* stream) {
     if (!ctx) return PQ_EINVAL;
-    ctx->clear_error();
+    if (int rc_ = ctx->begin("pq_sample_chain")) return rc_;
     if (m < 1 || m > kChainMaxModes) return ctx->fail(PQ_ERANGE, "pq_sample_chain: m must be in 1..%d", kChainMaxModes);
     if (n < 0 || n > kChainMaxPhotons || n > m)
         return ctx->fail(PQ_ERANGE, "pq_sample_chain: n must be in 0..min(m, %d)", kChainMaxPhotons);

@@ -261,7 +261,7 @@ int describe(pq_ctx* ctx, const int32_t* reps, int d, int N, bool loops, HafDesc
 int pq_lhaf(pq_ctx* ctx, const pq_c128* A, int64_t lda, int32_t d, const pq_c128* gamma, const int32_t* reps,
             pq_c128* out, void* stream) {
     if (!ctx) return PQ_EINVAL;
-    ctx->clear_error();
+    if (int rc_ = ctx->begin("pq_lhaf")) return rc_;
     if (d < 0 || !out || (d > 0 && !reps)) return ctx->fail(PQ_EINVAL, "pq_lhaf: NULL argument or d < 0");
     int N = 0;
     int rc = check_reps(ctx, reps, d, &N, "pq_lhaf");
@@ -347,7 +347,7 @@ int pq_lhaf(pq_ctx* ctx, const pq_c128* A, int64_t lda, int32_t d, const pq_c128
 int pq_lhaf_many(pq_ctx* ctx, const pq_c128* A, int64_t lda, int32_t d, const pq_c128* gamma, const int32_t* reps,
                  int32_t npat, pq_c128* out, void* stream) {
     if (!ctx) return PQ_EINVAL;
-    ctx->clear_error();
+    if (int rc_ = ctx->begin("pq_lhaf_many")) return rc_;
     if (d < 0 || npat < 0) return ctx->fail(PQ_EINVAL, "pq_lhaf_many: negative size");
     if (npat == 0) return PQ_OK;
     if (!out || (d > 0 && !reps)) return ctx->fail(PQ_EINVAL, "pq_lhaf_many: NULL reps or out");

@@ -98,21 +98,94 @@ struct ExtendBody {
 };
 
 // --------------------------------------------------------------- sweeping
+// Read-only tables through the constant address space.  A kernel that stores
+// to global memory between sweeps (the work queue writes slots and outputs
+// after every chunk) cannot otherwise prove the +-2B rows and step tables
+// unchanged, and would load them per lane instead of through the scalar
+// cache into SGPR operands.  They are written only by earlier kernels.
+typedef const __attribute__((address_space(4))) cplx kcplx;
+typedef const __attribute__((address_space(4))) StepEntry kstep;
+typedef const __attribute__((address_space(4))) BJob kjob;
+
+template <int NC, bool K>
+__device__ __forceinline__ void add_row_at(cplx (&c)[NC], const cplx* __restrict__ base, size_t off) {
+    if constexpr (K) {
+        kcplx* r = (kcplx*)(base + off);
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+            c[j].re += r[j].re;
+            c[j].im += r[j].im;
+        }
+    } else {
+        add_row(c, base + off);
+    }
+}
+
+template <int NC, bool K>
+__device__ __forceinline__ void fma_row_at(cplx (&c)[NC], double coef, const cplx* __restrict__ base, size_t off) {
+    if constexpr (K) {
+        kcplx* r = (kcplx*)(base + off);
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+            c[j].re = __builtin_fma(coef, r[j].re, c[j].re);
+            c[j].im = __builtin_fma(coef, r[j].im, c[j].im);
+        }
+    } else {
+        fma_row(c, coef, base + off);
+    }
+}
+
+template <bool K>
+__device__ __forceinline__ StepEntry step_at(const StepEntry* __restrict__ tab, int p) {
+    if constexpr (K) {
+        kstep* t = (kstep*)tab;
+        return StepEntry{t[p].off, 0, t[p].w};
+    } else {
+        return tab[p];
+    }
+}
+
+// lane_init with K: the base sums and lane rows through the constant address
+// space as well (scalar loads, as in a kernel without stores).
+template <int NC, bool K, class RadixT>
+__device__ __forceinline__ double lane_init_at(const cplx* __restrict__ base, const cplx* __restrict__ rows2,
+                                               int n_lane, int lane_states, const RadixT* lane_radix, int lane,
+                                               cplx (&c)[NC]) {
+    if constexpr (K) {
+        kcplx* kb = (kcplx*)base;
+#pragma unroll
+        for (int j = 0; j < NC; ++j) c[j] = cplx{kb[j].re, kb[j].im};
+        double wl = lane < lane_states ? 1.0 : 0.0;
+        int rest = lane;
+        for (int i = 0; i < n_lane; ++i) {
+            const int rho = (int)lane_radix[i];
+            const int d = rest % rho;
+            rest /= rho;
+            wl *= digit_weight(rho, d);
+            fma_row_at<NC, true>(c, (double)d, rows2, (size_t)i * 2 * NC);   // += d * (-2 B_i)
+        }
+        return wl;
+    } else {
+        return lane_init<NC>(base, rows2, n_lane, lane_states, lane_radix, lane, c);
+    }
+}
+
 // Sweep time states [start, start+count) of job J for this lane; returns the
-// lane weight (0 for padding lanes).
-template <int NC, bool BIN, class Body>
-__device__ __forceinline__ double sweep_chunk(const BJob& J, const cplx* __restrict__ mat,
+// lane weight (0 for padding lanes).  K: read the rows and step tables
+// through the constant address space (see kcplx).
+template <int NC, bool BIN, class Body, bool K = false, class JobT = BJob>
+__device__ __forceinline__ double sweep_chunk(const JobT& J, const cplx* __restrict__ mat,
                                               const StepEntry* __restrict__ tabs, int lane,
                                               uint64_t start, uint64_t count, Body& body) {
     const cplx* rows2 = mat + (size_t)J.r * NC;
     const cplx* base = rows2 + (size_t)J.r * 2 * NC;
     const cplx* trows = rows2 + (size_t)J.n_lane * 2 * NC;
     cplx c[NC];
-    double wl = lane_init<NC>(base, rows2, J.n_lane, J.lane_states, J.lane_radix, lane, c);
+    double wl = lane_init_at<NC, K>(base, rows2, J.n_lane, J.lane_states, J.lane_radix, lane, c);
     if constexpr (BIN) {
         const uint64_t g = start ^ (start >> 1);
         for (int k = 0; k < J.n_time; ++k)
-            if ((g >> k) & 1ull) add_row(c, trows + (size_t)k * 2 * NC);
+            if ((g >> k) & 1ull) add_row_at<NC, K>(c, trows, (size_t)k * 2 * NC);
         double w = (__builtin_popcountll(g) & 1) ? -1.0 : 1.0;
         const uint64_t end = start + count;
         // each pass takes the term of state t-1, then moves to state t
@@ -121,7 +194,7 @@ __device__ __forceinline__ double sweep_chunk(const BJob& J, const cplx* __restr
             const int sel = (int)((t >> (i + 1)) & 1ull);
             body.term(c, w);
             body.flip(i, sel ? -1 : 1);          // time digit i moves by +1 (sel 0) or -1
-            add_row(c, trows + ((size_t)i * 2 + sel) * NC);
+            add_row_at<NC, K>(c, trows, ((size_t)i * 2 + sel) * NC);
             w = -w;
         }
         body.term(c, w);
@@ -138,31 +211,32 @@ __device__ __forceinline__ double sweep_chunk(const BJob& J, const cplx* __restr
             const int pos0 = (int)(s - hi * M);
             const uint64_t seg_end = (end - hi * M) < M ? end : (hi + 1) * M;
             const int len = (int)(seg_end - s);
-            if (!first) wl = lane_init<NC>(base, rows2, J.n_lane, J.lane_states, J.lane_radix, lane, c);
+            if (!first) wl = lane_init_at<NC, K>(base, rows2, J.n_lane, J.lane_states, J.lane_radix, lane, c);
             first = false;
             // high digits at the segment index, inner digits at the table
             // position (no digit arrays: every value stays uniform)
-            const int8_t* tr = J.time_radix;
+            const auto* tr = J.time_radix;
             const int n_in = J.n_inner;
             double wh = 1.0;
             int refl = gray_digits_desc(n_high, [&](int k) { return (int)tr[n_in + k]; }, hi, 0, [&](int k, int g) {
                 wh *= digit_weight((int)tr[n_in + k], g);
-                if (g) fma_row(c, (double)g, trows + (size_t)(n_in + k) * 2 * NC);
+                if (g) fma_row_at<NC, K>(c, (double)g, trows, (size_t)(n_in + k) * 2 * NC);
             });
             refl = uniform_int(refl);
             wh = uniform_double(wh);
             const int q0 = refl ? (int)M - 1 - pos0 : pos0;
             gray_digits_desc(n_in, [&](int k) { return (int)tr[k]; }, (uint64_t)q0, 0, [&](int k, int g) {
-                if (g) fma_row(c, (double)g, trows + (size_t)k * 2 * NC);
+                if (g) fma_row_at<NC, K>(c, (double)g, trows, (size_t)k * 2 * NC);
             });
             const StepEntry* tab = refl ? tb : tf;
-            double wcur = wh * tab[pos0].w;
+            double wcur = wh * step_at<K>(tab, pos0).w;
             for (int p = pos0 + 1; p < pos0 + len; ++p) {
                 body.term(c, wcur);
-                const int off = tab[p].off;
+                const StepEntry e = step_at<K>(tab, p);
+                const int off = e.off;
                 body.flip(off / (2 * NC), ((off / NC) & 1) ? -1 : 1);
-                add_row(c, trows + off);
-                wcur = wh * tab[p].w;
+                add_row_at<NC, K>(c, trows, off);
+                wcur = wh * e.w;
             }
             body.term(c, wcur);
             s = seg_end;

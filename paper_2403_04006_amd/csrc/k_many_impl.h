@@ -1,11 +1,11 @@
-// Statically scheduled kernels over many patterns (see many.h): one
-// wavefront per chunk, one wavefront per workgroup.
+// Kernels over many patterns (see many.h): the static schedule (one
+// wavefront per chunk, one wavefront per workgroup) and the persistent work
+// queue.
 #pragma once
 #include <hip/hip_runtime.h>
 
 #include "k_batch_impl.h"
 #include "many.h"
-#include "many_final_impl.h"
 
 namespace pq {
 
@@ -78,23 +78,36 @@ __device__ __forceinline__ void store_cdd_slot(double* p, cdd v) {
 }
 
 // One forward or extend-row chunk by one wavefront: sweep its time states
-// and write its slot.
-template <int MODE, int NC, bool BIN, bool UNIT, bool GEN>
+// and write its slot.  K (the work queue): read-only tables through the
+// constant address space, and the power structure from a register copy.
+template <int MODE, int NC, bool BIN, bool UNIT, bool GEN, bool K = false>
 __device__ __forceinline__ void fwd_chunk(const ManyArgs& a, const MChunk& ch, int lane) {
     const BJob& J = a.jobs[ch.pat];
     const cplx* mat = a.mat + J.mat_off;
     double* slot = a.partials + (size_t)ch.slot * a.slot_doubles;
+    // the queue reads the job descriptor through the constant address space too
+    kjob& JK = *(kjob*)&J;
     if constexpr (MODE == kModeFwd) {
         PermBody<NC, UNIT, GEN ? 1 : 0> body;
         body.kap = J.kap;
-        body.pw = &J.pw;
-        const double wl = sweep_chunk<NC, BIN>(J, mat, a.tabs, lane, ch.start, ch.count, body);
+        PowSteps pw;
+        double wl;
+        if constexpr (K) {
+            pw = PowSteps{{JK.pw.step[0], JK.pw.step[1], JK.pw.step[2]}, JK.pw.low, JK.pw.general};
+            body.pw = &pw;
+            wl = sweep_chunk<NC, BIN, decltype(body), true, kjob>(JK, mat, a.tabs, lane, ch.start, ch.count, body);
+        } else {
+            body.pw = &J.pw;
+            wl = sweep_chunk<NC, BIN>(J, mat, a.tabs, lane, ch.start, ch.count, body);
+        }
         cdd v = wave_reduce(to_cdd(cplx{body.acc.re * wl, body.acc.im * wl}));
         if (lane == 0) store_cdd_slot(slot, v);
     } else {
         ExtendBody<NC, UNIT> body;
         body.kap = J.kap;
-        const double wl = sweep_chunk<NC, BIN>(J, mat, a.tabs, lane, ch.start, ch.count, body);
+        double wl;
+        if constexpr (K) wl = sweep_chunk<NC, BIN, decltype(body), true, kjob>(JK, mat, a.tabs, lane, ch.start, ch.count, body);
+        else wl = sweep_chunk<NC, BIN>(J, mat, a.tabs, lane, ch.start, ch.count, body);
 #pragma unroll
         for (int j = 0; j < NC; ++j) {
             if (j < J.nc) {
@@ -192,43 +205,37 @@ __global__ __launch_bounds__(64) void many_kernel(const ManyArgs a) {
     }
 }
 
-// The persistent work queue (see QueueArgs).  Every loop is bounded by a
-// kernel argument: a wavefront pops at most nchunks times, and a chunk whose
-// descriptor lies outside its pattern (which the host never plans) is not
-// swept: its slot is written as NaN, so the pattern's value shows it, and it
-// still counts toward the pattern's last chunk.  No wavefront waits on
-// another.
+// The persistent work queue (see QueueArgs).  Every 16th pop it reads the
+// ctx's cancellation word and stops once the host has set it.  Every loop is
+// bounded by a kernel argument: a wavefront pops at most nchunks times, and a
+// chunk whose descriptor lies outside its pattern (which the host never
+// plans) is not swept: its slot is written as NaN, so the pattern's value
+// shows it.  No wavefront waits on another.
 template <int MODE, int NC, bool BIN, bool UNIT, bool GEN = false>
 __global__ __launch_bounds__(64) void queue_kernel(const QueueArgs q) {
-    __shared__ cplx L[kMaxExtendCols];
     const ManyArgs& a = q.m;
     const int lane = threadIdx.x & 63;
     for (int it = 0; it < a.nchunks; ++it) {
+        if (q.cancel && (it & 15) == 0) {
+            // cancellation requested by the host: stop popping
+            int c = 0;
+            if (lane == 0) c = __hip_atomic_load(q.cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            if (__builtin_amdgcn_readfirstlane(c)) break;
+        }
         unsigned ci = 0;
         if (lane == 0) ci = atomicAdd(q.counter, 1u);
         ci = (unsigned)__builtin_amdgcn_readfirstlane((int)ci);
         if (ci >= (unsigned)a.nchunks) break;
         const MChunk ch = a.chunks[ci];
-        if (ch.pat < 0 || ch.pat >= q.fin.npat) continue;
         const BJob& J = a.jobs[ch.pat];
         const bool ok = ch.count >= 1 && ch.count <= J.time_states && ch.start <= J.time_states - ch.count &&
                         (BIN || J.m_inner >= 1);
         if (ok) {
-            fwd_chunk<MODE, NC, BIN, UNIT, GEN>(a, ch, lane);
+            fwd_chunk<MODE, NC, BIN, UNIT, GEN, true>(a, ch, lane);
         } else {
             double* slot = a.partials + (size_t)ch.slot * a.slot_doubles;
             const int nd = MODE == kModeFwd ? 4 : 4 * J.nc;
             for (int e = lane; e < nd; e += 64) slot[e] = __builtin_nan("");
-        }
-        // publish the slot, then count the chunk; the wavefront that counts
-        // the pattern's last chunk adds its slots and writes its outputs
-        __threadfence();
-        unsigned t = 0;
-        if (lane == 0) t = atomicAdd(q.tickets + ch.pat, 1u);
-        t = (unsigned)__builtin_amdgcn_readfirstlane((int)t);
-        if (t + 1 == (unsigned)J.nchunks) {
-            __threadfence();
-            final_pattern(q.fin, ch.pat, lane, L);
         }
     }
 }

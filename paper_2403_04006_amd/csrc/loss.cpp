@@ -11,7 +11,7 @@ using namespace pq;
 int pq_loss_dilation(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m, const double* eta, pq_c128* Ud,
                      int64_t ldd, void* stream) {
     if (!ctx) return PQ_EINVAL;
-    ctx->clear_error();
+    if (int rc_ = ctx->begin("pq_loss_dilation")) return rc_;
     if (m < 1 || m > (1 << 15)) return ctx->fail(PQ_ERANGE, "pq_loss_dilation: m must be in 1..32768");
     if (!U || !eta || !Ud || ldu < m || ldd < 2 * (int64_t)m)
         return ctx->fail(PQ_EINVAL, "pq_loss_dilation: NULL argument, ldu < m or ldd < 2m");

@@ -47,6 +47,7 @@ struct ManyEntry {
     int npat = 0, ntab = 0;      // npat: distinct patterns (identical ones are swept once)
     bool fuse_dred = false;      // adjoint: the final kernel reduces the derivative slots
     int max_chunks = 0;          // most chunks of any pattern (1: nothing for a work queue to balance)
+    int queue_pref = -1;         // the autotuner's schedule for pq_perm_batched (1 queue, 0 static, -1 none)
     size_t mat_elems = 0, partial_doubles = 0, dpat_elems = 0;
     std::vector<ManyClass> classes;
     ChunkPolicy policy;
@@ -66,7 +67,7 @@ struct ManyEntry {
     int32_t* d_dup_pat = nullptr;
     int64_t* d_dup_out = nullptr;
     cplx* d_gsum = nullptr;          // adjoint: summed cotangent per distinct pattern
-    unsigned* d_qzero = nullptr;     // work queue: one counter per class, then one ticket per pattern
+    unsigned* d_qzero = nullptr;     // work queue: one counter per class
     cplx* d_mat = nullptr;
     StepEntry* d_tabs = nullptr;
     double* d_partials = nullptr;
@@ -427,11 +428,8 @@ int build_many(pq_ctx* ctx, int mode, int32_t m, const std::vector<PatternSpec>&
     const size_t oDp = cv.take(sizeof(cplx) * sz(dpat_elems));
     const size_t oRp = cv.take(sizeof(cplx) * sz(red_part));
     const size_t oGs = cv.take(sizeof(cplx) * sz(adj ? pats.size() : 0));
-    const size_t oQz = cv.take(sizeof(unsigned) * sz(adj ? 0 : E.classes.size() + pats.size()));
-    if (hipMalloc((void**)&E.dmem, cv.off) != hipSuccess) {
-        E.dmem = nullptr;
-        return ctx->fail(PQ_ENOMEM, "many: hipMalloc(%zu) failed", cv.off);
-    }
+    const size_t oQz = cv.take(sizeof(unsigned) * sz(adj ? 0 : E.classes.size()));
+    if (int rc = ctx->device_alloc((void**)&E.dmem, cv.off, "many")) return rc;
     E.d_jobs = (BJob*)(E.dmem + oJobs);
     E.d_chunks = (MChunk*)(E.dmem + oCh);
     E.d_idx = (int32_t*)(E.dmem + oIdx);
@@ -496,8 +494,8 @@ int queue_grid(pq_ctx* ctx, const ManyClass& C) {
 }
 
 // Launch sequence of a plan.  queue (forward plans only): every class runs as
-// a persistent work queue whose wavefronts also finish the patterns, instead
-// of one workgroup per chunk followed by the final kernel.
+// a persistent work queue instead of one workgroup per chunk; the final
+// kernel follows either way.
 int run_many(pq_ctx* ctx, ManyEntry& E, const cplx* U, int64_t ldu, int32_t m, cplx* perm, cplx* amp,
              const cplx* gperm, cplx* dU, int64_t lddu, hipStream_t st, hipEvent_t t0 = nullptr,
              hipEvent_t t1 = nullptr, bool queue = false) {
@@ -541,8 +539,7 @@ int run_many(pq_ctx* ctx, ManyEntry& E, const cplx* U, int64_t ldu, int32_t m, c
     if (queue) {
         QueuePrepArgs qp;
         qp.zero = E.d_qzero;
-        qp.nzero = nclass + E.npat;
-        qp.fin = fa;
+        qp.nzero = nclass;
         rc = ctx->check(launch_queue_prep(qp, st), "queue prep");
         if (rc) return rc;
     }
@@ -572,9 +569,8 @@ int run_many(pq_ctx* ctx, ManyEntry& E, const cplx* U, int64_t ldu, int32_t m, c
         if (queue) {
             QueueArgs q;
             q.m = a;
-            q.fin = fa;
             q.counter = E.d_qzero + ci;
-            q.tickets = E.d_qzero + nclass;
+            q.cancel = ctx->cancel_word_dev;
             rc = ctx->check(launch_queue(C.mode, C.ncmax, C.var, q, queue_grid(ctx, C), st), "queue sweep");
         } else {
             rc = ctx->check(launch_many(C.mode, C.ncmax, C.var, a, st), "many sweep");
@@ -590,7 +586,6 @@ int run_many(pq_ctx* ctx, ManyEntry& E, const cplx* U, int64_t ldu, int32_t m, c
         if (rc) return rc;
         ctx->ev_used.emplace_back(e0, e1);
     }
-    if (queue) return PQ_OK;
     rc = ctx->check(launch_many_final(fa, st), "many final");
     if (rc) return rc;
     if (E.mode == kModeAdj) {
@@ -704,21 +699,18 @@ uint64_t shape_sig(int32_t m, const std::vector<PatternSpec>& pats) {
     return h;
 }
 
-// Build one candidate plan and time its class sweeps (best of two runs).
-int time_candidate(pq_ctx* ctx, int32_t m, const std::vector<PatternSpec>& pats, const ChunkPolicy& pol,
-                   const cplx* U, int64_t ldu, cplx* perm, cplx* amp, hipStream_t st,
-                   std::unique_ptr<ManyEntry>& out, double& ms, bool queue) {
-    std::unique_ptr<ManyEntry> e(new ManyEntry());
-    int rc = build_many(ctx, kModeFwd, m, pats, *e, st, pol);
-    if (rc) return rc;
+// Time the class sweeps of a built plan under one schedule (best of two runs).
+int time_plan(pq_ctx* ctx, ManyEntry& e, int32_t m, const cplx* U, int64_t ldu, cplx* perm, cplx* amp,
+              hipStream_t st, bool queue, double& ms) {
     hipEvent_t t0 = nullptr, t1 = nullptr;
     if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess) {
         if (t0) hipEventDestroy(t0);
         return ctx->fail(PQ_EDEVICE, "tune: hipEventCreate failed");
     }
+    int rc = PQ_OK;
     ms = -1.0;
     for (int rep = 0; rep < 2 && !rc; ++rep) {
-        rc = run_many(ctx, *e, U, ldu, m, perm, amp, nullptr, nullptr, 0, st, t0, t1, queue && e->max_chunks > 1);
+        rc = run_many(ctx, e, U, ldu, m, perm, amp, nullptr, nullptr, 0, st, t0, t1, queue && e.max_chunks > 1);
         if (rc) break;
         rc = ctx->check(hipEventSynchronize(t1), "tune: synchronize");
         if (rc) break;
@@ -728,6 +720,17 @@ int time_candidate(pq_ctx* ctx, int32_t m, const std::vector<PatternSpec>& pats,
     }
     hipEventDestroy(t0);
     hipEventDestroy(t1);
+    return rc;
+}
+
+// Build one candidate plan and time it.
+int time_candidate(pq_ctx* ctx, int32_t m, const std::vector<PatternSpec>& pats, const ChunkPolicy& pol,
+                   const cplx* U, int64_t ldu, cplx* perm, cplx* amp, hipStream_t st,
+                   std::unique_ptr<ManyEntry>& out, double& ms, bool queue) {
+    std::unique_ptr<ManyEntry> e(new ManyEntry());
+    int rc = build_many(ctx, kModeFwd, m, pats, *e, st, pol);
+    if (rc) return rc;
+    rc = time_plan(ctx, *e, m, U, ldu, perm, amp, st, queue, ms);
     if (rc) return rc;
     out = std::move(e);
     return PQ_OK;
@@ -768,6 +771,7 @@ int get_entry(pq_ctx* ctx, int mode, int32_t m, std::vector<int64_t>& key,
             ctx->last_tune.candidates = 0;
             ne.reset(new ManyEntry());
             rc = build_many(ctx, mode, m, pats, *ne, st, known->policy);
+            ne->queue_pref = known->queue;
         } else {
             TuneRecord rec;
             rec.sig = sig;
@@ -785,10 +789,22 @@ int get_entry(pq_ctx* ctx, int mode, int32_t m, std::vector<int64_t>& key,
                     ne = std::move(cand);
                 }
             }
+            if (!rc && queue && ne->max_chunks > 1) {
+                // the boundary's batched call: the kept policy under the
+                // static schedule as well; the faster schedule is recorded
+                double ms_static = 0.0;
+                rc = time_plan(ctx, *ne, m, U, ldu, perm, amp, st, false, ms_static);
+                if (!rc) {
+                    rec.queue = best <= ms_static ? 1 : 0;
+                    if (!rec.queue) best = ms_static;
+                    ne->queue_pref = rec.queue;
+                }
+            }
             if (!rc) {
                 rec.best_ms = best;
                 ctx->tuned.push_back(rec);
                 ctx->last_tune = rec;
+                ctx->tune_cache_store(rec, "many");
             }
         }
     } else {
@@ -833,7 +849,7 @@ void pq_release_many_cache(pq_ctx* ctx) {
 static int perm_jobs(pq_ctx* ctx, const char* name, const pq_c128* U, int64_t ldu, int32_t m,
                      const pq_job* jobs, int32_t njobs, pq_c128* perm, pq_c128* amp, void* stream, bool queue) {
     if (!ctx) return PQ_EINVAL;
-    ctx->clear_error();
+    if (int rc_ = ctx->begin(name)) return rc_;
     if (m < 0 || njobs < 0) return ctx->fail(PQ_EINVAL, "%s: negative size", name);
     if (njobs == 0) return PQ_OK;
     if (!jobs || !perm) return ctx->fail(PQ_EINVAL, "%s: NULL jobs or perm", name);
@@ -861,8 +877,9 @@ static int perm_jobs(pq_ctx* ctx, const char* name, const pq_c128* U, int64_t ld
     if (rc) return rc;
     if (queue) {
         // a plan whose every pattern is one chunk has nothing for a queue to
-        // balance: one workgroup per chunk is already that schedule
-        const bool q = E->max_chunks > 1;
+        // balance: one workgroup per chunk is already that schedule; a tuned
+        // plan follows the schedule the autotuner measured faster
+        const bool q = E->max_chunks > 1 && E->queue_pref != 0;
         if (!ctx->profiling)
             return run_many_graph(ctx, *E, (const cplx*)U, ldu, m, (cplx*)perm, (cplx*)amp, st, q);
         return run_many(ctx, *E, (const cplx*)U, ldu, m, (cplx*)perm, (cplx*)amp, nullptr, nullptr, 0, st,
@@ -890,7 +907,7 @@ int pq_perm_grad(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m,
                  const pq_c128* gperm, pq_c128* perm,
                  pq_c128* dU, int64_t lddu, void* stream) {
     if (!ctx) return PQ_EINVAL;
-    ctx->clear_error();
+    if (int rc_ = ctx->begin("pq_perm_grad")) return rc_;
     if (m < 0 || batch < 0) return ctx->fail(PQ_EINVAL, "pq_perm_grad: negative size");
     if (!dU || lddu < m) return ctx->fail(PQ_EINVAL, "pq_perm_grad: NULL dU or lddu < m");
     if (batch > 0 && (!S || !T || !gperm)) return ctx->fail(PQ_EINVAL, "pq_perm_grad: NULL pattern or gperm");

@@ -83,22 +83,19 @@ struct ManyFinalArgs {
 
 // Persistent work queue over one class's chunks (forward and extend-row
 // classes): a grid of resident wavefronts, each popping chunk indices from
-// `counter` until they run out; after a chunk's slot is written the wavefront
-// counts it in its pattern's ticket, and the one that counts the pattern's
-// last chunk runs the final step for it (final_pattern), so no other kernel
-// is needed.  counter and tickets start at zero (queue_prep_kernel).
+// `counter` until they run out and writing each chunk's slot; the final
+// kernel then adds every pattern's slots in slot order, as after the static
+// schedule.  counter starts at zero (queue_prep_kernel).
 struct QueueArgs {
     ManyArgs m;
-    ManyFinalArgs fin;
     unsigned* counter;         // this class's next-chunk counter
-    unsigned* tickets;         // [npat]: chunks finished per pattern
+    const int32_t* cancel;     // host-mapped word: nonzero stops the queue (pq_cancel); may be null
 };
 
-// Reset of the queue counters and constant outputs of trivial patterns.
+// Reset of the queue counters before the class queues run.
 struct QueuePrepArgs {
-    unsigned* zero;            // counters, then tickets
+    unsigned* zero;
     int32_t nzero;
-    ManyFinalArgs fin;         // trivial patterns (pat_class < 0) are written here
 };
 
 // Reduction of the reverse sweeps' derivative slots in two fixed-order

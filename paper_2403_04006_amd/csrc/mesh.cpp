@@ -22,7 +22,7 @@ static int check_mesh(pq_ctx* ctx, int32_t m, int32_t ncell, const int32_t* mode
 int pq_mesh_unitary(pq_ctx* ctx, int32_t m, int32_t ncell, const int32_t* modes, const double* angles,
                     pq_c128* U, int64_t ldu, void* stream) {
     if (!ctx) return PQ_EINVAL;
-    ctx->clear_error();
+    if (int rc_ = ctx->begin("pq_mesh_unitary")) return rc_;
     int rc = check_mesh(ctx, m, ncell, modes, angles);
     if (rc) return rc;
     if (!U || ldu < m) return ctx->fail(PQ_EINVAL, "pq_mesh_unitary: NULL U or ldu < m");
@@ -41,7 +41,7 @@ int pq_mesh_unitary(pq_ctx* ctx, int32_t m, int32_t ncell, const int32_t* modes,
 int pq_mesh_unitary_vjp(pq_ctx* ctx, int32_t m, int32_t ncell, const int32_t* modes, const double* angles,
                         const pq_c128* gU, int64_t ldg, double* gangles, void* stream) {
     if (!ctx) return PQ_EINVAL;
-    ctx->clear_error();
+    if (int rc_ = ctx->begin("pq_mesh_unitary_vjp")) return rc_;
     int rc = check_mesh(ctx, m, ncell, modes, angles);
     if (rc) return rc;
     if (!gU || ldg < m || (ncell > 0 && !gangles)) return ctx->fail(PQ_EINVAL, "pq_mesh_unitary_vjp: NULL argument or ldg < m");
@@ -61,7 +61,7 @@ int pq_mesh_unitary_vjp(pq_ctx* ctx, int32_t m, int32_t ncell, const int32_t* mo
 int pq_neg_log_prob(pq_ctx* ctx, int32_t batch, const pq_c128* perm, const double* log_norm, double* loss,
                     void* stream) {
     if (!ctx) return PQ_EINVAL;
-    ctx->clear_error();
+    if (int rc_ = ctx->begin("pq_neg_log_prob")) return rc_;
     if (batch < 1 || !perm || !loss) return ctx->fail(PQ_EINVAL, "pq_neg_log_prob: empty batch or NULL pointer");
     DeviceGuard guard(ctx->device);
     NllArgs a{(const cplx*)perm, log_norm, loss, batch};
@@ -71,7 +71,7 @@ int pq_neg_log_prob(pq_ctx* ctx, int32_t batch, const pq_c128* perm, const doubl
 int pq_neg_log_prob_vjp(pq_ctx* ctx, int32_t batch, const pq_c128* perm, const double* gloss, pq_c128* gperm,
                         void* stream) {
     if (!ctx) return PQ_EINVAL;
-    ctx->clear_error();
+    if (int rc_ = ctx->begin("pq_neg_log_prob_vjp")) return rc_;
     if (batch < 1 || !perm || !gperm) return ctx->fail(PQ_EINVAL, "pq_neg_log_prob_vjp: empty batch or NULL pointer");
     DeviceGuard guard(ctx->device);
     NllVjpArgs a{(const cplx*)perm, gloss, (cplx*)gperm, batch};

@@ -53,7 +53,7 @@ int pq_perm_noalloc(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m,
                     const int32_t* S, const int32_t* T,
                     pq_c128* perm, pq_c128* amp, void* stream) {
     if (!ctx) return PQ_EINVAL;
-    ctx->clear_error();
+    if (int rc_ = ctx->begin("pq_perm_noalloc")) return rc_;
     if (m < 0 || !S || !T) return ctx->fail(PQ_EINVAL, "pq_perm_noalloc: m < 0 or NULL occupation vector");
     if (m > 0 && (!U || ldu < m)) return ctx->fail(PQ_EINVAL, "pq_perm_noalloc: NULL U or ldu < m");
     Plan p;

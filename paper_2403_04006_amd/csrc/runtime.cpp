@@ -19,8 +19,70 @@ int pq_ctx::fail(int status, const char* fmt, ...) {
 }
 
 int pq_ctx::check(hipError_t e, const char* what) {
+    if (fault == PQ_FAULT_LAUNCH) return fail(PQ_EDEVICE, "%s: injected launch failure", what);
     if (e == hipSuccess) return PQ_OK;
     return fail(PQ_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+int pq_ctx::device_alloc(void** p, size_t bytes, const char* what) {
+    *p = nullptr;
+    if (fault == PQ_FAULT_ALLOC) return fail(PQ_ENOMEM, "%s: injected allocation failure (%zu bytes)", what, bytes);
+    if (hipMalloc(p, bytes) != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(PQ_ENOMEM, "%s: hipMalloc(%zu) failed", what, bytes);
+    }
+    return PQ_OK;
+}
+
+int pq_ctx::begin(const char* name) {
+    clear_error();
+    if (cancelled()) return fail(PQ_ECANCELLED, "%s: cancellation requested on this ctx (pq_cancel)", name);
+    return PQ_OK;
+}
+
+// One line per decision: {"device": "<arch>:<CUs>", "kind": "<kind>",
+// "sig": <decimal>, "policy": [a, b, c], "best_ms": x, "default_ms": y}.
+void pq_ctx::tune_cache_load() {
+    if (tune_cache.empty()) return;
+    FILE* f = fopen(tune_cache.c_str(), "r");
+    if (!f) return;
+    char line[1024];
+    while (fgets(line, sizeof(line), f)) {
+        char dev[256] = {0}, kind[64] = {0};
+        unsigned long long sig = 0;
+        int a = 0, b = 0, c = 0, qd = -1;
+        double best = 0.0, def = 0.0;
+        const int got = sscanf(line, " {\"device\": \"%255[^\"]\", \"kind\": \"%63[^\"]\", \"sig\": %llu, "
+                               "\"policy\": [%d, %d, %d], \"best_ms\": %lf, \"default_ms\": %lf, \"queue\": %d",
+                               dev, kind, &sig, &a, &b, &c, &best, &def, &qd);
+        if (got < 8) continue;
+        if (device_key != dev) continue;
+        pq::TuneRecord r;
+        r.sig = sig;
+        r.policy.waves_per_cu = a;
+        r.policy.chunks_per_wave = b;
+        r.policy.min_chunk = c;
+        r.best_ms = best;
+        r.default_ms = def;
+        r.candidates = 0;
+        r.queue = got == 9 ? qd : -1;
+        bool dup = false;
+        for (const pq::TuneRecord& t : tuned) dup = dup || t.sig == r.sig;
+        if (!dup) tuned.push_back(r);
+    }
+    fclose(f);
+}
+
+void pq_ctx::tune_cache_store(const pq::TuneRecord& rec, const char* kind) {
+    if (tune_cache.empty()) return;
+    FILE* f = fopen(tune_cache.c_str(), "a");
+    if (!f) return;
+    fprintf(f, "{\"device\": \"%s\", \"kind\": \"%s\", \"sig\": %llu, \"policy\": [%d, %d, %d], "
+            "\"best_ms\": %.6f, \"default_ms\": %.6f, \"queue\": %d}\n", device_key.c_str(), kind,
+            (unsigned long long)rec.sig, rec.policy.waves_per_cu, rec.policy.chunks_per_wave, rec.policy.min_chunk,
+            rec.best_ms, rec.default_ms, rec.queue);
+    fclose(f);
 }
 
 void* pq_ctx::workspace(size_t bytes) {
@@ -31,11 +93,7 @@ void* pq_ctx::workspace(size_t bytes) {
         ws_bytes = 0;
     }
     size_t want = bytes < ((size_t)1 << 20) ? ((size_t)1 << 20) : bytes;
-    if (hipMalloc(&ws, want) != hipSuccess) {
-        ws = nullptr;
-        fail(PQ_ENOMEM, "workspace: hipMalloc(%zu) failed", want);
-        return nullptr;
-    }
+    if (device_alloc(&ws, want, "workspace")) return nullptr;
     ws_bytes = want;
     return ws;
 }
@@ -108,6 +166,9 @@ int pq_ctx::status_reset() {
 }
 
 void pq_ctx::release_all() {
+    if (cancel_word) hipHostFree(cancel_word);
+    cancel_word = nullptr;
+    cancel_word_dev = nullptr;
     if (status_word) hipHostFree(status_word);
     status_word = nullptr;
     status_word_dev = nullptr;

@@ -29,6 +29,9 @@ struct TuneRecord {
     ChunkPolicy policy;
     double best_ms = 0.0, default_ms = 0.0;
     int32_t candidates = 0;
+    // pq_perm_batched: 1 when the work queue beat the static schedule under
+    // the kept policy, 0 when it did not, -1 when not timed
+    int32_t queue = -1;
 };
 }  // namespace pq
 
@@ -61,6 +64,29 @@ struct pq_ctx {
     pq::TuneRecord last_tune;
     // resident workgroups per CU of the work-queue kernels, by class
     std::map<int, int> queue_occ;
+
+    // fault injection (pq_fault_inject, PQ_FAULT_INJECT): while set, every
+    // device allocation (PQ_FAULT_ALLOC) or every launch check
+    // (PQ_FAULT_LAUNCH) of this ctx fails as if the runtime had refused it
+    int fault = PQ_FAULT_NONE;
+    int device_alloc(void** p, size_t bytes, const char* what);
+
+    // cancellation (pq_cancel): a pinned, device-mapped word that the work
+    // queue polls between chunks; while it is set, entry points refuse new
+    // work with PQ_ECANCELLED
+    int32_t* cancel_word = nullptr;
+    int32_t* cancel_word_dev = nullptr;
+    bool cancelled() const { return cancel_word && __atomic_load_n(cancel_word, __ATOMIC_SEQ_CST) != 0; }
+    // start of an entry point that enqueues GPU work: clears the error
+    // detail; PQ_ECANCELLED while cancellation is requested
+    int begin(const char* name);
+
+    // autotune decisions persisted across processes (PQ_AUTOTUNE_CACHE): the
+    // file, and this device's key in it (architecture and CU count)
+    std::string tune_cache;
+    std::string device_key;
+    void tune_cache_load();
+    void tune_cache_store(const pq::TuneRecord& rec, const char* kind);
 
     // pinned, device-mapped status word that kernels validating device-side
     // inputs (the sampler's input modes) mark; read after the stream finishes

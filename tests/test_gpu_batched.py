@@ -1,11 +1,10 @@
 """Parity of the batched boundary call (pq_perm_batched) against the oracle.
 
 pq_perm_batched runs multi-chunk plans as a persistent work queue (resident
-wavefronts pop chunks from an atomic counter; the one that finishes a
-pattern's last chunk writes its outputs) replayed from a captured HIP graph,
-and plans whose every job is one chunk on the static schedule.  The queue
-adds each pattern's slots in slot order with the static schedule's final
-step, so both schedules give the same bits."""
+wavefronts pop chunks from an atomic counter, each writing its chunk's slot)
+replayed from a captured HIP graph, and plans whose every job is one chunk on
+the static schedule.  Both schedules add each pattern's slots in slot order
+in the same final kernel, so they give the same bits."""
 import numpy as np
 import pytest
 
