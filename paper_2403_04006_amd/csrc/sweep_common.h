@@ -49,17 +49,25 @@ __device__ __forceinline__ void keep_branch(cplx& v) {
 //   prod_j c_j^{kap_j} = prod_g S_g^{d_g},
 // so one running suffix product and one multiply per unit of rise replace the
 // per-column repeated multiplies.  The rises come as uniform bit masks.
+// The masks pass through an empty register-only asm once per product: the
+// compiler then cannot hoist the per-column tests out of the sweep loop as
+// 64-bit lane masks (three per column, which spill to VGPR lanes and are read
+// back with two v_readlane each); each test stays one scalar bit test.
 template <int NC>
 __device__ __forceinline__ cplx product_grouped(const cplx (&c)[NC], const PowSteps& ps) {
+    uint64_t m0 = ps.step[0], m1 = ps.step[1], m2 = ps.step[2];
+#if defined(__HIP_DEVICE_COMPILE__)
+    asm("" : "+s"(m0), "+s"(m1), "+s"(m2));
+#endif
     cplx S = c[NC - 1];
     cplx R{1.0, 0.0};
 #pragma unroll
     for (int j = NC - 1; j >= 1; --j) {
-        if ((ps.step[0] >> j) & 1ull) {
+        if ((m0 >> j) & 1ull) {
             R = cmul(R, S);
-            if ((ps.step[1] >> j) & 1ull) {
+            if ((m1 >> j) & 1ull) {
                 R = cmul(R, S);
-                if ((ps.step[2] >> j) & 1ull) R = cmul(R, S);
+                if ((m2 >> j) & 1ull) R = cmul(R, S);
             }
             keep_branch(R);
         }
