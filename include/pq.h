@@ -358,6 +358,25 @@ int pq_loss_dilation(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m, cons
                      int64_t ldd, void* stream);
 
 /*
+ * pq_loss_dilation_vw -- a general lossy interferometer in the singular value
+ * form of the Boson Sampling section: A = V diag(mu) W with V, W unitary and
+ * mu_i = sqrt(eta_i), eta_i in [0, 1] the transmission of the i-th singular
+ * mode (A A^dagger <= I).  It is W, then a pure-loss beamsplitter on every
+ * mode (as in pq_loss_dilation), then V on the system modes:
+ *     Ud = (V (+) I) [[D, -E], [E, D]] (W (+) I) = [[V D W, -V E], [E W, D]],
+ * a 2m x 2m unitary whose top-left block is A.  pq_sample_chain and
+ * pq_perm_all_outputs on Ud (inputs in modes 0..m-1; outputs m..2m-1 are the
+ * lost photons) sample and evaluate A's lossy output distribution.
+ *   V, W   device, m x m, leading dimensions ldv, ldw >= m (unitarity is the
+ *          caller's; the dilation is unitary exactly when V and W are).
+ *   eta    host double[m] in [0, 1] (PQ_EINVAL otherwise).
+ *   Ud     device, 2m x 2m, leading dimension ldd >= 2m, written.
+ * With V = I it equals pq_loss_dilation(W, eta).
+ */
+int pq_loss_dilation_vw(pq_ctx* ctx, const pq_c128* V, int64_t ldv, const double* eta, const pq_c128* W,
+                        int64_t ldw, int32_t m, pq_c128* Ud, int64_t ldd, void* stream);
+
+/*
  * pq_lhaf -- loop hafnian with repeated modes (Appendix, Eq. loop_hafnian;
  * with gamma NULL the hafnian, Eq. haf_def), the matrix function of the
  * Gaussian Boson Sampling detection probability: lhaf(filldiag(A_r, gamma_r)),

@@ -28,6 +28,8 @@ What it computes (each function cites the passage it follows):
                              environment modes (Boson Sampling section), and
                              the detection probability of T marginalised over
                              the environment.
+* ``loss_dilation_vw(V, eta, W)`` -- the general lossy interferometer
+                             A = V diag(sqrt(eta)) W of the same section.
 * ``beamsplitter(theta, phi)``, ``mesh_unitary(angles)`` -- the beamsplitter
                              matrix of the "Beamsplitter gate" section and a
                              rectangular mesh of such cells.
@@ -368,16 +370,29 @@ def loss_dilation(U, eta) -> np.ndarray:
     return layer @ big
 
 
-def lossy_probability(U, eta, S, T) -> float:
+def loss_dilation_vw(V, eta, W) -> np.ndarray:
+    """2m-mode unitary of the general lossy interferometer A = V diag(sqrt(eta)) W
+    (the singular value form of the Boson Sampling section): W on the system
+    modes, then the pure-loss beamsplitter layer of loss_dilation, then V on
+    the system modes, multiplied out as matrices in that order."""
+    V = np.asarray(V, dtype=np.complex128)
+    W = np.asarray(W, dtype=np.complex128)
+    m = V.shape[0]
+    left = np.eye(2 * m, dtype=np.complex128)
+    left[:m, :m] = V
+    return left @ loss_dilation(W, eta)
+
+
+def lossy_probability(U, eta, S, T, V=None) -> float:
     """Probability of detecting T (sum T <= sum S) on the system modes after
-    U and the losses: the sum over environment patterns E of the ideal
-    probability of (T, E) on the dilation, inputs in the system modes."""
+    U, the losses and (if given) V: the sum over environment patterns E of the
+    ideal probability of (T, E) on the dilation, inputs in the system modes."""
     m = len(S)
     n = int(np.sum(S))
     k = n - int(np.sum(T))
     if k < 0:
         return 0.0
-    Ud = loss_dilation(U, eta)
+    Ud = loss_dilation(U, eta) if V is None else loss_dilation_vw(V, eta, U)
     S2 = np.concatenate([np.asarray(S, np.int32), np.zeros(m, np.int32)])
     total = 0.0
     for E in _compositions(m, k):

@@ -262,6 +262,21 @@ class Engine:
         (PQ_FAULT_LAUNCH) of this ctx fail; PQ_FAULT_NONE restores it."""
         _check(self._lib.pq_fault_inject(self._ctx, int(what)), self._ctx)
 
+    def loss_dilation_vw(self, V: torch.Tensor, eta: Sequence[float], W: torch.Tensor) -> torch.Tensor:
+        """2m x 2m unitary dilation of the lossy interferometer
+        A = V diag(sqrt(eta)) W (pq_loss_dilation_vw)."""
+        V, ldv = _as_matrix(V)
+        W, ldw = _as_matrix(W)
+        m = V.shape[0]
+        if W.shape[0] != m or len(eta) != m:
+            raise ValueError("V, W and eta must have the same mode count")
+        Ud = torch.empty((2 * m, 2 * m), dtype=torch.complex128, device=V.device)
+        arr = (ctypes.c_double * m)(*[float(x) for x in eta])
+        st = self._lib.pq_loss_dilation_vw(self._ctx, V.data_ptr(), ldv, arr, W.data_ptr(), ldw, m, Ud.data_ptr(),
+                                           2 * m, _stream_handle(V.device))
+        _check(st, self._ctx)
+        return Ud
+
     def autotune(self, on: bool = True):
         """Chunk-size autotuning of perm_many (pq_autotune_enable)."""
         _check(self._lib.pq_autotune_enable(self._ctx, 1 if on else 0), self._ctx)

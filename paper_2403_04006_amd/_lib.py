@@ -88,6 +88,8 @@ _SIGNATURES = {
     "pq_fock_count": ([ctypes.c_int32, ctypes.c_int32], ctypes.c_int64),
     "pq_loss_dilation": ([_VP, _VP, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), _VP,
                           ctypes.c_int64, _VP], ctypes.c_int),
+    "pq_loss_dilation_vw": ([_VP, _VP, ctypes.c_int64, ctypes.POINTER(ctypes.c_double), _VP, ctypes.c_int64,
+                             ctypes.c_int32, _VP, ctypes.c_int64, _VP], ctypes.c_int),
     "pq_sample_chain": ([_VP, _VP, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _VP, _VP, _VP,
                          _VP], ctypes.c_int),
     "pq_fock_unrank": ([ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, _I32P], ctypes.c_int),

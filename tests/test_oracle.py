@@ -513,6 +513,54 @@ def test_no_loss_reduces_to_ideal_and_dilation_is_unitary():
     assert np.max(np.abs(Ud @ Ud.conj().T - np.eye(6))) < 1e-14
 
 
+def test_general_lossy_form_mean_occupation():
+    # A = V diag(sqrt(eta)) W: mean detected occupation <n_j> = sum_i |A_ji|^2 s_i
+    # for Fock inputs through any passive linear network (first moment only
+    # depends on |A|^2), here with the two unitaries on either side of the loss
+    m = 4
+    V, W = workloads.haar(m, 34), workloads.haar(m, 35)
+    eta = [0.9, 0.35, 0.6, 1.0]
+    S = np.array([1, 2, 0, 1], np.int32)
+    A = np.zeros((m, m), complex)
+    for j in range(m):
+        for i in range(m):
+            A[j, i] = sum(V[j, k] * math.sqrt(eta[k]) * W[k, i] for k in range(m))
+    mean = np.zeros(m)
+    for T in _detected(m, 4):
+        mean += T * oracle.lossy_probability(W, eta, S, T, V=V)
+    assert np.max(np.abs(mean - (np.abs(A) ** 2) @ S)) < 1e-12
+
+
+def test_uniform_loss_commutes_with_the_interferometer():
+    # equal transmissivity on every mode commutes with any unitary: loss
+    # between W and V gives the same detection statistics as loss after V W
+    m, eta = 3, 0.55
+    V, W = workloads.haar(m, 36), workloads.haar(m, 37)
+    S = np.array([2, 0, 1], np.int32)
+    for T in _detected(m, 3):
+        a = oracle.lossy_probability(W, [eta] * m, S, T, V=V)
+        b = oracle.lossy_probability(V @ W, [eta] * m, S, T)
+        assert abs(a - b) < 1e-14
+
+
+def test_general_dilation_blocks_and_special_cases():
+    m = 3
+    V, W = workloads.haar(m, 38), workloads.haar(m, 39)
+    eta = [0.2, 0.7, 1.0]
+    Ud = oracle.loss_dilation_vw(V, eta, W)
+    assert np.max(np.abs(Ud @ Ud.conj().T - np.eye(2 * m))) < 1e-14
+    # the system block is the lossy transfer matrix, element by element
+    for j in range(m):
+        for i in range(m):
+            a = sum(V[j, k] * math.sqrt(eta[k]) * W[k, i] for k in range(m))
+            assert abs(Ud[j, i] - a) < 1e-15
+    # no unitary after the loss: the dilation of loss after W
+    assert np.max(np.abs(oracle.loss_dilation_vw(np.eye(m), eta, W) - oracle.loss_dilation(W, eta))) < 1e-15
+    # total loss: nothing reaches the detectors
+    S = np.array([1, 1, 0], np.int32)
+    assert abs(oracle.lossy_probability(W, [0.0] * m, S, np.zeros(m, np.int32), V=V) - 1.0) < 1e-14
+
+
 # -------------------------------------------------------------- loop hafnian
 def involutions(n):
     # number of single-pair matchings of n vertices: T(n) = T(n-1) + (n-1) T(n-2)
