@@ -256,6 +256,23 @@ int pq_perm_many(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m,
  * Off (0, the default): direct launches.  NULL ctx: PQ_EINVAL.
  */
 int pq_graph_enable(pq_ctx* ctx, int on);
+
+/*
+ * pq_walk_variant -- the form of pq_perm_grad's reverse sweep for wide
+ * collision-free patterns (16 to 32 photons, every mode at most once; the
+ * differentiation of the permanent in the Goals and in the differentiable
+ * Fock simulations of the Benchmarks).  register_digits (1..3): how many of
+ * the lowest time digits keep their summation-by-parts accumulators in
+ * registers (more registers per wavefront, fewer reductions through LDS and
+ * device atomics); swizzle (0 or 1): the exchanges between the four lanes of
+ * a term go through ds_swizzle instead of DPP moves.  Results agree to
+ * rounding between variants (the summation order of the derivative rows
+ * differs).  Applies to plans built afterwards (the variant is part of the
+ * plan key).  Default 3 register digits, DPP (the fastest measured at 20 and
+ * 30 photons); PQ_WALK=<digits>,<swizzle> in the environment sets it at
+ * pq_create.  Out of range: PQ_EINVAL.
+ */
+int pq_walk_variant(pq_ctx* ctx, int register_digits, int swizzle);
 int pq_autotune_enable(pq_ctx* ctx, int on);
 int pq_autotune_last(pq_ctx* ctx, int32_t policy[3], double* best_ms, double* default_ms,
                      int32_t* candidates);

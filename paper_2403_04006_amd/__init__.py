@@ -286,6 +286,11 @@ class Engine:
         (pq_graph_enable)."""
         _check(self._lib.pq_graph_enable(self._ctx, 1 if on else 0), self._ctx)
 
+    def walk_variant(self, register_digits: int, swizzle: bool = False):
+        """Form of the reverse sweep for wide collision-free patterns
+        (pq_walk_variant)."""
+        _check(self._lib.pq_walk_variant(self._ctx, int(register_digits), int(swizzle)), self._ctx)
+
     def autotune_last(self) -> dict:
         """The last autotuning decision (pq_autotune_last)."""
         pol = (ctypes.c_int32 * 3)()

@@ -62,11 +62,25 @@ int pq_create(pq_ctx** out, int hip_device) {
         else if (!strcmp(e, "launch")) c->fault = PQ_FAULT_LAUNCH;
     }
     if (const char* e = getenv("PQ_AUTOTUNE")) c->autotune = e[0] == '1';
+    if (const char* e = getenv("PQ_WALK")) {
+        int kd = 0, sw = 0;
+        if (sscanf(e, "%d,%d", &kd, &sw) == 2 && kd >= 1 && kd <= 3 && (sw == 0 || sw == 1))
+            c->walk_variant = 2 * (kd - 1) + sw;
+    }
     if (const char* e = getenv("PQ_AUTOTUNE_CACHE")) {
         c->tune_cache = e;
         c->tune_cache_load();
     }
     *out = c;
+    return PQ_OK;
+}
+
+int pq_walk_variant(pq_ctx* ctx, int register_digits, int swizzle) {
+    if (!ctx) return PQ_EINVAL;
+    ctx->clear_error();
+    if (register_digits < 1 || register_digits > 3 || (swizzle != 0 && swizzle != 1))
+        return ctx->fail(PQ_EINVAL, "pq_walk_variant: register_digits in 1..3, swizzle 0 or 1");
+    ctx->walk_variant = 2 * (register_digits - 1) + swizzle;
     return PQ_OK;
 }
 

@@ -237,13 +237,25 @@ hipError_t launch_many(int mode, int ncmax, int var, const ManyArgs& a, hipStrea
     if (mode == 2 && k < (int)(sizeof(g_m_adj) / sizeof(g_m_adj[0]))) return g_m_adj[k](var, a, s);
     if (mode == kModeAdjWalk) {
         switch (ncmax) {
-#define PQ_WCASE(NC) case NC: return launch_adjw_##NC(a, s);
+#define PQ_WCASE(NC) case NC: return launch_adjw_##NC(var, a, s);
             PQ_WCLASS(PQ_WCASE)
 #undef PQ_WCASE
             default: break;
         }
     }
     return hipErrorInvalidValue;
+}
+
+int occupancy_walk(int ncmax, int variant) {
+    int blocks = 0;
+    hipError_t e = hipErrorInvalidValue;
+    switch (ncmax) {
+#define PQ_WOCC(NC) case NC: e = occupancy_adjw_##NC(variant, &blocks); break;
+        PQ_WCLASS(PQ_WOCC)
+#undef PQ_WOCC
+        default: break;
+    }
+    return e == hipSuccess ? blocks : 0;
 }
 
 }  // namespace pq

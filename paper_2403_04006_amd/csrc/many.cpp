@@ -26,13 +26,17 @@ namespace pq {
 
 namespace {
 
-constexpr uint64_t kWalkMinChunk = 256;
+// shortest walk of the reverse sweep (a multiple of its 8-state blocks): a
+// walk's set-up and closing reductions cost a few steps
+constexpr uint64_t kWalkMinChunk = 32;
 // chunk policies the autotuner times (the first is the default)
 constexpr ChunkPolicy kTuneCandidates[] = {
     {16, 4, 64}, {4, 2, 64}, {8, 1, 64}, {8, 2, 64}, {8, 4, 64}, {16, 2, 64},
     {16, 8, 64}, {32, 4, 64}, {32, 8, 64}, {8, 2, 256}, {16, 4, 256},
 };
 constexpr int kMaxManyEntries = 4;
+struct ManyClass;
+int walk_occupancy(pq_ctx* ctx, const ManyClass& C);
 
 struct ManyClass {
     int mode = 0, ncmax = 0, var = 0;
@@ -191,7 +195,10 @@ int build_many(pq_ctx* ctx, int mode, int32_t m, const std::vector<PatternSpec>&
         if (adj && p.binary && ncmax >= kWalkMinCols && ncmax <= kWalkMaxCols) {
             Plan pw;
             plan_sparse(ps.rows, ps.cols, !ext, pw, ext, kWalkLaneStates);
-            if (!pw.status && !pw.trivial && pw.n_lane <= 4 && pw.n_time <= ncmax - 5) {
+            // the walk kernel needs four lane digits (16 terms per
+            // wavefront) and at least three time digits (whole 8-state blocks)
+            if (!pw.status && !pw.trivial && pw.n_lane == 4 && pw.lane_states == kWalkTerms && pw.n_time >= 3 &&
+                pw.n_time <= ncmax - 5) {
                 p = pw;
                 walk = true;
             }
@@ -261,7 +268,10 @@ int build_many(pq_ctx* ctx, int mode, int32_t m, const std::vector<PatternSpec>&
         const int kmode = adj ? (walk ? kModeAdjWalk : kModeAdj) : (ext ? kModeExt : kModeFwd);
         // variant: 2 * binary digits + unit powers, + 4 for powers whose steps
         // the grouped product does not cover (forward jobs only)
-        const int var = (bin ? 2 : 0) + (unit ? 1 : 0) + (!unit && kmode == kModeFwd && b.pw.general ? 4 : 0);
+        // walk classes carry the ctx's walk variant instead
+        const int var = kmode == kModeAdjWalk
+                            ? ctx->walk_variant
+                            : (bin ? 2 : 0) + (unit ? 1 : 0) + (!unit && kmode == kModeFwd && b.pw.general ? 4 : 0);
         by_class[std::make_tuple(kmode, ncmax, var)].push_back((int)k);
     }
     E.ntab = (int)sigs.size();
@@ -288,10 +298,12 @@ int build_many(pq_ctx* ctx, int mode, int32_t m, const std::vector<PatternSpec>&
             chunk = (total + target - 1) / target;
             if (chunk < (uint64_t)pol.min_chunk) chunk = (uint64_t)pol.min_chunk;
         } else if (C.mode == kModeAdjWalk) {
-            // two rounds of two resident wavefronts per SIMD
-            const uint64_t waves = (uint64_t)ctx->num_cu * 4 * 2 * 2;
+            // one round of the resident wavefronts (every walk costs the
+            // same), in whole 8-state blocks
+            const uint64_t waves = (uint64_t)ctx->num_cu * (uint64_t)kWalkWaves * (uint64_t)walk_occupancy(ctx, C);
             chunk = (total + waves - 1) / waves;
             if (chunk < kWalkMinChunk) chunk = kWalkMinChunk;
+            chunk = (chunk + 7) / 8 * 8;
         }
         std::vector<MChunk> cc;
         int slot = 0;
@@ -476,6 +488,17 @@ int build_many(pq_ctx* ctx, int mode, int32_t m, const std::vector<PatternSpec>&
     put(oDup, dup_pat.data(), sizeof(int32_t) * dup_pat.size());
     put(oDut, dup_out.data(), sizeof(int64_t) * dup_out.size());
     return ctx->upload(E.dmem, stage, upload_bytes, st);
+}
+
+// Resident walk workgroups per CU of a walk class (at least 1), cached on
+// the ctx with the queue occupancies (distinct mode field).
+int walk_occupancy(pq_ctx* ctx, const ManyClass& C) {
+    const int key = (C.mode << 16) | (C.ncmax << 4) | C.var;
+    auto it = ctx->queue_occ.find(key);
+    if (it != ctx->queue_occ.end()) return it->second;
+    const int occ = std::max(1, occupancy_walk(C.ncmax, C.var));
+    ctx->queue_occ[key] = occ;
+    return occ;
 }
 
 // Queue occupancy per (mode, padded columns, variant), cached on the ctx.
@@ -912,7 +935,7 @@ int pq_perm_grad(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m,
     if (!dU || lddu < m) return ctx->fail(PQ_EINVAL, "pq_perm_grad: NULL dU or lddu < m");
     if (batch > 0 && (!S || !T || !gperm)) return ctx->fail(PQ_EINVAL, "pq_perm_grad: NULL pattern or gperm");
     if (m > 0 && (!U || ldu < m)) return ctx->fail(PQ_EINVAL, "pq_perm_grad: NULL U or ldu < m");
-    std::vector<int64_t> key = {1, m, batch};
+    std::vector<int64_t> key = {1, m, batch, ctx->walk_variant};
     key.reserve(3 + 2 * (size_t)batch * m);
     std::vector<PatternSpec> pats(batch);
     for (int p = 0; p < batch; ++p) {

@@ -19,7 +19,9 @@ PQ_MCLASS_FWD(PQ_MDECL)
 PQ_MCLASS_EXT(PQ_MDECL)
 PQ_MCLASS_ADJ(PQ_MDECL)
 #undef PQ_MDECL
-#define PQ_WDECL(NC) hipError_t launch_adjw_##NC(const ManyArgs& a, hipStream_t s);
+#define PQ_WDECL(NC)                                                                 \
+    hipError_t launch_adjw_##NC(int variant, const ManyArgs& a, hipStream_t s); \
+    hipError_t occupancy_adjw_##NC(int variant, int* blocks);
 PQ_WCLASS(PQ_WDECL)
 #undef PQ_WDECL
 
@@ -31,7 +33,11 @@ PQ_MCLASS_FWD(PQ_QDECL)
 PQ_MCLASS_EXT(PQ_QDECL)
 #undef PQ_QDECL
 
+// var: the class variant (2 * binary + unit powers, + 4 general powers); for
+// walk classes (kModeAdjWalk) the walk variant 2 (KA - 1) + SWZ
 hipError_t launch_many(int mode, int ncmax, int var, const ManyArgs& a, hipStream_t s);
+// resident workgroups (of kWalkWaves wavefronts) per CU of a walk class (0 on failure)
+int occupancy_walk(int ncmax, int variant);
 // the work queue of one class on `grid` workgroups of one wavefront
 hipError_t launch_queue(int mode, int ncmax, int var, const QueueArgs& q, int grid, hipStream_t s);
 // resident workgroups per CU of that class's queue kernel (0 on failure)

@@ -32,6 +32,9 @@ constexpr int kMaxLaneDigits = 6;  // lane digits: product of radices <= 64
 constexpr int kMaxInner = 4096;    // entries of the per-step table
 constexpr int kBlock = 256;        // threads per workgroup (4 wavefronts)
 constexpr int kWavesPerBlock = kBlock / 64;
+// reverse-sweep walk variant used unless pq_walk_variant / PQ_WALK say
+// otherwise: 2 (register flip digits - 1) + (quad exchanges via ds_swizzle)
+constexpr int kWalkDefaultVariant = 4;   // 3 register digits, DPP
 
 struct cplx { double re, im; };
 

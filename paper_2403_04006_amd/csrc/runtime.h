@@ -62,8 +62,11 @@ struct pq_ctx {
     bool graphs = false;
     std::vector<pq::TuneRecord> tuned;
     pq::TuneRecord last_tune;
-    // resident workgroups per CU of the work-queue kernels, by class
+    // resident workgroups per CU of the work-queue and walk kernels, by class
     std::map<int, int> queue_occ;
+    // reverse-sweep walk variant (pq_walk_variant, PQ_WALK): 2 (register
+    // flip digits - 1) + (quad exchanges through ds_swizzle)
+    int walk_variant = pq::kWalkDefaultVariant;
 
     // fault injection (pq_fault_inject, PQ_FAULT_INJECT): while set, every
     // device allocation (PQ_FAULT_ALLOC) or every launch check

@@ -245,3 +245,60 @@ def test_repeated_patterns_are_swept_once_and_summed(eng):
     _, perm = eng.perm_grad(dev(U), Ss, Ts, torch.from_numpy(np.asarray(g, dtype=np.complex128)))
     perm = perm.cpu().numpy()
     assert perm[0] == perm[2] == perm[5] and perm[1] == perm[4]
+
+
+_VARIANT_REF = {}
+
+
+@pytest.mark.parametrize("digits,swizzle", [(1, 0), (1, 1), (2, 0), (2, 1), (3, 0), (3, 1)])
+@pytest.mark.parametrize("n", [16, 21])
+def test_wide_walk_variants_against_oracle(eng, n, digits, swizzle):
+    # every form of the long-walk reverse sweep (register flip digits 1..3,
+    # quad exchanges by DPP or ds_swizzle) against the oracle's minors, entry
+    # by entry; n = 21 pads 3 of its 24 columns
+    m = 2 * n * n
+    U = workloads.haar(m, 500 + n)
+    Ss, Ts, g = _wide_patterns(m, (n,), 600 + n)
+    if n not in _VARIANT_REF:
+        _VARIANT_REF[n] = oracle_vjp(U, Ss, Ts, g), oracle.perm_mult(U, Ss[0], Ts[0])
+    ref, ref_p = _VARIANT_REF[n]
+    eng.walk_variant(digits, bool(swizzle))
+    try:
+        dU, perm = eng.perm_grad(dev(U), Ss, Ts, torch.from_numpy(np.asarray(g, dtype=np.complex128)))
+    finally:
+        eng.walk_variant(3, False)
+    tol = 1e-10 if n <= 20 else 1e-8
+    assert_entries_close(dU.cpu().numpy(), ref, tol, vjp_floor(U, Ss, Ts, g), "dU")
+    assert_entries_close(perm.cpu().numpy()[0], ref_p, tol, floor_of(U, Ss[0], Ts[0]), "perm")
+
+
+@pytest.mark.parametrize("digits,swizzle", [(1, 0), (2, 1), (3, 0)])
+def test_wide_walk_variants_n30_laplace(eng, digits, swizzle):
+    # n = 30 (8 columns per lane, 2 padded): the forward value of the same
+    # sweep against the forward kernel, and the Laplace expansion along every
+    # row and column, for three forms of the walk
+    n, m = 30, 1800
+    U = workloads.haar(m, 30)
+    S = np.zeros(m, np.int32)
+    T = np.zeros(m, np.int32)
+    S[:n] = 1
+    T[:n] = 1
+    eng.walk_variant(digits, bool(swizzle))
+    try:
+        dU, perm = eng.perm_grad(dev(U), [S], [T], torch.ones(1, dtype=torch.complex128))
+    finally:
+        eng.walk_variant(3, False)
+    d = np.conj(dU.cpu().numpy())
+    p = complex(perm.cpu().numpy()[0])
+    pf, _ = eng.perm(dev(U), S, T)
+    pf = complex(pf.cpu().numpy())
+    assert abs(p - pf) < 1e-10 * abs(pf)
+    _laplace_check(U, S, T, d, p, 1e-9)
+
+
+def test_walk_variant_rejects_out_of_range(eng):
+    import paper_2403_04006_amd as pq
+    for digits, sw in ((0, 0), (4, 0), (1, 2)):
+        with pytest.raises(pq.PqError):
+            eng.walk_variant(digits, sw)
+    eng.walk_variant(3, False)
