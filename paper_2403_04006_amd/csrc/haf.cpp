@@ -228,21 +228,6 @@ int describe(pq_ctx* ctx, const int32_t* reps, int d, int N, bool loops, HafDesc
     D.n_in = p.n_in;
     D.lane_states = p.lane_states;
     D.M = p.M;
-    {
-        // square-and-multiply schedule of x^{N/2}
-        const int K = N / 2;
-        int top = 0;
-        while ((K >> (top + 1)) > 0) ++top;
-        int z = 0;
-        for (int b = top - 1; b >= 0; --b) {
-            ++z;
-            if ((K >> b) & 1) {
-                D.pw_pack |= (uint32_t)z << (4 * D.pw_nseg++);
-                z = 0;
-            }
-        }
-        D.pw_tail = z;
-    }
     for (int i = 0; i < p.k; ++i) {
         D.rad[i] = (int8_t)p.rad[i];
         D.rep[i] = (int8_t)p.rep[i];

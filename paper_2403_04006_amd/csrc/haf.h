@@ -79,12 +79,6 @@ struct HafDesc {
     int32_t lane_states;
     int32_t M;                        // inner block length
     int32_t N;
-    // x^{N/2} (no loops): for each set bit of N/2 below the top one (pw_nseg
-    // of them), bits 4i..4i+3 of pw_pack squarings then a multiply by x;
-    // pw_tail squarings at the end
-    int32_t pw_nseg;
-    int32_t pw_tail;
-    uint32_t pw_pack;
     int8_t rad[kHafMaxModes];         // radix per digit
     int8_t rep[kHafMaxModes];         // r per digit
     // loops: P_N(x, l) = l^(N mod 2) prod_{k < N/2} (x + b_k l^2) / (N/2)!,

@@ -42,6 +42,47 @@ __device__ __forceinline__ void csqr(cplx& p) {
     p.re = __builtin_fma(p.re, p.re, -t);
 }
 
+// p = x^J for RR values at once by the binary method, straight-line for a
+// compile-time J (x^(2k) = (x^k)^2, x^(2k+1) = x^(2k) x).
+template <int J, int RR>
+__device__ __forceinline__ void pow_chain(cplx (&p)[RR], const cplx (&x)[RR]) {
+    if constexpr (J == 1) {
+#pragma unroll
+        for (int d = 0; d < RR; ++d) p[d] = x[d];
+    } else if constexpr (J % 2 == 0) {
+        pow_chain<J / 2, RR>(p, x);
+#pragma unroll
+        for (int d = 0; d < RR; ++d) csqr(p[d]);
+    } else {
+        pow_chain<J - 1, RR>(p, x);
+#pragma unroll
+        for (int d = 0; d < RR; ++d) p[d] = cmul(p[d], x[d]);
+    }
+}
+
+// p = x^J for a wavefront-uniform J in 1..kHafMaxN/2: one uniform branch to
+// the exponent's straight-line chain (no loop counters, no registers rotated
+// through loop-carried copies)
+template <int RR>
+__device__ __forceinline__ void pow_uniform(cplx (&p)[RR], const cplx (&x)[RR], int J) {
+    switch (J) {
+#define PQ_POW_CASE(j) \
+    case j: pow_chain<j, RR>(p, x); break;
+        PQ_POW_CASE(1) PQ_POW_CASE(2) PQ_POW_CASE(3) PQ_POW_CASE(4) PQ_POW_CASE(5) PQ_POW_CASE(6)
+        PQ_POW_CASE(7) PQ_POW_CASE(8) PQ_POW_CASE(9) PQ_POW_CASE(10) PQ_POW_CASE(11) PQ_POW_CASE(12)
+        PQ_POW_CASE(13) PQ_POW_CASE(14) PQ_POW_CASE(15) PQ_POW_CASE(16) PQ_POW_CASE(17) PQ_POW_CASE(18)
+        PQ_POW_CASE(19) PQ_POW_CASE(20) PQ_POW_CASE(21) PQ_POW_CASE(22) PQ_POW_CASE(23) PQ_POW_CASE(24)
+        PQ_POW_CASE(25) PQ_POW_CASE(26) PQ_POW_CASE(27) PQ_POW_CASE(28) PQ_POW_CASE(29) PQ_POW_CASE(30)
+        PQ_POW_CASE(31) PQ_POW_CASE(32)
+#undef PQ_POW_CASE
+        default:
+#pragma unroll
+            for (int d = 0; d < RR; ++d) p[d] = cplx{__builtin_nan(""), __builtin_nan("")};
+            break;
+    }
+}
+static_assert(kHafMaxN / 2 == 32, "pow_uniform covers exponents up to kHafMaxN / 2");
+
 // sTT[t][s] = A[time s][time t] of one pattern (zero outside): lane s adds dX
 // times it to T_s when time digit t moves.  Every thread of the workgroup.
 template <int NL, int RR>
@@ -182,28 +223,8 @@ __device__ __forceinline__ cdd haf_sweep(const HafDesc& a, const cplx* Ac, const
                 p[d] = pd;
             }
         } else {
-            // x^K by uniform loops: per set bit below the top one, z squarings
-            // (4 bits each of pw_pack) then one multiply by x; the trailing
-            // squarings last
-#pragma unroll
-            for (int d = 0; d < RR; ++d) p[d] = xd[d];
-            uint32_t pk = (uint32_t)a.pw_pack;
-            for (int i = 0; i < a.pw_nseg; ++i) {
-                const int z = (int)(pk & 15u);
-                pk >>= 4;
-#pragma unroll 2
-                for (int q = 0; q < z; ++q) {
-#pragma unroll
-                    for (int d = 0; d < RR; ++d) csqr(p[d]);
-                }
-#pragma unroll
-                for (int d = 0; d < RR; ++d) p[d] = cmul(p[d], xd[d]);
-            }
-#pragma unroll 2
-            for (int q = 0; q < a.pw_tail; ++q) {
-#pragma unroll
-                for (int d = 0; d < RR; ++d) csqr(p[d]);
-            }
+            // x^(N/2): the exponent's straight-line chain
+            pow_uniform<RR>(p, xd, J);
         }
         cplx in{0.0, 0.0};
 #pragma unroll
