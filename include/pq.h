@@ -191,6 +191,12 @@ typedef struct {
  *   - A plan whose every job is a single chunk (small jobs: all digits fit the
  *     lanes of one wavefront) has nothing for a queue to balance and runs the
  *     static schedule instead (one workgroup per chunk, then a final kernel).
+ *   - Within a plan, a column class runs as a queue only when it has more
+ *     chunks than resident wavefronts and they average at least 32 Gray time
+ *     states; lighter classes take one workgroup per chunk in the same launch
+ *     sequence (every pop is an atomic on one counter, and thousands of tiny
+ *     chunks popped at once cost more than their sweeps).  pq_queue_mode
+ *     overrides this.
  *   - Chunk sizes follow the autotuner when it is enabled (off by default: a
  *     first call then times 11 chunk policies under the queue, about 22 runs
  *     of the batch, and the kept policy under the static schedule as well;
@@ -206,6 +212,17 @@ typedef struct {
 int pq_perm_batched(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m,
                     const pq_job* jobs, int32_t njobs,
                     pq_c128* perm, pq_c128* amp, void* stream);
+
+/*
+ * pq_queue_mode -- which column classes pq_perm_batched runs as work queues:
+ * PQ_QUEUE_AUTO (default: the rule above, and a tuned plan's recorded
+ * schedule), PQ_QUEUE_ALWAYS (every class of a multi-chunk plan), or
+ * PQ_QUEUE_NEVER (the static schedule throughout).  Results are the same bits
+ * in every mode.  PQ_QUEUE=auto|always|never in the environment sets it at
+ * pq_create.  NULL ctx or another value: PQ_EINVAL.
+ */
+enum { PQ_QUEUE_AUTO = 0, PQ_QUEUE_ALWAYS = 1, PQ_QUEUE_NEVER = 2 };
+int pq_queue_mode(pq_ctx* ctx, int mode);
 
 /*
  * pq_perm_many -- the same jobs and outputs as pq_perm_batched, scheduled

@@ -286,6 +286,12 @@ class Engine:
         (pq_graph_enable)."""
         _check(self._lib.pq_graph_enable(self._ctx, 1 if on else 0), self._ctx)
 
+    def queue_mode(self, mode: str = "auto"):
+        """Which column classes perm_batched runs as work queues: "auto",
+        "always" or "never" (pq_queue_mode)."""
+        code = {"auto": 0, "always": 1, "never": 2}[mode]
+        _check(self._lib.pq_queue_mode(self._ctx, code), self._ctx)
+
     def walk_variant(self, register_digits: int, swizzle: bool = False):
         """Form of the reverse sweep for wide collision-free patterns
         (pq_walk_variant)."""

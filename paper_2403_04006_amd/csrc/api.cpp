@@ -62,6 +62,10 @@ int pq_create(pq_ctx** out, int hip_device) {
         else if (!strcmp(e, "launch")) c->fault = PQ_FAULT_LAUNCH;
     }
     if (const char* e = getenv("PQ_AUTOTUNE")) c->autotune = e[0] == '1';
+    if (const char* e = getenv("PQ_QUEUE")) {
+        if (!strcmp(e, "always")) c->queue_mode = PQ_QUEUE_ALWAYS;
+        else if (!strcmp(e, "never")) c->queue_mode = PQ_QUEUE_NEVER;
+    }
     if (const char* e = getenv("PQ_WALK")) {
         int kd = 0, sw = 0;
         if (sscanf(e, "%d,%d", &kd, &sw) == 2 && kd >= 1 && kd <= 3 && (sw == 0 || sw == 1))
@@ -72,6 +76,15 @@ int pq_create(pq_ctx** out, int hip_device) {
         c->tune_cache_load();
     }
     *out = c;
+    return PQ_OK;
+}
+
+int pq_queue_mode(pq_ctx* ctx, int mode) {
+    if (!ctx) return PQ_EINVAL;
+    ctx->clear_error();
+    if (mode != PQ_QUEUE_AUTO && mode != PQ_QUEUE_ALWAYS && mode != PQ_QUEUE_NEVER)
+        return ctx->fail(PQ_EINVAL, "pq_queue_mode: mode %d", mode);
+    ctx->queue_mode = mode;
     return PQ_OK;
 }
 

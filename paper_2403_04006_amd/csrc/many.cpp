@@ -41,6 +41,7 @@ int walk_occupancy(pq_ctx* ctx, const ManyClass& C);
 struct ManyClass {
     int mode = 0, ncmax = 0, var = 0;
     int first_chunk = 0, nchunks = 0;
+    uint64_t states = 0;     // time states of all its chunks
     int slot_doubles = 0;
     int64_t slot_off = 0;    // doubles
 };
@@ -90,6 +91,7 @@ struct ManyEntry {
         cplx* perm;
         cplx* amp;
         bool queue;
+        int qmode;           // the ctx's queue mode when captured
         hipGraph_t graph;
         hipGraphExec_t exec;
     };
@@ -334,6 +336,7 @@ int build_many(pq_ctx* ctx, int mode, int32_t m, const std::vector<PatternSpec>&
             std::stable_sort(cc.begin(), cc.end(), [](const MChunk& x, const MChunk& y) { return x.count > y.count; });
         C.first_chunk = (int)hch.size();
         C.nchunks = (int)cc.size();
+        for (const MChunk& ch : cc) C.states += ch.count;
         C.slot_off = (int64_t)partial_doubles;
         partial_doubles += (size_t)slot * C.slot_doubles;
         hch.insert(hch.end(), cc.begin(), cc.end());
@@ -516,9 +519,24 @@ int queue_grid(pq_ctx* ctx, const ManyClass& C) {
     return (int)std::max(1L, std::min((long)C.nchunks, resident));
 }
 
-// Launch sequence of a plan.  queue (forward plans only): every class runs as
-// a persistent work queue instead of one workgroup per chunk; the final
-// kernel follows either way.
+// Whether a class runs as a work queue in pq_perm_batched: only a class with
+// more chunks than resident wavefronts has anything to balance, and only
+// chunks of some length amortise a pop.  Every pop is an atomic on one
+// counter, and on this multi-XCD part those serialise: thousands of one-state
+// chunks popped at once cost a few hundred microseconds, where one workgroup
+// per chunk (the static launch) costs tens.
+constexpr uint64_t kQueueMinMeanStates = 32;
+bool class_queues(pq_ctx* ctx, const ManyClass& C) {
+    if (C.mode != kModeFwd && C.mode != kModeExt) return false;
+    if (C.nchunks <= 0 || ctx->queue_mode == PQ_QUEUE_NEVER) return false;
+    if (ctx->queue_mode == PQ_QUEUE_ALWAYS) return true;
+    if (C.states < kQueueMinMeanStates * (uint64_t)C.nchunks) return false;
+    return C.nchunks > queue_grid(ctx, C);
+}
+
+// Launch sequence of a plan.  queue (forward plans only): the classes that
+// class_queues admits run as persistent work queues, the rest with one
+// workgroup per chunk; the final kernel follows either way.
 int run_many(pq_ctx* ctx, ManyEntry& E, const cplx* U, int64_t ldu, int32_t m, cplx* perm, cplx* amp,
              const cplx* gperm, cplx* dU, int64_t lddu, hipStream_t st, hipEvent_t t0 = nullptr,
              hipEvent_t t1 = nullptr, bool queue = false) {
@@ -559,7 +577,9 @@ int run_many(pq_ctx* ctx, ManyEntry& E, const cplx* U, int64_t ldu, int32_t m, c
     fa.gperm = gperm;
     fa.gsum = E.d_gsum;
     const int nclass = (int)E.classes.size();
-    if (queue) {
+    bool any_queue = false;
+    for (const ManyClass& C : E.classes) any_queue = any_queue || (queue && class_queues(ctx, C));
+    if (any_queue) {
         QueuePrepArgs qp;
         qp.zero = E.d_qzero;
         qp.nzero = nclass;
@@ -589,7 +609,7 @@ int run_many(pq_ctx* ctx, ManyEntry& E, const cplx* U, int64_t ldu, int32_t m, c
         a.idx = E.d_idx;
         a.tabs = E.d_tabs;
         a.partials = E.d_partials + C.slot_off;
-        if (queue) {
+        if (queue && class_queues(ctx, C)) {
             QueueArgs q;
             q.m = a;
             q.counter = E.d_qzero + ci;
@@ -654,7 +674,9 @@ int run_many_graph(pq_ctx* ctx, ManyEntry& E, const cplx* U, int64_t ldu, int32_
                    hipStream_t st, bool queue = false) {
     ManyEntry::GraphRec* rec = nullptr;
     for (auto& g : E.graphs)
-        if (g.U == U && g.ldu == ldu && g.perm == perm && g.amp == amp && g.queue == queue) rec = &g;
+        if (g.U == U && g.ldu == ldu && g.perm == perm && g.amp == amp && g.queue == queue &&
+            g.qmode == ctx->queue_mode)
+            rec = &g;
     if (!rec) {
         ManyCache* cache = many_cache(ctx);
         int rc;
@@ -685,7 +707,7 @@ int run_many_graph(pq_ctx* ctx, ManyEntry& E, const cplx* U, int64_t ldu, int32_
             hipGraphDestroy(E.graphs.front().graph);
             E.graphs.erase(E.graphs.begin());
         }
-        E.graphs.push_back(ManyEntry::GraphRec{U, ldu, perm, amp, queue, g, x});
+        E.graphs.push_back(ManyEntry::GraphRec{U, ldu, perm, amp, queue, ctx->queue_mode, g, x});
         rec = &E.graphs.back();
     }
     return ctx->check(hipGraphLaunch(rec->exec, st), "graph launch");
@@ -902,7 +924,8 @@ static int perm_jobs(pq_ctx* ctx, const char* name, const pq_c128* U, int64_t ld
         // a plan whose every pattern is one chunk has nothing for a queue to
         // balance: one workgroup per chunk is already that schedule; a tuned
         // plan follows the schedule the autotuner measured faster
-        const bool q = E->max_chunks > 1 && E->queue_pref != 0;
+        const bool q = E->max_chunks > 1 && (E->queue_pref != 0 || ctx->queue_mode == PQ_QUEUE_ALWAYS) &&
+                       ctx->queue_mode != PQ_QUEUE_NEVER;
         if (!ctx->profiling)
             return run_many_graph(ctx, *E, (const cplx*)U, ldu, m, (cplx*)perm, (cplx*)amp, st, q);
         return run_many(ctx, *E, (const cplx*)U, ldu, m, (cplx*)perm, (cplx*)amp, nullptr, nullptr, 0, st,

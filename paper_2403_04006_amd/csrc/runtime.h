@@ -67,6 +67,8 @@ struct pq_ctx {
     // reverse-sweep walk variant (pq_walk_variant, PQ_WALK): 2 (register
     // flip digits - 1) + (quad exchanges through ds_swizzle)
     int walk_variant = pq::kWalkDefaultVariant;
+    // which classes pq_perm_batched runs as work queues (pq_queue_mode, PQ_QUEUE)
+    int queue_mode = PQ_QUEUE_AUTO;
 
     // fault injection (pq_fault_inject, PQ_FAULT_INJECT): while set, every
     // device allocation (PQ_FAULT_ALLOC) or every launch check

@@ -1,10 +1,12 @@
 """Parity of the batched boundary call (pq_perm_batched) against the oracle.
 
-pq_perm_batched runs multi-chunk plans as a persistent work queue (resident
-wavefronts pop chunks from an atomic counter, each writing its chunk's slot)
-replayed from a captured HIP graph, and plans whose every job is one chunk on
-the static schedule.  Both schedules add each pattern's slots in slot order
-in the same final kernel, so they give the same bits."""
+pq_perm_batched replays its launch sequence from a captured HIP graph. The
+heavy column classes of a multi-chunk plan run as a persistent work queue
+(resident wavefronts pop chunks from an atomic counter, each writing its
+chunk's slot); light classes, and plans whose every job is one chunk, run the
+static schedule (one workgroup per chunk).  Both schedules add each pattern's
+slots in slot order in the same final kernel, so they give the same bits; the
+queue tests force every class through the queue (pq_queue_mode)."""
 import numpy as np
 import pytest
 
@@ -268,12 +270,27 @@ def test_sampling_shaped_extend_jobs_full_size(eng):
 
 
 def _queue_vs_static(eng, U, jobs, n_out=None):
+    # every class of the plan through the work queue kernel (these batches
+    # are lighter than the automatic rule's threshold), against the static
+    # schedule; the automatic and the never-queue modes give the same bits
     Ud = dev(U)
-    a, _ = eng.perm_batched(Ud, jobs, n_out=n_out)
+    eng.queue_mode("always")
+    try:
+        a, _ = eng.perm_batched(Ud, jobs, n_out=n_out)
+    finally:
+        eng.queue_mode("auto")
     b, _ = eng.perm_many(Ud, jobs, n_out=n_out)
+    c, _ = eng.perm_batched(Ud, jobs, n_out=n_out)
+    eng.queue_mode("never")
+    try:
+        d, _ = eng.perm_batched(Ud, jobs, n_out=n_out)
+    finally:
+        eng.queue_mode("auto")
     torch.cuda.synchronize()
-    a, b = a.cpu().numpy(), b.cpu().numpy()
+    a, b, c, d = a.cpu().numpy(), b.cpu().numpy(), c.cpu().numpy(), d.cpu().numpy()
     assert np.array_equal(a, b)
+    assert np.array_equal(c, b)
+    assert np.array_equal(d, b)
     return a
 
 
@@ -326,6 +343,7 @@ def test_work_queue_graph_replays_match_static(eng):
     jobs = [perm_job(S, T, out=k) for k, (S, T) in enumerate(pats)]
     Ud = dev(workloads.haar(m, 45))
     out = torch.empty(24, dtype=torch.complex128, device="cuda")
+    eng.queue_mode("always")
     for rep in range(4):
         if rep == 2:
             Ud.copy_(torch.from_numpy(workloads.haar(m, 46)))
@@ -335,6 +353,18 @@ def test_work_queue_graph_replays_match_static(eng):
         ref, _ = eng.perm_many(Ud, jobs)
         torch.cuda.synchronize()
         assert np.array_equal(out.cpu().numpy(), ref.cpu().numpy()), rep
+    eng.queue_mode("auto")
+
+
+def test_queue_mode_rejects_unknown_modes(eng):
+    import paper_2403_04006_amd as pq
+    from paper_2403_04006_amd import _lib
+    assert eng._lib.pq_queue_mode(eng._ctx, 3) == _lib.PQ_EINVAL
+    assert eng._lib.pq_queue_mode(eng._ctx, -1) == _lib.PQ_EINVAL
+    with pytest.raises(KeyError):
+        eng.queue_mode("sometimes")
+    eng.queue_mode("auto")
+    assert pq is not None
 
 
 @pytest.mark.skip(reason="the first persistent work-queue schedule (an earlier kernel, since removed) did not "
