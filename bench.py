@@ -27,16 +27,16 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CUs x 2.4 GHz x 128 FP64 flop/clk/CU
 # HBM traffic of one n=30 sweep launch, from two rocprofv3 --pmc passes
 # (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) over this script with
 # --calib-copy-mib 256; each scaled by what the same counter read for a plain
-# 256 MiB device-to-device copy in the same run (FETCH 131088.6 KiB, WRITE
+# 256 MiB device-to-device copy in the same run (FETCH 131092.9 KiB, WRITE
 # 262144 KiB, against 262144 KiB moved each way).  Valid only for the sources
 # it was measured on: the hash covers every file that shapes the launch.
 SWEEP_TRAFFIC = {
     "sources": ["k_glynn_impl.h", "k_glynn_p2.hip", "sweep_common.h", "device.h", "pq_common.h",
                 "runtime.cpp", "runtime.h", "plan.cpp", "plan.h", "api.cpp", "k_misc.hip"],
-    "sha256": "3dc48c55a2bf6e084bfa65c78e96221732412eb1680e7e827ee10990c3f54bd5",
+    "sha256": "82ca502996d84b4ccc33e530e14565da28712c90daa113621721159af05850f0",
     "n": 30,
-    "fetch_kib": 246.7, "write_kib": 24.0,
-    "fetch_factor": 262144.0 / 131088.6, "write_factor": 1.0,
+    "fetch_kib": 245.2, "write_kib": 24.0,
+    "fetch_factor": 262144.0 / 131092.9, "write_factor": 1.0,
 }
 
 

@@ -198,7 +198,7 @@ typedef struct {
  *     chunks popped at once cost more than their sweeps).  pq_queue_mode
  *     overrides this.
  *   - Chunk sizes follow the autotuner when it is enabled (off by default: a
- *     first call then times 11 chunk policies under the queue, about 22 runs
+ *     first call then times 13 chunk policies under the queue, about 26 runs
  *     of the batch, and the kept policy under the static schedule as well;
  *     the faster schedule is recorded with the policy).  Recorded decisions
  *     (pq_autotune_enable, PQ_AUTOTUNE_CACHE) apply.  Untuned plans run the
@@ -248,7 +248,7 @@ int pq_perm_many(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m,
  * list whose shape (m, and for every job kind and padded column count the
  * number of jobs and of Gray terms, each rounded to half an octave) has no
  * recorded policy plans and runs the job
- * list under each of 11 candidate policies (the default first), timing the
+ * list under each of 13 candidate policies (the default first), timing the
  * sweep kernels with HIP events (best of two runs each), keeps the fastest
  * plan and records its policy.  That call therefore runs the jobs about 22
  * times and synchronizes the stream; its outputs are those of the kept plan.

@@ -32,7 +32,7 @@ constexpr uint64_t kWalkMinChunk = 32;
 // chunk policies the autotuner times (the first is the default)
 constexpr ChunkPolicy kTuneCandidates[] = {
     {16, 4, 64}, {4, 2, 64}, {8, 1, 64}, {8, 2, 64}, {8, 4, 64}, {16, 2, 64},
-    {16, 8, 64}, {32, 4, 64}, {32, 8, 64}, {8, 2, 256}, {16, 4, 256},
+    {16, 8, 64}, {32, 4, 64}, {32, 8, 64}, {8, 2, 256}, {16, 4, 256}, {32, 8, 32}, {64, 8, 32},
 };
 constexpr int kMaxManyEntries = 4;
 struct ManyClass;
