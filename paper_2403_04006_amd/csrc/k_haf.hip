@@ -1,6 +1,8 @@
 // Kernels of the loop hafnian sum (see haf.h).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "device.h"
 #include "haf.h"
 
@@ -168,7 +170,8 @@ __device__ __forceinline__ cdd haf_sweep(const HafDesc& a, const cplx* Ac, const
     // and l_d = l + X_d gamma_r, x = q / 2 over the other digits, u = (A X)_r
     // (the common 1 / (N/2)! is applied once at the end).  The RR evaluations
     // share every loop and coefficient load.
-    auto terms = [&](const cplx& x, const cplx& l, const cplx& u, double w) {
+    auto terms = [&](auto jc, const cplx& x, const cplx& l, const cplx& u, double w) {
+        constexpr int JC = decltype(jc)::value;   // N/2 when known at compile time, else 0
         cplx xd[RR], p[RR];
 #pragma unroll
         for (int d = 0; d < RR; ++d) {
@@ -224,7 +227,8 @@ __device__ __forceinline__ cdd haf_sweep(const HafDesc& a, const cplx* Ac, const
             }
         } else {
             // x^(N/2): the exponent's straight-line chain
-            pow_uniform<RR>(p, xd, J);
+            if constexpr (JC > 0) pow_chain<JC, RR>(p, xd);
+            else pow_uniform<RR>(p, xd, J);
         }
         cplx in{0.0, 0.0};
 #pragma unroll
@@ -275,7 +279,10 @@ __device__ __forceinline__ cdd haf_sweep(const HafDesc& a, const cplx* Ac, const
         cplx x{0.5 * (qLL.re + 2.0 * qLT.re + tt.re), 0.5 * (qLL.im + 2.0 * qLT.im + tt.im)};
         cplx l{lL.re + lT.re, lL.im + lT.im};
         const HafStep* tab = refl ? tabp + M : tabp;
-        terms(x, l, cplx{uL.re + U.re, uL.im + U.im}, wh * tab[pos0].w);
+        // the segment's steps, with the exponent of the term polynomial as a
+        // compile-time constant when jc carries it
+        auto steps = [&](auto jc) {
+        terms(jc, x, l, cplx{uL.re + U.re, uL.im + U.im}, wh * tab[pos0].w);
         for (int p = pos0 + 1; p < pos0 + len; ++p) {
             const HafStep e = tab[p];
             const int t = e.t;
@@ -292,7 +299,25 @@ __device__ __forceinline__ cdd haf_sweep(const HafDesc& a, const cplx* Ac, const
             if constexpr (RR > 1) cfma_to(U, dx, row[NL]);
             if constexpr (LOOP) cfma_to(l, dx, gc[TO + t]);
             cfma_to(T, dx, sTT[t][sl]);
-            terms(x, l, cplx{uL.re + U.re, uL.im + U.im}, wh * e.w);
+            terms(jc, x, l, cplx{uL.re + U.re, uL.im + U.im}, wh * e.w);
+        }
+        };
+        if constexpr (!LOOP) {
+            // one uniform branch per segment to the exponent's own step loop
+            switch (J) {
+#define PQ_SEG_CASE(j) \
+    case j: steps(std::integral_constant<int, j>{}); break;
+                PQ_SEG_CASE(1) PQ_SEG_CASE(2) PQ_SEG_CASE(3) PQ_SEG_CASE(4) PQ_SEG_CASE(5) PQ_SEG_CASE(6)
+                PQ_SEG_CASE(7) PQ_SEG_CASE(8) PQ_SEG_CASE(9) PQ_SEG_CASE(10) PQ_SEG_CASE(11) PQ_SEG_CASE(12)
+                PQ_SEG_CASE(13) PQ_SEG_CASE(14) PQ_SEG_CASE(15) PQ_SEG_CASE(16) PQ_SEG_CASE(17) PQ_SEG_CASE(18)
+                PQ_SEG_CASE(19) PQ_SEG_CASE(20) PQ_SEG_CASE(21) PQ_SEG_CASE(22) PQ_SEG_CASE(23) PQ_SEG_CASE(24)
+                PQ_SEG_CASE(25) PQ_SEG_CASE(26) PQ_SEG_CASE(27) PQ_SEG_CASE(28) PQ_SEG_CASE(29) PQ_SEG_CASE(30)
+                PQ_SEG_CASE(31) PQ_SEG_CASE(32)
+#undef PQ_SEG_CASE
+                default: steps(std::integral_constant<int, 0>{}); break;
+            }
+        } else {
+            steps(std::integral_constant<int, 0>{});
         }
         s = seg_end;
     }
