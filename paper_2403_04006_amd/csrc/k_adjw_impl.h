@@ -284,7 +284,8 @@ __global__ __launch_bounds__(kWalkWaves * 64) void adjw_kernel(const ManyArgs a)
     // digits, the fixed row after them and chunks of whole 8-state blocks
     if (J.n_time > kRowsMax || J.n_time < 3 || J.n_lane != 4 || J.lane_states != kWalkTerms ||
         J.r < J.n_lane + J.n_time + 1 || ((ch.start | ch.count) & 7ull) != 0) {
-        if (lane < 4) slot[lane] = __builtin_nan("");
+        // the whole slot, so the value and every derivative of the pattern show it
+        for (int e = lane; e < a.slot_doubles; e += 64) slot[e] = __builtin_nan("");
         return;
     }
     const cplx* mat = a.mat + J.mat_off;
