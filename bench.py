@@ -280,7 +280,7 @@ def main() -> int:
     grad_kernel = None
     if not args.no_grad:
         grad_kernel = []
-        for nk in (20, n):
+        for nk in sorted({20, 24, n, 32}):
             Uk = torch.from_numpy(workloads.collision_free_block(nk, 0)).to(dev)
             onesk = np.ones(nk, np.int32)
             pk = pq.PatternSet([onesk], [onesk], nk)

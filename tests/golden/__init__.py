@@ -52,3 +52,23 @@ def load_repeated(path):
         cases.append({"index": idx, "S": S, "T": T, "perm": complex(q[0] + q[1], q[2] + q[3])})
         i += 4
     return U, cases
+
+
+def load_minors(n):
+    """Stored permanents of minors of the seed-0 block (make_golden_minors.py):
+    (A, [(i, j, value), ...]) with A from single_n<n>_blocks.npy."""
+    import os
+    here = os.path.dirname(os.path.abspath(__file__))
+    A = np.load(os.path.join(here, f"single_n{n}_blocks.npy"), allow_pickle=False)[0]
+    out = []
+    with open(os.path.join(here, f"minors_n{n}.txt")) as f:
+        for ln in f:
+            if not ln.strip() or ln.startswith("#"):
+                continue
+            head = ln.split()
+            assert head[0] == "minor" and int(head[1]) == n and int(head[2]) == 0
+            out.append((int(head[3]), int(head[4]), complex(float(head[5]), float(head[6]))))
+    return A, out
+
+
+MINOR_SIZES = (30, 32)

@@ -302,3 +302,19 @@ def test_walk_variant_rejects_out_of_range(eng):
         with pytest.raises(pq.PqError):
             eng.walk_variant(digits, sw)
     eng.walk_variant(3, False)
+
+
+@pytest.mark.parametrize("n", [30, 32])
+def test_wide_gradient_full_size_against_stored_minors(eng, n):
+    # the reverse walk's derivative entries at full size against the oracle's
+    # permanents of the corresponding minors (tests/golden/make_golden_minors.py),
+    # each entry by its own relative error, 1e-8 for n <= 32
+    from tests.golden import load_minors
+    A, minors = load_minors(n)
+    S = np.ones(n, np.int32)
+    dU, perm = eng.perm_grad(dev(A), [S], [S], torch.ones(1, dtype=torch.complex128))
+    d = np.conj(dU.cpu().numpy())
+    for i, j, want in minors:
+        err = abs(d[i, j] - want) / abs(want)
+        print(f"n={n} d perm / d A[{i},{j}]: rel err {err:.2e}", flush=True)
+        assert err < 1e-8, (i, j, d[i, j], want)
