@@ -74,7 +74,8 @@ const char* pq_version(void);
  * PQ_AUTOTUNE_CACHE=<file> loads this device's recorded tuning decisions from
  * that file and appends new ones to it (one JSON object per line, keyed by
  * the device's architecture and CU count and the job list's shape);
- * PQ_FAULT_INJECT (pq_fault_inject). */
+ * PQ_FAULT_INJECT (pq_fault_inject); PQ_QUEUE (pq_queue_mode); PQ_WALK
+ * (pq_walk_variant); PQ_LHAF_PACK (pq_lhaf_pack). */
 int pq_create(pq_ctx** out, int hip_device);
 
 /* Destroy a context (NULL-safe).  Waits for the device before freeing. */
@@ -432,6 +433,24 @@ int pq_loss_dilation_vw(pq_ctx* ctx, const pq_c128* V, int64_t ldv, const double
  */
 int pq_lhaf(pq_ctx* ctx, const pq_c128* A, int64_t lda, int32_t d, const pq_c128* gamma,
             const int32_t* reps, pq_c128* out, void* stream);
+
+/*
+ * pq_lhaf_pack -- whether pq_lhaf fills idle lanes.  When the lane digits of
+ * a sweep leave lanes of a wavefront idle (between 33 and 63 lane states,
+ * e.g. 54 for (2, ..., 2) repetitions), the idle lanes can run lane states of
+ * a second Gray segment of the same parity, so that nearly every lane does
+ * useful work (378 of 384 lanes at 54 states).
+ *   PQ_LHAF_PACK_AUTO (default): packed when the sweep fills every resident
+ *     wavefront of the device without it (shorter sweeps gain nothing and
+ *     pay the per-segment set-up);
+ *   PQ_LHAF_PACK_ALWAYS / PQ_LHAF_PACK_NEVER: whenever the lane states allow
+ *     it / never.
+ * Results agree to rounding (the order of the partial sums differs).
+ * PQ_LHAF_PACK=auto|always|never in the environment sets it at pq_create.
+ * NULL ctx or another mode: PQ_EINVAL.
+ */
+enum { PQ_LHAF_PACK_AUTO = 0, PQ_LHAF_PACK_ALWAYS = 1, PQ_LHAF_PACK_NEVER = 2 };
+int pq_lhaf_pack(pq_ctx* ctx, int mode);
 
 /*
  * pq_lhaf_many -- pq_lhaf for npat repetition vectors on one matrix (the

@@ -292,6 +292,12 @@ class Engine:
         code = {"auto": 0, "always": 1, "never": 2}[mode]
         _check(self._lib.pq_queue_mode(self._ctx, code), self._ctx)
 
+    def lhaf_pack(self, mode: str = "auto"):
+        """When the loop hafnian sweep fills idle lanes across Gray segments:
+        "auto", "always" or "never" (pq_lhaf_pack)."""
+        code = {"auto": 0, "always": 1, "never": 2}[mode]
+        _check(self._lib.pq_lhaf_pack(self._ctx, code), self._ctx)
+
     def walk_variant(self, register_digits: int, swizzle: bool = False):
         """Form of the reverse sweep for wide collision-free patterns
         (pq_walk_variant)."""

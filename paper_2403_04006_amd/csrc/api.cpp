@@ -66,6 +66,10 @@ int pq_create(pq_ctx** out, int hip_device) {
         if (!strcmp(e, "always")) c->queue_mode = PQ_QUEUE_ALWAYS;
         else if (!strcmp(e, "never")) c->queue_mode = PQ_QUEUE_NEVER;
     }
+    if (const char* e = getenv("PQ_LHAF_PACK")) {
+        if (!strcmp(e, "always")) c->lhaf_pack = PQ_LHAF_PACK_ALWAYS;
+        else if (!strcmp(e, "never")) c->lhaf_pack = PQ_LHAF_PACK_NEVER;
+    }
     if (const char* e = getenv("PQ_WALK")) {
         int kd = 0, sw = 0;
         if (sscanf(e, "%d,%d", &kd, &sw) == 2 && kd >= 1 && kd <= 3 && (sw == 0 || sw == 1))
@@ -85,6 +89,15 @@ int pq_queue_mode(pq_ctx* ctx, int mode) {
     if (mode != PQ_QUEUE_AUTO && mode != PQ_QUEUE_ALWAYS && mode != PQ_QUEUE_NEVER)
         return ctx->fail(PQ_EINVAL, "pq_queue_mode: mode %d", mode);
     ctx->queue_mode = mode;
+    return PQ_OK;
+}
+
+int pq_lhaf_pack(pq_ctx* ctx, int mode) {
+    if (!ctx) return PQ_EINVAL;
+    ctx->clear_error();
+    if (mode != PQ_LHAF_PACK_AUTO && mode != PQ_LHAF_PACK_ALWAYS && mode != PQ_LHAF_PACK_NEVER)
+        return ctx->fail(PQ_EINVAL, "pq_lhaf_pack: mode %d", mode);
+    ctx->lhaf_pack = mode;
     return PQ_OK;
 }
 

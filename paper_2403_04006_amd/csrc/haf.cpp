@@ -262,10 +262,31 @@ int pq_lhaf(pq_ctx* ctx, const pq_c128* A, int64_t lda, int32_t d, const pq_c128
     if (rc) return rc;
     if (D.nchunks == 0) return ctx->check(launch_fill((cplx*)out, nullptr, D.trivial, st), "fill");
 
-    const int occ = occupancy_haf(loops, p.nl, p.rr);
+    // lane packing (HafPack): possible when the lane digits leave lanes idle
+    // and every lane index past them fits the upper half's T vector; by
+    // default taken when the unpacked sweep fills every resident wavefront
+    bool pack = ctx->lhaf_pack != PQ_LHAF_PACK_NEVER && p.lane_states > kHafMaxTime && p.lane_states < 64;
+    if (pack && ctx->lhaf_pack == PQ_LHAF_PACK_AUTO) {
+        const int occ0 = occupancy_haf(loops, p.nl, p.rr);
+        const uint64_t full = (uint64_t)ctx->num_cu * (uint64_t)(occ0 > 0 ? occ0 : 0) * kWavesPerBlock;
+        pack = (p.time_states + kHafMinChunk - 1) / kHafMinChunk > full;
+    }
+    HafPack pk;
+    memset(&pk, 0, sizeof(pk));
+    uint64_t work = p.time_states;
+    if (pack) {
+        const uint64_t ns = p.time_states / (uint64_t)p.M;
+        pk.seg[0] = (ns + 1) / 2;
+        pk.seg[1] = ns / 2;
+        pk.fill = 64 - p.lane_states;
+        pk.per = (p.lane_states + pk.fill - 1) / pk.fill;
+        pk.cols0 = haf_pack_columns(pk, pk.seg[0]);
+        work = (pk.cols0 + haf_pack_columns(pk, pk.seg[1])) * (uint64_t)p.M;
+    }
+    const int occ = pack ? occupancy_haf_pack(loops, p.nl, p.rr) : occupancy_haf(loops, p.nl, p.rr);
     if (occ <= 0) return ctx->fail(PQ_EDEVICE, "pq_lhaf: occupancy query failed");
     const uint64_t max_waves = (uint64_t)ctx->num_cu * (uint64_t)occ * kWavesPerBlock;
-    uint64_t waves = (p.time_states + kHafMinChunk - 1) / kHafMinChunk;
+    uint64_t waves = (work + kHafMinChunk - 1) / kHafMinChunk;
     if (waves > max_waves) waves = max_waves;
     if (waves < 1) waves = 1;
     const int grid = (int)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
@@ -302,6 +323,8 @@ int pq_lhaf(pq_ctx* ctx, const pq_c128* A, int64_t lda, int32_t d, const pq_c128
     a.tab = (const HafStep*)(ws + oT);
     a.partials = (double*)(ws + oP);
     a.waves = (uint32_t)waves;
+    a.work = work;
+    a.pk = pk;
     a.d = D;
 
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -312,7 +335,8 @@ int pq_lhaf(pq_ctx* ctx, const pq_c128* A, int64_t lda, int32_t d, const pq_c128
         rc = ctx->check(hipEventRecord(e0, st), "profile: record");
         if (rc) return rc;
     }
-    rc = ctx->check(launch_haf(loops, p.nl, p.rr, a, grid, st), "hafnian sweep");
+    rc = ctx->check(pack ? launch_haf_pack(loops, p.nl, p.rr, a, grid, st) : launch_haf(loops, p.nl, p.rr, a, grid, st),
+                    "hafnian sweep");
     if (rc) return rc;
     if (ctx->profiling) {
         rc = ctx->check(hipEventRecord(e1, st), "profile: record");

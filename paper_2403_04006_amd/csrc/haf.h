@@ -96,12 +96,63 @@ struct HafDesc {
     cplx trivial;
 };
 
+// Lane packing of one pattern whose L lane states leave F = 64 - L lanes of
+// a wavefront idle (32 < L < 64).  The inner Gray block is walked the same way
+// in every segment of one parity of its Gray rank (rank hi walks it reflected
+// when hi is odd), so lanes L..63 can run a slice of F lane states of a
+// second segment of the same parity while lanes 0..L-1 run all L states of
+// the first; lanes 32..63 then keep the second segment's T vector.  The
+// segments of one parity are taken in groups of per + 1: the first per
+// segments of a group are the first segments of its per columns (wavefront
+// segments) and its last is split into per slices of at most F states.
+// Segments left over after the last full group run alone.  Useful lanes:
+// (per + 1) L of per x 64 (378 of 384 at L = 54).
+struct HafPack {
+    uint64_t seg[2];                  // segments of even and of odd Gray rank
+    uint64_t cols0;                   // columns of the even segments
+    int32_t per;                      // columns per group: ceil(L / F)
+    int32_t fill;                     // F
+};
+
+// Column col of a packed sweep: the ranks of its two segments and the slice
+// [off, off + cnt) of the second one's lane states (cnt 0: none).
+PQ_HD void haf_pack_column(const HafPack& pk, int L, uint64_t col, uint64_t& hi_a, uint64_t& hi_b, int& off,
+                           int& cnt) {
+    const int par = col < pk.cols0 ? 0 : 1;
+    const uint64_t c = par ? col - pk.cols0 : col;
+    const uint64_t per = (uint64_t)pk.per, grp = per + 1;
+    const uint64_t ng = pk.seg[par] / grp;
+    uint64_t ia, ib;
+    if (c < ng * per) {
+        const uint64_t g = c / per, j = c - g * per;
+        ia = g * grp + j;
+        ib = g * grp + per;
+        off = (int)j * pk.fill;
+        cnt = L - off < pk.fill ? L - off : pk.fill;
+    } else {
+        ia = ng * grp + (c - ng * per);
+        ib = ia;
+        off = 0;
+        cnt = 0;
+    }
+    hi_a = 2 * ia + (uint64_t)par;
+    hi_b = 2 * ib + (uint64_t)par;
+}
+
+// Columns of a packed sweep over K segments of one parity.
+PQ_HD uint64_t haf_pack_columns(const HafPack& pk, uint64_t K) {
+    const uint64_t grp = (uint64_t)pk.per + 1, ng = K / grp;
+    return ng * (uint64_t)pk.per + (K - ng * grp);
+}
+
 struct HafArgs {
     const cplx* Ac;                   // [k][k]
     const cplx* gc;                   // [k]
     const HafStep* tab;               // [2][M]: forward block, reflected block
     double* partials;                 // [waves][4] double-double per wavefront
     uint32_t waves;
+    uint64_t work;                    // wavefront steps: time_states, or columns x M when packed
+    HafPack pk;
     HafDesc d;
 };
 
@@ -145,6 +196,9 @@ hipError_t launch_haf_prep(const HafPrepArgs& a, hipStream_t s);
 // rr in 1..3.
 hipError_t launch_haf(bool loops, int nl, int rr, const HafArgs& a, int grid, hipStream_t s);
 int occupancy_haf(bool loops, int nl, int rr);
+// the packed sweep (HafPack): the same digits, lanes filled across segments
+hipError_t launch_haf_pack(bool loops, int nl, int rr, const HafArgs& a, int grid, hipStream_t s);
+int occupancy_haf_pack(bool loops, int nl, int rr);
 hipError_t launch_haf_many_prep(const HafManyPrepArgs& a, int npat, hipStream_t s);
 hipError_t launch_haf_many(bool loops, int nl, int rr, const HafManyArgs& a, int blocks, hipStream_t s);
 hipError_t launch_haf_many_final(const HafManyFinalArgs& a, hipStream_t s);

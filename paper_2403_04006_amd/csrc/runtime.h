@@ -69,6 +69,9 @@ struct pq_ctx {
     int walk_variant = pq::kWalkDefaultVariant;
     // which classes pq_perm_batched runs as work queues (pq_queue_mode, PQ_QUEUE)
     int queue_mode = PQ_QUEUE_AUTO;
+    // when pq_lhaf fills idle lanes across Gray segments (pq_lhaf_pack,
+    // PQ_LHAF_PACK)
+    int lhaf_pack = PQ_LHAF_PACK_AUTO;
 
     // fault injection (pq_fault_inject, PQ_FAULT_INJECT): while set, every
     // device allocation (PQ_FAULT_ALLOC) or every launch check

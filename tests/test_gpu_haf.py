@@ -303,3 +303,66 @@ def test_constant_matrix_every_vertex_count(eng, N):
     got = gpu_lhaf(eng, np.full((3, 3), a), np.full(3, gv), reps)
     bound = max(tol(N), 64 * 2.0 ** -52 * sum_condition(a, gv, reps, True))
     assert rel(got, want) <= bound, (N, rel(got, want), bound)
+
+
+def lane_plan(reps):
+    """Lane states, time states and inner block of pq_lhaf's plan (the
+    planner's digit rules restated for choosing test cases)."""
+    r = [x for x in reps if x > 0]
+    f = int(np.argmin(r))
+    rho = [x if i == f else x + 1 for i, x in enumerate(r)]
+    order = sorted(range(len(r)), key=lambda i: (rho[i] != 1, -rho[i]))
+    lane, prod, big = set(), 1, 0
+    for i in order:
+        if rho[i] == 1:
+            lane.add(i)
+        elif big < 6 and prod * rho[i] <= 64:
+            lane.add(i)
+            prod *= rho[i]
+            big += 1
+    rest = [i for i in range(len(r)) if i not in lane]
+    reg = next((i for want in (3, 2) for i in rest if rho[i] == want), None)
+    time = [rho[i] for i in rest if i != reg]
+    ts, M = 1, 1
+    for x in time:
+        ts *= x
+    for x in time:
+        if M * x > 2048:
+            break
+        M *= x
+    return prod, ts, M
+
+
+@pytest.mark.parametrize("reps", [[2] * 14, [4, 4] + [2] * 10, [5, 5] + [1] * 16, [3, 3, 2] + [1] * 16])
+def test_lane_packing_matches_unpacked_and_oracle(eng, reps):
+    # between 33 and 63 lane states the idle lanes run a second Gray segment
+    # of the same parity: 54, 50, 36 and 48 lane states, several segments of
+    # each parity, full groups and leftover segments; the packed sweep
+    # against the oracle, and against the unpacked one (the same terms added
+    # in another order: they differ by the rounding of a sum that cancels to
+    # about 1e-3 of its terms here, a few 1e-12 relative)
+    L, ts, M = lane_plan(reps)
+    assert 32 < L < 64 and ts // M >= 4, (L, ts, M)
+    d = len(reps)
+    A = workloads.gbs_matrix(d, d + 3)
+    g = workloads.loop_vector(d, d + 3)
+    N = sum(reps)
+    try:
+        for gamma in (g, None):
+            eng.lhaf_pack("always")
+            packed = gpu_lhaf(eng, A, gamma, reps)
+            eng.lhaf_pack("never")
+            plain = gpu_lhaf(eng, A, gamma, reps)
+            assert rel(packed, plain) <= 1e-10, (reps, gamma is None)
+            assert rel(packed, oracle.lhaf_rep(A, gamma, reps)) <= tol(N), (reps, gamma is None)
+    finally:
+        eng.lhaf_pack("auto")
+
+
+def test_lane_packing_rejects_unknown_modes(eng):
+    from paper_2403_04006_amd import _lib
+    assert eng._lib.pq_lhaf_pack(eng._ctx, 3) == _lib.PQ_EINVAL
+    assert eng._lib.pq_lhaf_pack(eng._ctx, -1) == _lib.PQ_EINVAL
+    with pytest.raises(KeyError):
+        eng.lhaf_pack("sometimes")
+    eng.lhaf_pack("auto")
