@@ -631,6 +631,9 @@ def main() -> int:
             "traffic": sweep_traffic_bytes(n),
             "kernel": f"glynn_bin<{n}>",
             "flops_per_launch": algo_flops,
+            # the device as the HIP runtime reports it; peak above is the
+            # published figure
+            "device": eng.device_peak(),
         },
         "parity": parity,
         "inputs": input_source,

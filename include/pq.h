@@ -67,6 +67,15 @@ enum {
 /* Library version string, e.g. "pq 0.1 gfx950". Static storage. */
 const char* pq_version(void);
 
+/*
+ * pq_device_peak -- the ctx's device as the HIP runtime reports it: compute
+ * units (*cus), peak engine clock in kHz (*clock_khz), and the FP64 vector
+ * peak they imply, cus x clock x 128 flops (4 SIMDs of 16 FP64 lanes per CU,
+ * one FMA each per clock), in TFLOP/s (*fp64_tflops).  Host-only, no GPU
+ * work.  NULL ctx or output: PQ_EINVAL.
+ */
+int pq_device_peak(pq_ctx* ctx, int32_t* cus, int32_t* clock_khz, double* fp64_tflops);
+
 /* Create a context on HIP device `hip_device` (PQ_EINVAL for a bad ordinal or
  * NULL out, PQ_EDEVICE if the device cannot be queried).  *out is set only on
  * success.  The ctx owns device workspace, grown on demand.  Environment read

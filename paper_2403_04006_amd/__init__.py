@@ -80,6 +80,14 @@ class Engine:
         except Exception:
             pass
 
+    def device_peak(self) -> dict:
+        """Compute units, peak clock and the FP64 vector peak they imply, as
+        the HIP runtime reports the device (pq_device_peak)."""
+        cus, khz, tf = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        _check(self._lib.pq_device_peak(self._ctx, ctypes.byref(cus), ctypes.byref(khz), ctypes.byref(tf)),
+               self._ctx)
+        return {"cus": cus.value, "clock_mhz": khz.value / 1e3, "fp64_vector_peak_tflops": tf.value}
+
     # ----------------------------------------------------------- pq_perm
     def perm(self, U: torch.Tensor, S: Sequence[int], T: Sequence[int], *,
              out_perm: torch.Tensor | None = None, out_amp: torch.Tensor | None = None):

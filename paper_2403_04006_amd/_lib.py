@@ -63,6 +63,8 @@ _VP = ctypes.c_void_p
 
 _SIGNATURES = {
     "pq_version": ([], ctypes.c_char_p),
+    "pq_device_peak": ([_VP, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                        ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "pq_create": ([ctypes.POINTER(ctypes.c_void_p), ctypes.c_int], ctypes.c_int),
     "pq_destroy": ([_VP], None),
     "pq_strerror": ([ctypes.c_int], ctypes.c_char_p),

@@ -1,6 +1,6 @@
 """Runtime services of the C ABI on the device: fault injection (the status
-propagates and the ctx stays usable), cancellation of the work queue, and
-autotuning decisions persisted to a file."""
+propagates and the ctx stays usable), cancellation of the work queue,
+autotuning decisions persisted to a file, and the device's reported peak."""
 import os
 
 import numpy as np
@@ -143,3 +143,15 @@ def test_autotune_decisions_persist_in_the_cache_file(pq, tmp_path, monkeypatch)
     assert [info2["waves_per_cu"], info2["chunks_per_wave"], info2["min_chunk"]] == \
         [info["waves_per_cu"], info["chunks_per_wave"], info["min_chunk"]]
     assert torch.equal(a, b)
+
+
+def test_device_peak_matches_the_runtime_properties(pq):
+    # the CU count and peak clock of torch's view of the same device, and the
+    # FP64 vector peak as CUs x clock x 128 flops
+    eng = pq.Engine(0)
+    d = eng.device_peak()
+    props = torch.cuda.get_device_properties(0)
+    assert d["cus"] == props.multi_processor_count
+    assert 500.0 <= d["clock_mhz"] <= 5000.0
+    assert d["fp64_vector_peak_tflops"] == pytest.approx(d["cus"] * d["clock_mhz"] * 1e6 * 128 / 1e12)
+    eng.close()
