@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 
 import oracle
+from tests.tolerance import assert_entries_close
 import workloads
 
 pytestmark = pytest.mark.gpu
@@ -86,9 +87,22 @@ def test_mesh_training_step_vs_oracle(ag):
     want_l = oracle.mesh_loss(U, S, pats)
     want_g = oracle.mesh_loss_grad(ang, CELLS, M, S, pats)
     assert abs(got_l - want_l) < 1e-12 * abs(want_l)
-    err = np.max(np.abs(got_g - want_g)) / np.max(np.abs(want_g))
+    # every angle's derivative is a sum over the patterns: each is compared
+    # by its own relative error, with a floor of the same 1e-10 times the
+    # sum of the patterns' contributions' magnitudes (where they cancel; 1.3
+    # to 250 times the derivative here), and for the 8 derivatives that are
+    # exactly 0 (cells whose action reaches only the columns of the empty
+    # input modes 8..11, which no permanent reads) the rounding of the mesh
+    # itself, 1e-14 of the largest
+    J = oracle.mesh_jacobian(ang, CELLS, M)
+    scale = np.zeros_like(want_g)
+    for T in pats:
+        p = oracle.perm_mult(U, S, T)
+        scale += np.abs(np.real(np.einsum("ab,qkab->qk", oracle.perm_grad(U, S, T), J) / p))
+    scale *= 2.0 / len(pats)
+    floor = 1e-10 * scale + 1e-14 * np.max(np.abs(want_g))
+    err = assert_entries_close(got_g, want_g, 1e-10, floor, "mesh gradient")
     print(f"mesh gradient vs oracle: max rel err {err:.2e}")
-    assert err < 1e-10
 
 
 def test_mesh_training_step_vs_finite_differences(ag):
