@@ -52,15 +52,16 @@ int plan_haf(const int32_t* reps, int d, HafPlan& p, const char** why) {
         if (r[i] < r[f]) f = i;
     int rho[kHafMaxModes];
     for (int i = 0; i < k; ++i) rho[i] = i == f ? r[i] : r[i] + 1;
-    std::vector<int> order(k);
+    int order[kHafMaxModes];
     for (int i = 0; i < k; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    std::stable_sort(order, order + k, [&](int a, int b) {
         if ((rho[a] == 1) != (rho[b] == 1)) return rho[a] == 1;
         return rho[a] > rho[b];
     });
-    std::vector<char> is_lane(k, 0);
+    char is_lane[kHafMaxModes] = {0};
     int lane_prod = 1, nl = 0, big = 0;
-    for (int i : order) {
+    for (int oi = 0; oi < k; ++oi) {
+        const int i = order[oi];
         if (rho[i] == 1) {
             is_lane[i] = 1;
             ++nl;
@@ -204,11 +205,12 @@ int check_reps(pq_ctx* ctx, const int32_t* reps, int d, int* N, const char* who)
     return PQ_OK;
 }
 
-// Plan one pattern: its descriptor (offsets left to the caller), plan and
-// step tables.  Trivial patterns (N = 0; odd N without loops) get
-// nchunks = 0 and their value.
+// Plan one pattern: its descriptor (offsets left to the caller), plan and,
+// when tab is not null, step tables.  Trivial patterns (N = 0; odd N without
+// loops) get nchunks = 0 and their value.  The loop factors (kHafFactors)
+// are the caller's: they depend only on N.
 int describe(pq_ctx* ctx, const int32_t* reps, int d, int N, bool loops, HafDesc& D, HafPlan& p,
-             std::vector<HafStep>& tab, const char* who) {
+             std::vector<HafStep>* tab, const char* who) {
     memset(&D, 0, sizeof(D));
     D.N = N;
     if (N == 0 || (!loops && (N & 1))) {
@@ -219,7 +221,7 @@ int describe(pq_ctx* ctx, const int32_t* reps, int d, int N, bool loops, HafDesc
     const char* why = "";
     int rc = plan_haf(reps, d, p, &why);
     if (rc) return ctx->fail(rc, "%s: %s", who, why);
-    haf_tables(p, tab);
+    if (tab) haf_tables(p, *tab);
     D.time_states = p.time_states;
     D.k = p.k;
     D.nl = p.nl;
@@ -235,7 +237,6 @@ int describe(pq_ctx* ctx, const int32_t* reps, int d, int N, bool loops, HafDesc
     double fact[kHafMaxN + 1];
     fact[0] = 1.0;
     for (int i = 1; i <= kHafMaxN; ++i) fact[i] = fact[i - 1] * (double)i;
-    if (loops) hermite_factors(N, D.hb);
     D.scale = ldexp(1.0, -(N - 1)) / fact[N / 2];
     D.nchunks = 1;
     return PQ_OK;
@@ -258,7 +259,7 @@ int pq_lhaf(pq_ctx* ctx, const pq_c128* A, int64_t lda, int32_t d, const pq_c128
     HafDesc D;
     HafPlan p;
     std::vector<HafStep> tab;
-    rc = describe(ctx, reps, d, N, loops, D, p, tab, "pq_lhaf");
+    rc = describe(ctx, reps, d, N, loops, D, p, &tab, "pq_lhaf");
     if (rc) return rc;
     if (D.nchunks == 0) return ctx->check(launch_fill((cplx*)out, nullptr, D.trivial, st), "fill");
 
@@ -323,6 +324,7 @@ int pq_lhaf(pq_ctx* ctx, const pq_c128* A, int64_t lda, int32_t d, const pq_c128
     a.tab = (const HafStep*)(ws + oT);
     a.partials = (double*)(ws + oP);
     a.waves = (uint32_t)waves;
+    if (loops) hermite_factors(N, a.hb);
     a.work = work;
     a.pk = pk;
     a.d = D;
@@ -362,11 +364,13 @@ int pq_lhaf_many(pq_ctx* ctx, const pq_c128* A, int64_t lda, int32_t d, const pq
     if (!out || (d > 0 && !reps)) return ctx->fail(PQ_EINVAL, "pq_lhaf_many: NULL reps or out");
     const bool loops = gamma != nullptr;
     std::vector<HafDesc> descs((size_t)npat);
-    std::vector<HafPlan> plans((size_t)npat);
+    HafPlan p;   // each pattern's plan, kept only while its descriptor is filled in
     std::vector<int32_t> modes;
     std::vector<int64_t> mode_off((size_t)npat, 0);
     std::vector<HafStep> tabs;
     std::map<std::vector<int>, int64_t> tab_of;    // inner radices -> table offset
+    std::vector<double> hbs;                       // loop factors per distinct N
+    std::map<int, int64_t> hb_of;                  // N -> offset in hbs
     bool any = false;
     int64_t ac = 0, gcn = 0;
     for (int q = 0; q < npat; ++q) {
@@ -374,20 +378,30 @@ int pq_lhaf_many(pq_ctx* ctx, const pq_c128* A, int64_t lda, int32_t d, const pq
         int N = 0;
         int rc = check_reps(ctx, r, d, &N, "pq_lhaf_many");
         if (rc) return rc;
-        std::vector<HafStep> tab;
-        rc = describe(ctx, r, d, N, loops, descs[q], plans[q], tab, "pq_lhaf_many");
+        rc = describe(ctx, r, d, N, loops, descs[q], p, nullptr, "pq_lhaf_many");
         if (rc) return rc;
         if (descs[q].nchunks == 0) continue;
         any = true;
-        const HafPlan& p = plans[q];
         HafDesc& D = descs[q];
+        // step tables depend only on the inner radices: built once per set
         std::vector<int> sig(p.rad + p.to, p.rad + p.to + p.n_in);
         auto it = tab_of.find(sig);
         if (it == tab_of.end()) {
+            std::vector<HafStep> tab;
+            haf_tables(p, tab);
             it = tab_of.emplace(sig, (int64_t)tabs.size()).first;
             tabs.insert(tabs.end(), tab.begin(), tab.end());
         }
         D.tab_off = it->second;
+        if (loops) {
+            auto ih = hb_of.find(N);
+            if (ih == hb_of.end()) {
+                ih = hb_of.emplace(N, (int64_t)hbs.size()).first;
+                hbs.resize(hbs.size() + kHafFactors, 0.0);
+                hermite_factors(N, hbs.data() + ih->second);
+            }
+            D.hb_off = ih->second;
+        }
         D.ac_off = ac;
         D.gc_off = gcn;
         ac += (int64_t)p.k * p.k;
@@ -438,6 +452,7 @@ int pq_lhaf_many(pq_ctx* ctx, const pq_c128* A, int64_t lda, int32_t d, const pq
     const size_t oM = cv.take(sizeof(int32_t) * sz(modes.size()));
     const size_t oMo = cv.take(sizeof(int64_t) * (size_t)npat);
     const size_t oT = cv.take(sizeof(HafStep) * sz(tabs.size()));
+    const size_t oH = cv.take(sizeof(double) * sz(hbs.size()));
     const size_t upload = cv.off;
     const size_t oA = cv.take(sizeof(cplx) * sz((size_t)ac));
     const size_t oG = cv.take(sizeof(cplx) * sz((size_t)gcn));
@@ -446,12 +461,14 @@ int pq_lhaf_many(pq_ctx* ctx, const pq_c128* A, int64_t lda, int32_t d, const pq
     if (!ws) return PQ_ENOMEM;
     char* stage = (char*)ctx->staging(upload);
     if (!stage) return PQ_ENOMEM;
-    memset(stage, 0, upload);
+    // every region is written below (the alignment gaps between them are
+    // never read)
     memcpy(stage + oD, descs.data(), sizeof(HafDesc) * descs.size());
     if (!chunks.empty()) memcpy(stage + oC, chunks.data(), sizeof(HafChunk) * chunks.size());
     if (!modes.empty()) memcpy(stage + oM, modes.data(), sizeof(int32_t) * modes.size());
     memcpy(stage + oMo, mode_off.data(), sizeof(int64_t) * mode_off.size());
     if (!tabs.empty()) memcpy(stage + oT, tabs.data(), sizeof(HafStep) * tabs.size());
+    if (!hbs.empty()) memcpy(stage + oH, hbs.data(), sizeof(double) * hbs.size());
     int rc = ctx->upload(ws, stage, upload, st);
     if (rc) return rc;
     const HafDesc* d_desc = (const HafDesc*)(ws + oD);
@@ -477,6 +494,7 @@ int pq_lhaf_many(pq_ctx* ctx, const pq_c128* A, int64_t lda, int32_t d, const pq
         }
         for (const auto& L : launches) {
             HafManyArgs ma;
+            ma.hb = (const double*)(ws + oH);
             ma.descs = d_desc;
             ma.chunks = (const HafChunk*)(ws + oC) + (size_t)std::get<2>(L) * kWavesPerBlock;
             ma.Ac = (const cplx*)(ws + oA);

@@ -21,7 +21,7 @@
 // P_N = (-2x)^{N/2} He_N(l / sqrt(-2x)) / N! (He_N the probabilists' Hermite
 // polynomial), and pairing its real roots +-h_k gives
 // P_N = l^(N mod 2) prod_k (x + l^2 / (2 h_k^2)) / floor(N/2)!; the factors
-// are multiplied four at a time in expanded form (HafDesc::hb).
+// are multiplied four at a time in expanded form (kHafFactors).
 //
 // Work split: lane digits (product of radices <= 64) are fixed per lane; a
 // register digit of radix 2 or 3 (if one is left) is evaluated at all its
@@ -81,12 +81,8 @@ struct HafDesc {
     int32_t N;
     int8_t rad[kHafMaxModes];         // radix per digit
     int8_t rep[kHafMaxModes];         // r per digit
-    // loops: P_N(x, l) = l^(N mod 2) prod_{k < N/2} (x + b_k l^2) / (N/2)!,
-    // b_k = 1 / (2 h_k^2) over the positive roots h_k of the probabilists'
-    // Hermite polynomial He_N; hb holds the factors grouped by four (then a
-    // pair, then a single) as elementary symmetric functions of their b's
-    double hb[kHafMaxN / 2];
     // batched path
+    int64_t hb_off;                   // into the loop-factor arena (HafManyArgs::hb), loops only
     int64_t ac_off;                   // complex elements into the Ac arena
     int64_t gc_off;                   // complex elements into the gc arena
     int64_t tab_off;                  // entries into the step-table arena
@@ -145,7 +141,15 @@ PQ_HD uint64_t haf_pack_columns(const HafPack& pk, uint64_t K) {
     return ng * (uint64_t)pk.per + (K - ng * grp);
 }
 
+// The loop polynomial's factors: P_N(x, l) = l^(N mod 2) prod_{k < N/2}
+// (x + b_k l^2) / (N/2)!, b_k = 1 / (2 h_k^2) over the positive roots h_k of
+// the probabilists' Hermite polynomial He_N, grouped by four (then a pair,
+// then a single) and stored as the elementary symmetric functions of each
+// group's b's: floor(N/2) values, which depend only on N.
+constexpr int kHafFactors = kHafMaxN / 2;
+
 struct HafArgs {
+    double hb[kHafFactors];           // loop factors (loops only)
     const cplx* Ac;                   // [k][k]
     const cplx* gc;                   // [k]
     const HafStep* tab;               // [2][M]: forward block, reflected block
@@ -165,6 +169,7 @@ struct HafChunk {
 };
 
 struct HafManyArgs {
+    const double* hb;                 // loop factors per distinct N, kHafFactors each (loops only)
     const HafDesc* descs;
     const HafChunk* chunks;           // 4 per workgroup
     const cplx* Ac;                   // arenas

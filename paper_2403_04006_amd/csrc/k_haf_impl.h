@@ -98,9 +98,9 @@ __device__ __forceinline__ double bperm_d(double v, int addr) {
 // slice of its second.  Returns the wavefront's double-double sum (in lane
 // 0).
 template <int NL, int RR, bool LOOP, bool PACK>
-__device__ __forceinline__ cdd haf_sweep(const HafDesc& a, const HafPack* pk, const cplx* Ac, const cplx* gc,
-                                         const HafStep* tabp, const cplx (*sTT)[kHafMaxTime], uint64_t start,
-                                         uint64_t count) {
+__device__ __forceinline__ cdd haf_sweep(const HafDesc& a, const HafPack* pk, const double* hb, const cplx* Ac,
+                                         const cplx* gc, const HafStep* tabp, const cplx (*sTT)[kHafMaxTime],
+                                         uint64_t start, uint64_t count) {
     constexpr int TO = NL + (RR > 1 ? 1 : 0);   // first time digit
     const int k = a.k, nt = a.nt;
     const int lane = (int)(threadIdx.x & 63);
@@ -198,11 +198,11 @@ __device__ __forceinline__ cdd haf_sweep(const HafDesc& a, const HafPack* pk, co
                 const cplx x2 = cmul(xd[d], xd[d]), xy = cmul(xd[d], y), y2 = cmul(y, y);
                 cplx pd{1.0, 0.0};
                 if (rem & 1) {
-                    const double b = a.hb[J - 1];
+                    const double b = hb[J - 1];
                     pd = cplx{__builtin_fma(b, y.re, xd[d].re), __builtin_fma(b, y.im, xd[d].im)};
                 }
                 if (rem >= 2) {
-                    const double e1 = a.hb[4 * nq], e2 = a.hb[4 * nq + 1];
+                    const double e1 = hb[4 * nq], e2 = hb[4 * nq + 1];
                     const cplx f{__builtin_fma(e2, y2.re, __builtin_fma(e1, xy.re, x2.re)),
                                  __builtin_fma(e2, y2.im, __builtin_fma(e1, xy.im, x2.im))};
                     pd = (rem & 1) ? cmul(pd, f) : f;
@@ -211,7 +211,7 @@ __device__ __forceinline__ cdd haf_sweep(const HafDesc& a, const HafPack* pk, co
                     const cplx m0 = cmul(x2, x2), m1 = cmul(x2, xy), m2 = cmul(xy, xy), m3 = cmul(xy, y2),
                                m4 = cmul(y2, y2);
                     auto quad = [&](int q) {
-                        const double* e = a.hb + 4 * q;
+                        const double* e = hb + 4 * q;
                         return cplx{__builtin_fma(e[3], m4.re, __builtin_fma(e[2], m3.re,
                                         __builtin_fma(e[1], m2.re, __builtin_fma(e[0], m1.re, m0.re)))),
                                     __builtin_fma(e[3], m4.im, __builtin_fma(e[2], m3.im,
@@ -395,7 +395,7 @@ __global__ __launch_bounds__(kBlock, (HafMinWaves<NL, LOOP>::value)) void haf_ke
     if (wave >= a.waves) return;
     uint64_t start, count;
     split_range(a.work, a.waves, wave, start, count);
-    const cdd v = haf_sweep<NL, RR, LOOP, PACK>(a.d, &a.pk, a.Ac, a.gc, a.tab, sTT, start, count);
+    const cdd v = haf_sweep<NL, RR, LOOP, PACK>(a.d, &a.pk, a.hb, a.Ac, a.gc, a.tab, sTT, start, count);
     if ((threadIdx.x & 63) == 0) store_partial(a.partials + 4 * (size_t)wave, v);
 }
 
@@ -412,8 +412,8 @@ __global__ __launch_bounds__(kBlock, (HafMinWaves<NL, LOOP>::value)) void haf_ma
     const HafChunk ch = a.chunks[(size_t)blockIdx.x * kWavesPerBlock + wv];
     cdd v{{0.0, 0.0}, {0.0, 0.0}};
     if (ch.count > 0)
-        v = haf_sweep<NL, RR, LOOP, false>(J, nullptr, Ac, a.gc + J.gc_off, a.tab + J.tab_off, sTT, ch.start,
-                                           ch.count);
+        v = haf_sweep<NL, RR, LOOP, false>(J, nullptr, a.hb + J.hb_off, Ac, a.gc + J.gc_off, a.tab + J.tab_off,
+                                           sTT, ch.start, ch.count);
     if ((threadIdx.x & 63) == 0) store_partial(a.partials + 4 * (size_t)ch.slot, v);
 }
 
