@@ -506,24 +506,32 @@ def main() -> int:
             "samples": 1000, "photons": 20, "modes": 400, "dilated_modes": 800, "transmissivity": 0.9,
             "kernel_ms": ms / 3, "wall_ms": tw * 1e3, "samples_per_s": 1000 / tw,
             "lost_fraction": float((drawn >= 400).double().mean())}
-        # every output amplitude of 10 photons in 16 modes (3268760 outputs)
+        # every output amplitude of 10 photons in 16 modes (3268760 outputs):
+        # the default form (the contraction at this size), then the sweep
         U16 = torch.from_numpy(workloads.haar(16, 1)).to(dev)
         S16 = [1] * 10 + [0] * 6
-        eng.perm_all_outputs(U16, S16)
-        torch.cuda.synchronize()
-        eng.profile(True)
-        eng.profile_read()
-        tw = time.perf_counter()
-        for _ in range(3):
-            _, amp16 = eng.perm_all_outputs(U16, S16)
-        torch.cuda.synchronize()
-        tw = (time.perf_counter() - tw) / 3
-        nl, ms = eng.profile_read()
-        eng.profile(False)
+        forms = {}
+        for form in ("auto", "never"):
+            eng.all_outputs_gemm(form)
+            eng.perm_all_outputs(U16, S16)
+            torch.cuda.synchronize()
+            eng.profile(True)
+            eng.profile_read()
+            tw = time.perf_counter()
+            for _ in range(3):
+                _, amp16 = eng.perm_all_outputs(U16, S16)
+            torch.cuda.synchronize()
+            tw = (time.perf_counter() - tw) / 3
+            nl, ms = eng.profile_read()
+            eng.profile(False)
+            forms[form] = (ms / 3, tw, abs(float(torch.sum(torch.abs(amp16) ** 2)) - 1.0))
+        eng.all_outputs_gemm("auto")
         batched["all_outputs_10_in_16"] = {
-            "outputs": pq.fock_count(16, 10), "sweep_ms": ms / 3, "wall_ms": tw * 1e3,
-            "outputs_per_s": pq.fock_count(16, 10) / tw,
-            "completeness_error": abs(float(torch.sum(torch.abs(amp16) ** 2)) - 1.0)}
+            "outputs": pq.fock_count(16, 10), "form": "contraction (rocBLAS zgemm per degree split)",
+            "kernel_ms": forms["auto"][0], "wall_ms": forms["auto"][1] * 1e3,
+            "outputs_per_s": pq.fock_count(16, 10) / forms["auto"][1],
+            "completeness_error": forms["auto"][2],
+            "sweep_form_kernel_ms": forms["never"][0], "sweep_form_completeness_error": forms["never"][2]}
         print(f"# batched: {batched}", file=sys.stderr, flush=True)
 
     # loop hafnians with the paper's (2, ..., 2) repetitions on 20 modes (40

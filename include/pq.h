@@ -84,7 +84,8 @@ int pq_device_peak(pq_ctx* ctx, int32_t* cus, int32_t* clock_khz, double* fp64_t
  * that file and appends new ones to it (one JSON object per line, keyed by
  * the device's architecture and CU count and the job list's shape);
  * PQ_FAULT_INJECT (pq_fault_inject); PQ_QUEUE (pq_queue_mode); PQ_WALK
- * (pq_walk_variant); PQ_LHAF_PACK (pq_lhaf_pack). */
+ * (pq_walk_variant); PQ_LHAF_PACK (pq_lhaf_pack); PQ_ALL_GEMM
+ * (pq_all_outputs_gemm). */
 int pq_create(pq_ctx** out, int hip_device);
 
 /* Destroy a context (NULL-safe).  Waits for the device before freeing. */
@@ -350,10 +351,36 @@ int pq_perm_grad(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m,
  * Limits (PQ_ERANGE): m <= 64; at most PQ_ALL_MAX_OUTPUTS outputs; at most
  * 2^20 Gray terms (prod over occupied input modes of (s_j + 1), halved on the
  * smallest).  n == 0 writes the single vacuum output perm = amp = 1.
+ * Two forms compute the same sum (pq_all_outputs_gemm picks between them):
+ *   - the sweep: one thread per output T, terms staged through LDS;
+ *   - the contraction: with the output modes split into halves a and b,
+ *     prod_i c_i^{t_i} = M_a(T_a) M_b(T_b) (the monomials of each half), so
+ *     for each degree k = |T_a| the outputs are one complex matrix product
+ *     over the terms of the weighted half-a monomials (one column per T_a of
+ *     degree k) and the half-b monomials (one per T_b of degree n - k),
+ *     computed by rocBLAS zgemm (the device's FP64 matrix cores; the blocks
+ *     of different k side by side on four streams of the ctx).  Its tables
+ *     (one complex per term and composition of at most n photons in either
+ *     half) take workspace of up to 1 GiB, its products as much as the
+ *     outputs.
+ * The two forms agree to rounding (another order of the sum over terms).
  */
 #define PQ_ALL_MAX_OUTPUTS (1ll << 31)
 int pq_perm_all_outputs(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m, const int32_t* S,
                         pq_c128* perm, pq_c128* amp, void* stream);
+
+/*
+ * pq_all_outputs_gemm -- which form pq_perm_all_outputs takes:
+ *   PQ_ALL_GEMM_AUTO (default): the contraction when its tables fit 1 GiB
+ *     and outputs x terms >= 2^29 (below that its fixed cost, about 0.2 ms
+ *     of launches, outweighs the sweep); the sweep otherwise;
+ *   PQ_ALL_GEMM_ALWAYS: the contraction whenever its tables fit;
+ *   PQ_ALL_GEMM_NEVER: the sweep.
+ * PQ_ALL_GEMM=auto|always|never in the environment sets it at pq_create.
+ * NULL ctx or another mode: PQ_EINVAL.
+ */
+enum { PQ_ALL_GEMM_AUTO = 0, PQ_ALL_GEMM_ALWAYS = 1, PQ_ALL_GEMM_NEVER = 2 };
+int pq_all_outputs_gemm(pq_ctx* ctx, int mode);
 
 /*
  * pq_sample_chain -- chain-rule boson sampling (Clifford & Clifford's

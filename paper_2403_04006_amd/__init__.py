@@ -300,6 +300,13 @@ class Engine:
         code = {"auto": 0, "always": 1, "never": 2}[mode]
         _check(self._lib.pq_queue_mode(self._ctx, code), self._ctx)
 
+    def all_outputs_gemm(self, mode: str = "auto"):
+        """Which form perm_all_outputs takes: "auto", "always" (the
+        contraction on rocBLAS zgemm whenever its tables fit) or "never" (the
+        sweep) (pq_all_outputs_gemm)."""
+        code = {"auto": 0, "always": 1, "never": 2}[mode]
+        _check(self._lib.pq_all_outputs_gemm(self._ctx, code), self._ctx)
+
     def lhaf_pack(self, mode: str = "auto"):
         """When the loop hafnian sweep fills idle lanes across Gray segments:
         "auto", "always" or "never" (pq_lhaf_pack)."""

@@ -105,6 +105,7 @@ _SIGNATURES = {
     "pq_walk_variant": ([_VP, ctypes.c_int, ctypes.c_int], ctypes.c_int),
     "pq_queue_mode": ([_VP, ctypes.c_int], ctypes.c_int),
     "pq_lhaf_pack": ([_VP, ctypes.c_int], ctypes.c_int),
+    "pq_all_outputs_gemm": ([_VP, ctypes.c_int], ctypes.c_int),
     "pq_autotune_last": ([_VP, _I32P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), _I32P],
                          ctypes.c_int),
 }

@@ -70,6 +70,10 @@ int pq_create(pq_ctx** out, int hip_device) {
         if (!strcmp(e, "always")) c->lhaf_pack = PQ_LHAF_PACK_ALWAYS;
         else if (!strcmp(e, "never")) c->lhaf_pack = PQ_LHAF_PACK_NEVER;
     }
+    if (const char* e = getenv("PQ_ALL_GEMM")) {
+        if (!strcmp(e, "always")) c->all_gemm = PQ_ALL_GEMM_ALWAYS;
+        else if (!strcmp(e, "never")) c->all_gemm = PQ_ALL_GEMM_NEVER;
+    }
     if (const char* e = getenv("PQ_WALK")) {
         int kd = 0, sw = 0;
         if (sscanf(e, "%d,%d", &kd, &sw) == 2 && kd >= 1 && kd <= 3 && (sw == 0 || sw == 1))
@@ -129,6 +133,7 @@ void pq_destroy(pq_ctx* ctx) {
     hipSetDevice(ctx->device);
     hipDeviceSynchronize();
     pq_release_many_cache(ctx);
+    pq_release_all_cache(ctx);
     ctx->release_all();
     if (prev >= 0) hipSetDevice(prev);
     delete ctx;

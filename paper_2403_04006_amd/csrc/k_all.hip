@@ -27,6 +27,7 @@ __global__ __launch_bounds__(kBlock) void all_sums_kernel(const AllSumsArgs a) {
         w *= digit_weight(j == 0 ? a.in_mult[j] : a.in_mult[j] + 1, dj);
     }
     a.csum[d * (uint64_t)a.m + i] = cplx{re, im};
+    if (a.csum_t) a.csum_t[(uint64_t)i * a.terms + d] = cplx{re, im};
     if (i == 0) a.w[d] = w;
 }
 
@@ -182,6 +183,80 @@ __global__ __launch_bounds__(kBlock, 4) void all_out_kernel(const AllOutArgs a) 
         const double nrm = a.norm_s / sqrt(tfact);
         a.amp[idx] = cplx{re * nrm, im * nrm};
     }
+}
+
+// Workgroup = (kBlock consecutive terms, a run of kAllTableRun compositions
+// of one half); each thread holds its term's column sums of that half (at
+// most Q modes) in registers and writes the run's monomials, times the
+// term's weight for half a.  The exponents are uniform over the workgroup,
+// and each composition's row is written in one sweep over the terms.
+template <int Q>
+__global__ __launch_bounds__(kBlock) void all_table_kernel(const AllTableArgs a) {
+    const uint32_t blk = blockIdx.x;
+    const uint64_t run = blk / a.term_blocks;
+    const uint32_t d = (blk - (uint32_t)run * a.term_blocks) * kBlock + threadIdx.x;
+    const bool half_a = (int64_t)run < a.runs_a;
+    const int64_t e0 = half_a ? (int64_t)run * kAllTableRun
+                              : a.entries_a + ((int64_t)run - a.runs_a) * kAllTableRun;
+    const int64_t end = half_a ? a.entries_a : a.entries;
+    const int64_t e1 = e0 + kAllTableRun < end ? e0 + kAllTableRun : end;
+    if (d >= a.terms || e0 >= e1) return;
+    const int lo = half_a ? 0 : a.ma, q = half_a ? a.ma : a.m - a.ma;
+    cplx c[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) c[i] = i < q ? a.csum_t[(uint64_t)(lo + i) * a.terms + d] : cplx{1.0, 0.0};
+    const double w0 = half_a ? a.w[d] : 1.0;
+    for (int64_t e = e0; e < e1; ++e) {
+        const uint8_t* x = a.exps + (uint64_t)e * (uint64_t)a.stride;
+        cplx p{w0, 0.0};
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            if (i < q) {
+                const int ti = (int)x[i];
+                for (int r = 0; r < ti; ++r) p = cmul(p, c[i]);
+            }
+        }
+        a.table[(uint64_t)e * a.terms + d] = p;
+    }
+}
+
+// One thread per product: block b, row i (T_a), column j (T_b) go to output
+// base[T_a] + j, scaled; the amplitude takes both halves' 1 / sqrt(T!).
+__global__ __launch_bounds__(kBlock) void all_scatter_kernel(const AllScatterArgs a) {
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= a.outputs) return;
+    int b = 0;
+    while (b + 1 < a.nblocks && a.off[b + 1] <= e) ++b;
+    const int64_t local = e - a.off[b];
+    const int64_t i = local / a.cols[b], j = local - i * a.cols[b];
+    const int64_t ia = a.ia0[b] + i, ib = a.ib0[b] + j;
+    const int64_t pos = a.base[ia] + j;
+    const cplx v = a.prod[e];
+    const cplx pv{v.re * a.scale, v.im * a.scale};
+    a.perm[pos] = pv;
+    if (a.amp) {
+        const double f = a.norm_s * a.fnorm[ia] * a.fnorm[ib];
+        a.amp[pos] = cplx{pv.re * f, pv.im * f};
+    }
+}
+
+hipError_t launch_all_table(const AllTableArgs& a, hipStream_t s) {
+    const int64_t runs_b = (a.entries - a.entries_a + kAllTableRun - 1) / kAllTableRun;
+    const uint64_t blocks = (uint64_t)(a.runs_a + runs_b) * a.term_blocks;
+    if (blocks == 0 || blocks > 0xffffffffull) return hipErrorInvalidValue;
+    const int q = a.ma > a.m - a.ma ? a.ma : a.m - a.ma;
+    const dim3 g((unsigned)blocks), b(kBlock);
+    if (q <= 8) hipLaunchKernelGGL(all_table_kernel<8>, g, b, 0, s, a);
+    else if (q <= 16) hipLaunchKernelGGL(all_table_kernel<16>, g, b, 0, s, a);
+    else if (q <= kAllMaxModes / 2) hipLaunchKernelGGL(all_table_kernel<kAllMaxModes / 2>, g, b, 0, s, a);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_all_scatter(const AllScatterArgs& a, hipStream_t s) {
+    const uint64_t blocks = ((uint64_t)a.outputs + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(all_scatter_kernel, dim3((unsigned)(blocks > 0 ? blocks : 1)), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_all_sums(const AllSumsArgs& a, hipStream_t s) {

@@ -72,6 +72,11 @@ struct pq_ctx {
     // when pq_lhaf fills idle lanes across Gray segments (pq_lhaf_pack,
     // PQ_LHAF_PACK)
     int lhaf_pack = PQ_LHAF_PACK_AUTO;
+    // when pq_perm_all_outputs takes its contraction form (pq_all_outputs_gemm,
+    // PQ_ALL_GEMM), and that form's state: rocBLAS handle, side streams and
+    // the last plan (all.cpp; created on first use)
+    int all_gemm = PQ_ALL_GEMM_AUTO;
+    void* all_cache = nullptr;
 
     // fault injection (pq_fault_inject, PQ_FAULT_INJECT): while set, every
     // device allocation (PQ_FAULT_ALLOC) or every launch check
@@ -124,6 +129,7 @@ struct pq_ctx {
 };
 
 void pq_release_many_cache(pq_ctx* ctx);
+void pq_release_all_cache(pq_ctx* ctx);
 // Validate pq_job descriptions (modes, multiplicities, photon counts, output
 // overlap) and append them to `key`.
 int pq_validate_jobs(pq_ctx* ctx, int32_t m, const pq_job* jobs, int32_t njobs, std::vector<int64_t>& key);

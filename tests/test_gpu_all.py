@@ -1,6 +1,7 @@
 """Every output amplitude of one input pattern (pq_perm_all_outputs) against
 the oracle's amplitude of each output, and completeness of the output
-distribution."""
+distribution, in both of its forms (the sweep, and the contraction on matrix
+products), and the two forms against each other at the benchmark size."""
 import numpy as np
 import pytest
 
@@ -13,11 +14,19 @@ torch = pytest.importorskip("torch")
 
 
 @pytest.fixture(scope="module")
-def eng():
+def engine():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     import paper_2403_04006_amd as pq
     return pq.Engine(0)
+
+
+@pytest.fixture(params=["never", "always"])
+def eng(engine, request):
+    # each test in the sweep form and in the contraction form
+    engine.all_outputs_gemm(request.param)
+    yield engine
+    engine.all_outputs_gemm("auto")
 
 
 def dev(U):
@@ -105,3 +114,71 @@ def test_argument_errors(eng):
     big = dev(workloads.haar(40, 0))
     with pytest.raises(pq.PqError):
         eng.perm_all_outputs(big, [1] * 20 + [0] * 20)    # C(59, 20) outputs
+
+
+def compositions_array(m, n):
+    """Every occupation vector with n photons on m modes, in ascending
+    lexicographic order (the output order), as rows of an array."""
+    from functools import lru_cache
+
+    @lru_cache(maxsize=None)
+    def rec(q, k):
+        if q == 1:
+            return np.array([[k]], np.uint8)
+        parts = []
+        for v in range(k + 1):
+            sub = rec(q - 1, k - v)
+            parts.append(np.hstack([np.full((len(sub), 1), v, np.uint8), sub]))
+        return np.vstack(parts)
+
+    return rec(m, n)
+
+
+def test_compositions_array_is_the_output_order():
+    # against the enumeration the other tests use, where that one is small
+    for m, n in ((4, 3), (5, 4), (3, 6)):
+        want = np.array(workloads.fock_outputs(m, n))
+        assert np.array_equal(compositions_array(m, n), want)
+
+
+def test_forms_agree_at_benchmark_size(engine):
+    # 10 photons in 16 modes (3,268,760 outputs, 512 terms): the contraction
+    # against the sweep on every output, each within 1e-10 of its own size or
+    # the rounding floor of its Gray-code sum, and a sample against the oracle
+    from tests.tolerance import FLOOR_C, EPS
+    import paper_2403_04006_amd as pq
+    m, n = 16, 10
+    U = workloads.haar(m, 1)
+    S = [1] * n + [0] * (m - n)
+    out = {}
+    for form in ("never", "always"):
+        engine.all_outputs_gemm(form)
+        perm, amp = engine.perm_all_outputs(dev(U), S)
+        out[form] = (perm.cpu().numpy(), amp.cpu().numpy())
+    engine.all_outputs_gemm("auto")
+    p_sweep, a_sweep = out["never"]
+    p_gemm, a_gemm = out["always"]
+    assert p_gemm.shape == (3268760,)
+    # every output's term scale: prod over input columns j of
+    # sqrt(sum_i t_i |U_ij|^2), the occupation vectors in output order
+    T = compositions_array(m, n).astype(np.float64)
+    assert T.shape == (3268760, m)
+    col = T @ (np.abs(U[:, :n]) ** 2)
+    scale = np.prod(np.sqrt(col), axis=1)
+    floor = FLOOR_C * (n + 1) * EPS * scale
+    err = np.abs(p_gemm - p_sweep)
+    assert np.all(err <= np.maximum(1e-10 * np.abs(p_sweep), floor)), float(np.max(err / np.maximum(1e-10 * np.abs(p_sweep), floor)))
+    assert abs(np.sum(np.abs(a_gemm) ** 2) - 1.0) < 1e-11
+    rng = np.random.default_rng(5)
+    for r in rng.choice(3268760, 16, replace=False):
+        Tr = np.array(pq.fock_unrank(m, n, int(r)), np.int32)
+        rp = oracle.perm_mult(U, np.array(S, np.int32), Tr)
+        assert abs(p_gemm[r] - rp) <= max(1e-10 * abs(rp), floor[r]), (int(r), p_gemm[r], rp)
+
+
+def test_form_mode_rejects_unknown_modes(engine):
+    from paper_2403_04006_amd import _lib
+    assert engine._lib.pq_all_outputs_gemm(engine._ctx, 3) == _lib.PQ_EINVAL
+    with pytest.raises(KeyError):
+        engine.all_outputs_gemm("sometimes")
+    engine.all_outputs_gemm("auto")

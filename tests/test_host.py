@@ -62,6 +62,7 @@ def test_null_arguments_are_rejected_without_a_device():
     assert lib.pq_walk_variant(None, 1, 0) == _lib.PQ_EINVAL
     assert lib.pq_queue_mode(None, 0) == _lib.PQ_EINVAL
     assert lib.pq_lhaf_pack(None, 1) == _lib.PQ_EINVAL
+    assert lib.pq_all_outputs_gemm(None, 1) == _lib.PQ_EINVAL
     assert lib.pq_device_peak(None, None, None, None) == _lib.PQ_EINVAL
     lib.pq_destroy(None)
     assert lib.pq_last_error(None) == b""
