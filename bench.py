@@ -33,10 +33,10 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CUs x 2.4 GHz x 128 FP64 flop/clk/CU
 SWEEP_TRAFFIC = {
     "sources": ["k_glynn_impl.h", "k_glynn_p2.hip", "sweep_common.h", "device.h", "pq_common.h",
                 "runtime.cpp", "runtime.h", "plan.cpp", "plan.h", "api.cpp", "k_misc.hip"],
-    "sha256": "b3a8aeb3c0cdddfd3dc12910fa6b6af6b7376a38533d0ab662f82078ec0caf56",
+    "sha256": "0c5b4697b83d5de0ec3ae9273722df5cab2f72b292f205a721a0ae1cd5a62f81",
     "n": 30,
     "fetch_kib": 245.2, "write_kib": 24.0,
-    "fetch_factor": 262144.0 / 131088.4, "write_factor": 1.0,
+    "fetch_factor": 262144.0 / 131093.2, "write_factor": 1.0,
 }
 
 
