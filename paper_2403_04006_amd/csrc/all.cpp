@@ -416,10 +416,26 @@ int pq_perm_all_outputs(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m, c
         for (int oi = 0; oi < sc.nblocks; ++oi) {
             const int b = order[(size_t)oi];
             const int lane = oi % (nside + 1);
-            if (rocblas_set_stream(h, lane == 0 ? st : cache->side[lane - 1]) != rocblas_status_success)
-                return ctx->fail(PQ_EDEVICE, "pq_perm_all_outputs: rocblas_set_stream failed");
+            hipStream_t bst = lane == 0 ? st : cache->side[lane - 1];
             const int64_t size = (b + 1 < sc.nblocks ? sc.off[b + 1] : g.products) - sc.off[b];
             const int64_t cols = sc.cols[b], nrow = size / cols;
+            if (nrow <= kAllThinMax || cols <= kAllThinMax) {
+                AllThinArgs th;
+                th.table = tab;
+                th.terms = (uint32_t)terms;
+                th.long_is_col = nrow <= cols ? 1 : 0;
+                th.long0 = th.long_is_col ? sc.ib0[b] : sc.ia0[b];
+                th.short0 = th.long_is_col ? sc.ia0[b] : sc.ib0[b];
+                th.nlong = th.long_is_col ? cols : nrow;
+                th.nshort = (int32_t)(th.long_is_col ? nrow : cols);
+                th.cols = cols;
+                th.prod = prod + sc.off[b];
+                rc = ctx->check(launch_all_thin(th, bst), "all-outputs thin block");
+                if (rc) return rc;
+                continue;
+            }
+            if (rocblas_set_stream(h, bst) != rocblas_status_success)
+                return ctx->fail(PQ_EDEVICE, "pq_perm_all_outputs: rocblas_set_stream failed");
             // block b, column-major cols x nrow: entry (j, i) = sum over delta
             // of M_b(delta, T_b = j) [w M_a](delta, T_a = i), i.e. the complex
             // row-major block [i][j]

@@ -107,6 +107,23 @@ struct AllScatterArgs {
     cplx* amp;                   // may be null
 };
 
+// A thin block (at most kAllThinMax T_a's or T_b's): one wavefront per
+// entry of the long side, its lanes splitting the terms, the products
+// written in the block's layout.  A 64 x 64 matrix-core tile would compute up
+// to 64 times the needed products there.
+constexpr int kAllThinMax = 8;
+struct AllThinArgs {
+    const cplx* table;           // [entries][terms]
+    uint32_t terms;
+    int64_t long0, short0;       // first table row of the long and of the short side
+    int64_t nlong;
+    int32_t nshort;              // 1..kAllThinMax
+    int32_t long_is_col;         // 1: long side = T_b (product [v][u]); 0: T_a (product [u][v])
+    int64_t cols;                // T_b's per row of the block
+    cplx* prod;                  // the block's first product
+};
+hipError_t launch_all_thin(const AllThinArgs& a, hipStream_t s);
+
 hipError_t launch_all_table(const AllTableArgs& a, hipStream_t s);
 hipError_t launch_all_scatter(const AllScatterArgs& a, hipStream_t s);
 
