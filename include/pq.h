@@ -359,7 +359,8 @@ int pq_perm_grad(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m,
  *     over the terms of the weighted half-a monomials (one column per T_a of
  *     degree k) and the half-b monomials (one per T_b of degree n - k),
  *     computed by rocBLAS zgemm (the device's FP64 matrix cores; the blocks
- *     of different k side by side on four streams of the ctx).  Its tables
+ *     of different k side by side on four streams of the ctx; blocks with at
+ *     most 8 compositions on one side by a kernel of their own).  Its tables
  *     (one complex per term and composition of at most n photons in either
  *     half) take workspace of up to 1 GiB, its products as much as the
  *     outputs.
