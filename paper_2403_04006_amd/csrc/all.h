@@ -107,8 +107,8 @@ struct AllScatterArgs {
     cplx* amp;                   // may be null
 };
 
-// A thin block (at most kAllThinMax T_a's or T_b's): one wavefront per
-// entry of the long side, its lanes splitting the terms, the products
+// A thin block (at most kAllThinMax T_a's or T_b's): one wavefront per four
+// entries of the long side, its lanes splitting the terms, the products
 // written in the block's layout.  A 64 x 64 matrix-core tile would compute up
 // to 64 times the needed products there.
 constexpr int kAllThinMax = 8;

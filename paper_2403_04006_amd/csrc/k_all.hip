@@ -240,42 +240,58 @@ __global__ __launch_bounds__(kBlock) void all_scatter_kernel(const AllScatterArg
     }
 }
 
-// A thin block (AllThinArgs): wavefront u takes long-side entry u and all
-// nshort <= S entries of the short side.  Its lanes split the terms, so
-// every load of a row is one contiguous sweep; the lane sums meet in a
-// butterfly at the end.
+// A thin block (AllThinArgs): a wavefront takes kAllThinRun consecutive
+// long-side entries and all nshort <= S entries of the short side, so each
+// short-side value it loads serves that many products.  Its lanes split the
+// terms, so every load of a row is one contiguous sweep; the lane sums meet
+// in a butterfly at the end.
+constexpr int kAllThinRun = 4;
 template <int S>
 __global__ __launch_bounds__(kBlock) void all_thin_kernel(const AllThinArgs a) {
     const int lane = (int)(threadIdx.x & 63);
-    const int64_t u = (int64_t)blockIdx.x * kWavesPerBlock + (int64_t)(threadIdx.x >> 6);
-    if (u >= a.nlong) return;   // whole wavefronts
-    const cplx* lrow = a.table + (uint64_t)(a.long0 + u) * a.terms;
+    const int64_t u0 = ((int64_t)blockIdx.x * kWavesPerBlock + (int64_t)(threadIdx.x >> 6)) * kAllThinRun;
+    if (u0 >= a.nlong) return;   // whole wavefronts
+    const int nu = a.nlong - u0 < kAllThinRun ? (int)(a.nlong - u0) : kAllThinRun;
+    const cplx* lrow = a.table + (uint64_t)(a.long0 + u0) * a.terms;
     const cplx* srow = a.table + (uint64_t)a.short0 * a.terms;
-    cplx acc[S];
+    cplx acc[kAllThinRun][S];
 #pragma unroll
-    for (int v = 0; v < S; ++v) acc[v] = cplx{0.0, 0.0};
+    for (int r = 0; r < kAllThinRun; ++r)
+#pragma unroll
+        for (int v = 0; v < S; ++v) acc[r][v] = cplx{0.0, 0.0};
     for (uint32_t d = (uint32_t)lane; d < a.terms; d += 64) {
-        const cplx x = lrow[d];
+        cplx x[kAllThinRun];
+#pragma unroll
+        for (int r = 0; r < kAllThinRun; ++r)
+            x[r] = r < nu ? lrow[(uint64_t)r * a.terms + d] : cplx{0.0, 0.0};
 #pragma unroll
         for (int v = 0; v < S; ++v) {
             if (v < a.nshort) {
                 const cplx y = srow[(uint64_t)v * a.terms + d];
-                acc[v].re = __builtin_fma(x.re, y.re, __builtin_fma(-x.im, y.im, acc[v].re));
-                acc[v].im = __builtin_fma(x.re, y.im, __builtin_fma(x.im, y.re, acc[v].im));
+#pragma unroll
+                for (int r = 0; r < kAllThinRun; ++r) {
+                    acc[r][v].re = __builtin_fma(x[r].re, y.re, __builtin_fma(-x[r].im, y.im, acc[r][v].re));
+                    acc[r][v].im = __builtin_fma(x[r].re, y.im, __builtin_fma(x[r].im, y.re, acc[r][v].im));
+                }
             }
         }
     }
 #pragma unroll
-    for (int v = 0; v < S; ++v) {
-        if (v < a.nshort) {
+    for (int r = 0; r < kAllThinRun; ++r) {
+        if (r >= nu) break;
 #pragma unroll
-            for (int m = 32; m >= 1; m >>= 1) {
-                acc[v].re += shfl_xor_d(acc[v].re, m);
-                acc[v].im += shfl_xor_d(acc[v].im, m);
-            }
-            if (lane == v) {
-                const int64_t idx = a.long_is_col ? (int64_t)v * a.cols + u : u * a.cols + v;
-                a.prod[idx] = acc[v];
+        for (int v = 0; v < S; ++v) {
+            if (v < a.nshort) {
+#pragma unroll
+                for (int m = 32; m >= 1; m >>= 1) {
+                    acc[r][v].re += shfl_xor_d(acc[r][v].re, m);
+                    acc[r][v].im += shfl_xor_d(acc[r][v].im, m);
+                }
+                if (lane == v) {
+                    const int64_t u = u0 + r;
+                    const int64_t idx = a.long_is_col ? (int64_t)v * a.cols + u : u * a.cols + v;
+                    a.prod[idx] = acc[r][v];
+                }
             }
         }
     }
@@ -283,7 +299,8 @@ __global__ __launch_bounds__(kBlock) void all_thin_kernel(const AllThinArgs a) {
 
 hipError_t launch_all_thin(const AllThinArgs& a, hipStream_t s) {
     if (a.nlong <= 0 || a.nshort < 1 || a.nshort > kAllThinMax) return hipErrorInvalidValue;
-    const uint64_t blocks = ((uint64_t)a.nlong + kWavesPerBlock - 1) / kWavesPerBlock;
+    const uint64_t waves = ((uint64_t)a.nlong + kAllThinRun - 1) / kAllThinRun;
+    const uint64_t blocks = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
     const dim3 g((unsigned)blocks), b(kBlock);
     if (a.nshort == 1) hipLaunchKernelGGL(all_thin_kernel<1>, g, b, 0, s, a);
     else if (a.nshort <= 2) hipLaunchKernelGGL(all_thin_kernel<2>, g, b, 0, s, a);
