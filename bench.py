@@ -33,7 +33,7 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CUs x 2.4 GHz x 128 FP64 flop/clk/CU
 SWEEP_TRAFFIC = {
     "sources": ["k_glynn_impl.h", "k_glynn_p2.hip", "sweep_common.h", "device.h", "pq_common.h",
                 "runtime.cpp", "runtime.h", "plan.cpp", "plan.h", "api.cpp", "k_misc.hip"],
-    "sha256": "0c5b4697b83d5de0ec3ae9273722df5cab2f72b292f205a721a0ae1cd5a62f81",
+    "sha256": "42c1c6129c3ed2a895a864ac856e6327d336c3fbde9989190ec8db426e348406",
     "n": 30,
     "fetch_kib": 245.2, "write_kib": 24.0,
     "fetch_factor": 262144.0 / 131093.2, "write_factor": 1.0,
@@ -379,7 +379,7 @@ def main() -> int:
             "samples": 1000, "jobs": len(jl), "sweep_ms": ms / 3, "wall_ms": tw * 1e3,
             "samples_per_s": 1000 / tw}
         # the same two workloads with chunk sizes picked by the autotuner: the
-        # first call times 11 candidate policies, then 3 calls of the kept plan
+        # first call times 14 candidate policies, then 3 calls of the kept plan
         teng = pq.Engine(0)
         teng.autotune(True)
         tuned_runs = {}

@@ -253,15 +253,17 @@ int pq_perm_many(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m,
  * boson-sampling run in one statically scheduled launch per column class).
  * A plan aims at num_cu * waves_per_cu * chunks_per_wave chunks per class,
  * none shorter than min_chunk Gray time states; the default policy is
- * (16, 4, 64).
+ * (64, 8, 256): fine chunks for long uneven jobs (a short tail), and short
+ * jobs kept whole.  It applies to pq_perm_batched as well, so the two calls
+ * give the same bits on the same job list.
  *
  * pq_autotune_enable -- on (nonzero): the first pq_perm_many call on a job
  * list whose shape (m, and for every job kind and padded column count the
  * number of jobs and of Gray terms, each rounded to half an octave) has no
  * recorded policy plans and runs the job
- * list under each of 13 candidate policies (the default first), timing the
+ * list under each of 14 candidate policies (the default first), timing the
  * sweep kernels with HIP events (best of two runs each), keeps the fastest
- * plan and records its policy.  That call therefore runs the jobs about 22
+ * plan and records its policy.  That call therefore runs the jobs about 28
  * times and synchronizes the stream; its outputs are those of the kept plan.
  * Later job lists of the same shape are planned with the recorded policy.
  * Results differ between policies only by the order of the double-double

@@ -31,9 +31,13 @@ namespace {
 constexpr uint64_t kWalkMinChunk = 32;
 // chunk policies the autotuner times (the first is the default)
 constexpr ChunkPolicy kTuneCandidates[] = {
-    {16, 4, 64}, {4, 2, 64}, {8, 1, 64}, {8, 2, 64}, {8, 4, 64}, {16, 2, 64},
+    {64, 8, 256}, {16, 4, 64}, {4, 2, 64}, {8, 1, 64}, {8, 2, 64}, {8, 4, 64}, {16, 2, 64},
     {16, 8, 64}, {32, 4, 64}, {32, 8, 64}, {8, 2, 256}, {16, 4, 256}, {32, 8, 32}, {64, 8, 32},
 };
+static_assert(kTuneCandidates[0].waves_per_cu == ChunkPolicy().waves_per_cu &&
+                  kTuneCandidates[0].chunks_per_wave == ChunkPolicy().chunks_per_wave &&
+                  kTuneCandidates[0].min_chunk == ChunkPolicy().min_chunk,
+              "the first candidate is the default policy");
 constexpr int kMaxManyEntries = 4;
 struct ManyClass;
 int walk_occupancy(pq_ctx* ctx, const ManyClass& C);
@@ -1000,6 +1004,13 @@ int pq_autotune_enable(pq_ctx* ctx, int on) {
 int pq_autotune_last(pq_ctx* ctx, int32_t policy[3], double* best_ms, double* default_ms, int32_t* candidates) {
     if (!ctx || !policy || !best_ms || !default_ms || !candidates) return PQ_EINVAL;
     const TuneRecord& t = ctx->last_tune;
+    if (t.sig == 0 && t.candidates == 0 && t.best_ms == 0.0) {
+        // no decision yet
+        policy[0] = policy[1] = policy[2] = 0;
+        *best_ms = *default_ms = 0.0;
+        *candidates = 0;
+        return PQ_OK;
+    }
     policy[0] = t.policy.waves_per_cu;
     policy[1] = t.policy.chunks_per_wave;
     policy[2] = t.policy.min_chunk;

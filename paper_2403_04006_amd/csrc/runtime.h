@@ -15,11 +15,13 @@
 namespace pq {
 // How the forward and extend-row classes of a many-pattern plan are cut into
 // chunks (one wavefront each): aim at num_cu * waves_per_cu * chunks_per_wave
-// chunks per class, none shorter than min_chunk time states.
+// chunks per class, none shorter than min_chunk time states.  The default
+// cuts long uneven jobs finely (a short tail of the longest chunks) while the
+// minimum keeps the many short jobs of a sampling run in few chunks.
 struct ChunkPolicy {
-    int32_t waves_per_cu = 16;
-    int32_t chunks_per_wave = 4;
-    int32_t min_chunk = 64;
+    int32_t waves_per_cu = 64;
+    int32_t chunks_per_wave = 8;
+    int32_t min_chunk = 256;
 };
 // One autotuning decision: the policy kept for a job-list shape, its sweep
 // time, the default policy's, and how many candidates were timed (0: taken

@@ -131,7 +131,7 @@ def test_autotune_decisions_persist_in_the_cache_file(pq, tmp_path, monkeypatch)
     a, _ = first.perm_many(U, jobs, n_out=off, with_amp=False)
     info = first.autotune_last()
     first.close()
-    assert info["candidates"] == 13
+    assert info["candidates"] == 14
     lines = path.read_text().strip().splitlines()
     assert len(lines) == 1 and '"kind": "many"' in lines[0] and '"device": "gfx' in lines[0]
     # a new ctx (as a new process would) reads the decision: no timing runs
