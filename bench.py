@@ -27,16 +27,16 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CUs x 2.4 GHz x 128 FP64 flop/clk/CU
 # HBM traffic of one n=30 sweep launch, from two rocprofv3 --pmc passes
 # (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) over this script with
 # --calib-copy-mib 256; each scaled by what the same counter read for a plain
-# 256 MiB device-to-device copy in the same run (FETCH 131092.9 KiB, WRITE
+# 256 MiB device-to-device copy in the same run (FETCH 131089.2 KiB, WRITE
 # 262144 KiB, against 262144 KiB moved each way).  Valid only for the sources
 # it was measured on: the hash covers every file that shapes the launch.
 SWEEP_TRAFFIC = {
     "sources": ["k_glynn_impl.h", "k_glynn_p2.hip", "sweep_common.h", "device.h", "pq_common.h",
                 "runtime.cpp", "runtime.h", "plan.cpp", "plan.h", "api.cpp", "k_misc.hip"],
-    "sha256": "42c1c6129c3ed2a895a864ac856e6327d336c3fbde9989190ec8db426e348406",
+    "sha256": "fe87c4d525305e57717c363e6e347b9a607fe564f382862f252949e1c10c14cc",
     "n": 30,
-    "fetch_kib": 245.2, "write_kib": 24.0,
-    "fetch_factor": 262144.0 / 131093.2, "write_factor": 1.0,
+    "fetch_kib": 242.2, "write_kib": 48.0,
+    "fetch_factor": 262144.0 / 131089.2, "write_factor": 1.0,
 }
 
 

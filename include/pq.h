@@ -129,6 +129,9 @@ const char* pq_last_error(const pq_ctx* ctx);
  *   perm   device, 1 complex, may be NULL: perm(U_{T,S}).
  *   amp    device, 1 complex, may be NULL: perm / sqrt(prod S! prod T!).
  * U must not be NULL when m > 0; S and T must not be NULL.
+ * The sweep splits its Gray range evenly over two rounds of the resident
+ * wavefronts (each at least 32 time states); with autotuning on
+ * (pq_autotune_enable) the launch shape follows the autotuner instead.
  */
 int pq_perm(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m,
             const int32_t* S, const int32_t* T,
@@ -138,15 +141,17 @@ int pq_perm(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m,
  * pq_perm_noalloc -- pq_perm for callers that cannot allocate device memory:
  * code under HIP graph capture, tight serving loops, and harnesses that
  * forbid allocation.  Same arguments, planning, errors and results as
- * pq_perm (the same kernels in the same launch geometry), but the launch
+ * pq_perm (the same kernels in the same launch geometry: the default, or
+ * the autotuner's recorded decision for the shape), but the launch
  * sequence's scratch (compact matrix, +-2B rows, step tables, workgroup
  * partials) is a static device array of PQ_NOALLOC_SCRATCH_BYTES per GPU,
  * resolved by pq_create; the call itself allocates nothing (no hipMalloc,
  * hipFree or allocating library routine) and records no profiling events.
  *   - A permanent whose launch needs more scratch than that returns
- *     PQ_ERANGE (outputs untouched); pq_perm handles it.  Every binary
- *     (collision-free) permanent up to n = 48 fits; large mixed-radix ones
- *     with 4096-state step tables and 40 distinct columns may not.
+ *     PQ_ERANGE (outputs untouched); pq_perm handles it.  Under the default
+ *     launch shape every binary (collision-free) permanent up to n = 48
+ *     fits; large mixed-radix ones with 4096-state step tables and 40
+ *     distinct columns may not, nor may shapes the autotuner gave 4 rounds.
  *   - Every call on one GPU, from every ctx, shares that GPU's array: calls
  *     whose GPU work overlaps (other streams, other ctxs, other threads) race
  *     and give wrong results.  Calls ordered on one stream are safe; nothing
@@ -268,11 +273,21 @@ int pq_perm_many(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m,
  * Later job lists of the same shape are planned with the recorded policy.
  * Results differ between policies only by the order of the double-double
  * partial sums.  Off (0, the default): the default policy.
+ *   The same switch tunes pq_perm's launch shape: the first call on a plan
+ * shape (kernel kind, column count, digit radices and column powers: n and
+ * the multiplicity class) with no recorded decision runs the whole launch
+ * sequence under 2, 1 and 4 rounds of the resident wavefronts (the default
+ * first, best of two runs each, timed with HIP events around the sequence:
+ * 6 runs, and the stream is synchronized), keeps the fastest, records it,
+ * and then runs once more with it.  Later calls of that shape reuse the
+ * record; pq_perm_noalloc follows a recorded decision but never times.
+ * PQ_AUTOTUNE_CACHE persists these decisions too (kind "perm").
  *
  * pq_autotune_last -- the last decision: policy = {waves_per_cu,
- * chunks_per_wave, min_chunk}, the kept plan's sweep time and the default
- * policy's (ms), and the number of candidates timed (0: the policy came
- * from the record).  All zero before any tuning.  NULL arguments: PQ_EINVAL.
+ * chunks_per_wave, min_chunk} (for pq_perm: {wavefronts per CU, 1, 32}),
+ * the kept plan's or shape's time and the default's (ms), and the number of
+ * candidates timed (0: the decision came from the record).  All zero before
+ * any tuning.  NULL arguments: PQ_EINVAL.
  */
 /*
  * pq_graph_enable -- on (nonzero): pq_perm_many captures its launch sequence

@@ -68,7 +68,7 @@ int pq_perm_noalloc(pq_ctx* ctx, const pq_c128* U, int64_t ldu, int32_t m,
     }
     char* ws = scratch_of(ctx->device);
     if (!ws) return ctx->fail(PQ_EDEVICE, "pq_perm_noalloc: the static scratch of device %d was not resolved", ctx->device);
-    const SingleLayout L = single_layout(ctx, p);
+    const SingleLayout L = single_layout(ctx, p, single_waves_per_cu(ctx, p));
     if (L.bytes > kNoAllocScratchBytes)
         return ctx->fail(PQ_ERANGE, "pq_perm_noalloc: this permanent needs %zu bytes of scratch, more than the %zu "
                          "bytes of the static buffer (use pq_perm)", L.bytes, kNoAllocScratchBytes);

@@ -208,16 +208,52 @@ int sweep_kind(const Plan& p) {
     return ps.general ? kSweepMixGeneral : kSweepMix;
 }
 
-Geometry sweep_geometry(pq_ctx* ctx, const Plan& p) {
+int sweep_waves_per_cu(pq_ctx* ctx, const Plan& p, int rounds) {
+    return ctx->occupancy(sweep_kind(p), p.nc) * kWavesPerBlock * rounds;
+}
+
+Geometry sweep_geometry(pq_ctx* ctx, const Plan& p, int waves_per_cu) {
     Geometry g;
-    const int occ = ctx->occupancy(sweep_kind(p), p.nc);
-    const uint64_t full = (uint64_t)occ * (uint64_t)ctx->num_cu * kWavesPerBlock;
+    const uint64_t full = (uint64_t)(waves_per_cu > 0 ? waves_per_cu : 1) * (uint64_t)ctx->num_cu;
     uint64_t waves = (p.time_states + kMinStepsPerWave - 1) / kMinStepsPerWave;
     if (waves > full) waves = full;
     if (waves < 1) waves = 1;
     g.waves = (uint32_t)waves;
     g.grid = (int)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
     return g;
+}
+
+uint64_t single_sig(const Plan& p) {
+    // seeded apart from the job-list shape signatures, which share the
+    // records and the cache file
+    uint64_t h = 0x70657266ull * 1099511628211ull;
+    auto mix = [&](uint64_t x) {
+        h ^= x;
+        h *= 1099511628211ull;
+        h ^= h >> 29;
+    };
+    mix((uint64_t)sweep_kind(p));
+    mix((uint64_t)p.r);
+    mix((uint64_t)p.nc);
+    mix((uint64_t)p.n_lane);
+    for (int k = 0; k < p.n_lane; ++k) mix((uint64_t)p.lane_radix[k]);
+    mix((uint64_t)p.n_time);
+    for (int k = 0; k < p.n_time; ++k) mix((uint64_t)p.time_radix[k]);
+    mix((uint64_t)p.n_inner);
+    for (int j = 0; j < p.nc; ++j) mix((uint64_t)p.col_kap[j]);
+    return h;
+}
+
+static const TuneRecord* recorded(pq_ctx* ctx, uint64_t sig) {
+    for (const TuneRecord& t : ctx->tuned)
+        if (t.sig == sig) return &t;
+    return nullptr;
+}
+
+int single_waves_per_cu(pq_ctx* ctx, const Plan& p) {
+    if (ctx->autotune)
+        if (const TuneRecord* t = recorded(ctx, single_sig(p))) return t->policy.waves_per_cu;
+    return sweep_waves_per_cu(ctx, p);
 }
 
 int timed_sweep(pq_ctx* ctx, int kind, int nc, const GlynnArgs& a, int grid, hipStream_t st) {
@@ -239,9 +275,9 @@ int timed_sweep(pq_ctx* ctx, int kind, int nc, const GlynnArgs& a, int grid, hip
     return PQ_OK;
 }
 
-SingleLayout single_layout(pq_ctx* ctx, const Plan& p) {
+SingleLayout single_layout(pq_ctx* ctx, const Plan& p, int waves_per_cu) {
     SingleLayout L;
-    L.geo = sweep_geometry(ctx, p);
+    L.geo = sweep_geometry(ctx, p, waves_per_cu);
     const int r = p.r, nc = p.nc;
     const size_t ntab = p.binary ? 0 : (size_t)p.m_inner;
     Carve cv;
@@ -319,9 +355,73 @@ int run_single_at(pq_ctx* ctx, const Plan& p, const SingleLayout& L, char* ws, c
     return ctx->check(launch_final(fa, st), "final");
 }
 
+// Time the whole launch sequence of a plan under 2, 1 and 4 rounds of the
+// resident wavefronts (the default first; best of two runs each), record the
+// fastest for the plan's shape, and return its wavefronts per CU.  The runs
+// write perm and amp; the caller's run afterwards writes them again.
+static int tune_single(pq_ctx* ctx, const Plan& p, const cplx* U, int64_t ldu, cplx* perm, cplx* amp,
+                       hipStream_t st, int& wpc) {
+    TuneRecord rec;
+    rec.sig = single_sig(p);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) hipEventDestroy(e0);
+        return ctx->fail(PQ_EDEVICE, "tune: hipEventCreate failed");
+    }
+    int rc = PQ_OK;
+    double best = -1.0;
+    for (int rounds : {kSweepRounds, 1, 4}) {
+        const int w = sweep_waves_per_cu(ctx, p, rounds);
+        const SingleLayout L = single_layout(ctx, p, w);
+        char* ws = (char*)ctx->workspace(L.bytes);
+        if (!ws) {
+            rc = PQ_ENOMEM;
+            break;
+        }
+        double ms = -1.0;
+        for (int rep = 0; rep < 2 && !rc; ++rep) {
+            rc = ctx->check(hipEventRecord(e0, st), "tune: record");
+            if (!rc) rc = run_single_at(ctx, p, L, ws, U, ldu, perm, amp, st, false);
+            if (!rc) rc = ctx->check(hipEventRecord(e1, st), "tune: record");
+            if (!rc) rc = ctx->check(hipEventSynchronize(e1), "tune: synchronize");
+            float f = 0.0f;
+            if (!rc) rc = ctx->check(hipEventElapsedTime(&f, e0, e1), "tune: elapsed");
+            if (!rc && (ms < 0.0 || f < ms)) ms = f;
+        }
+        if (rc) break;
+        ++rec.candidates;
+        if (rec.candidates == 1) rec.default_ms = ms;
+        if (best < 0.0 || ms < best) {
+            best = ms;
+            rec.policy.waves_per_cu = w;
+            rec.policy.chunks_per_wave = 1;
+            rec.policy.min_chunk = (int32_t)kMinStepsPerWave;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc) return rc;
+    rec.best_ms = best;
+    ctx->tuned.push_back(rec);
+    ctx->last_tune = rec;
+    ctx->tune_cache_store(rec, "perm");
+    wpc = rec.policy.waves_per_cu;
+    return PQ_OK;
+}
+
 int run_single(pq_ctx* ctx, const Plan& p, const cplx* U, int64_t ldu, cplx* perm, cplx* amp,
                hipStream_t st) {
-    const SingleLayout L = single_layout(ctx, p);
+    int wpc = sweep_waves_per_cu(ctx, p);
+    if (ctx->autotune) {
+        if (const TuneRecord* t = recorded(ctx, single_sig(p))) {
+            ctx->last_tune = *t;
+            ctx->last_tune.candidates = 0;
+            wpc = t->policy.waves_per_cu;
+        } else if (int rc = tune_single(ctx, p, U, ldu, perm, amp, st, wpc)) {
+            return rc;
+        }
+    }
+    const SingleLayout L = single_layout(ctx, p, wpc);
     char* ws = (char*)ctx->workspace(L.bytes);
     if (!ws) return PQ_ENOMEM;
     return run_single_at(ctx, p, L, ws, U, ldu, perm, amp, st, true);

@@ -56,8 +56,9 @@ struct pq_ctx {
     // resident workgroups per CU per (binary, nc); 0 = not yet queried
     int occ[3][pq::kMaxDim + 1] = {};
 
-    // chunk-policy autotuning of pq_perm_many (pq_autotune_enable): tuned
-    // policies by job-list shape signature, and the last decision
+    // autotuning (pq_autotune_enable): chunk policies of pq_perm_many by
+    // job-list shape signature and pq_perm's launch shapes by plan shape
+    // signature, and the last decision
     bool autotune = false;
     // pq_perm_many replays a captured HIP graph of its launch sequence
     // (pq_graph_enable)
@@ -164,7 +165,21 @@ struct Geometry {
     int grid = 1;       // workgroups
     uint32_t waves = 1; // active wavefronts
 };
-Geometry sweep_geometry(pq_ctx* ctx, const Plan& p);
+// The sweep splits its time-state range evenly over num_cu * waves_per_cu
+// wavefronts (each at least 32 states).  The default is two rounds of the
+// resident wavefronts: the dispatcher hands the second round's workgroups to
+// the CUs that finish their first ones early, which evens out unequal CU and
+// XCD speeds that a single round leaves on the critical path.
+constexpr int kSweepRounds = 2;
+// rounds x the resident wavefronts per CU of the plan's sweep kernel
+int sweep_waves_per_cu(pq_ctx* ctx, const Plan& p, int rounds = kSweepRounds);
+Geometry sweep_geometry(pq_ctx* ctx, const Plan& p, int waves_per_cu);
+// Shape signature of a single permanent's launch (kernel kind, sums, digits
+// and powers: n and the multiplicity class), for the autotuner's records.
+uint64_t single_sig(const Plan& p);
+// pq_perm's wavefronts per CU: with autotuning on, the decision recorded for
+// the plan's shape if there is one; otherwise the default.
+int single_waves_per_cu(pq_ctx* ctx, const Plan& p);
 
 // Launch a sweep, bracketed by timing events when profiling is on.
 int timed_sweep(pq_ctx* ctx, int kind, int nc, const GlynnArgs& a, int grid, hipStream_t st);
@@ -177,14 +192,17 @@ struct SingleLayout {
     size_t oB = 0, oR = 0, oBase = 0, oTf = 0, oTb = 0, oP = 0;
     size_t bytes = 0;
 };
-SingleLayout single_layout(pq_ctx* ctx, const Plan& p);
+SingleLayout single_layout(pq_ctx* ctx, const Plan& p, int waves_per_cu);
 
 // Full single-permanent sequence (prep, table, sweep, final) on the scratch
 // `ws` laid out by `L`; `timed` brackets the sweep with profiling events.
 int run_single_at(pq_ctx* ctx, const Plan& p, const SingleLayout& L, char* ws, const cplx* U, int64_t ldu,
                   cplx* perm, cplx* amp, hipStream_t st, bool timed);
 
-// The same on the ctx workspace (grown on demand).
+// The same on the ctx workspace (grown on demand).  With autotuning on, a
+// plan shape without a recorded decision first times the whole sequence
+// under 2, 1 and 4 rounds of the resident wavefronts (best of two runs each)
+// and records the fastest.
 int run_single(pq_ctx* ctx, const Plan& p, const cplx* U, int64_t ldu, cplx* perm, cplx* amp,
                hipStream_t st);
 

@@ -25,7 +25,7 @@ def test_traffic_gate():
     t = bench.SWEEP_TRAFFIC
     want = 1024.0 * (t["fetch_kib"] * t["fetch_factor"] + t["write_kib"] * t["write_factor"])
     assert v is None or v == pytest.approx(want)
-    assert want == pytest.approx(526_664, abs=1)
+    assert want == pytest.approx(545_113, abs=1)
 
 
 def test_repeated_flops_model():

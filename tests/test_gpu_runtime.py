@@ -143,6 +143,22 @@ def test_autotune_decisions_persist_in_the_cache_file(pq, tmp_path, monkeypatch)
     assert [info2["waves_per_cu"], info2["chunks_per_wave"], info2["min_chunk"]] == \
         [info["waves_per_cu"], info["chunks_per_wave"], info["min_chunk"]]
     assert torch.equal(a, b)
+    # pq_perm's launch-shape decisions go to the same file (kind "perm")
+    Ub = dev(workloads.collision_free_block(20, 5))
+    ones = [1] * 20
+    third = pq.Engine(0)
+    p3, _ = third.perm(Ub, ones, ones)
+    info3 = third.autotune_last()
+    third.close()
+    assert info3["candidates"] == 3
+    lines = path.read_text().strip().splitlines()
+    assert len(lines) == 2 and '"kind": "perm"' in lines[1]
+    fourth = pq.Engine(0)
+    p4, _ = fourth.perm(Ub, ones, ones)
+    info4 = fourth.autotune_last()
+    fourth.close()
+    assert info4["candidates"] == 0 and info4["waves_per_cu"] == info3["waves_per_cu"]
+    assert torch.equal(p3, p4)
 
 
 def test_device_peak_matches_the_runtime_properties(pq):

@@ -167,3 +167,57 @@ def test_no_decision_reads_as_zero():
         fresh.close()
     assert (info["waves_per_cu"], info["chunks_per_wave"], info["min_chunk"]) == (0, 0, 0)
     assert info["best_ms"] == 0.0 and info["default_ms"] == 0.0 and info["candidates"] == 0
+
+
+def test_perm_launch_shape_is_tuned_per_shape(engines):
+    # pq_perm under the autotuner: 2, 1 and 4 rounds of the resident
+    # wavefronts are timed once per plan shape (n and multiplicity class);
+    # the kept shape sums the same terms in another partition
+    tuned, plain = engines
+    n = 24
+    ones = [1] * n
+    A = workloads.collision_free_block(n, 11)
+    got, _ = tuned.perm(dev(A), ones, ones)
+    info = tuned.autotune_last()
+    ref, _ = plain.perm(dev(A), ones, ones)
+    torch.cuda.synchronize()
+    assert info["candidates"] == 3 and 0 < info["best_ms"] <= info["default_ms"]
+    assert info["waves_per_cu"] > 0 and info["chunks_per_wave"] == 1 and info["min_chunk"] == 32
+    assert rel(complex(got.item()), complex(ref.item())) <= 1e-12
+    want = oracle.perm_ryser(A)
+    assert rel(complex(got.item()), want) <= 1e-8
+    # another matrix of the same shape reuses the decision
+    B = workloads.collision_free_block(n, 12)
+    got2, _ = tuned.perm(dev(B), ones, ones)
+    info2 = tuned.autotune_last()
+    torch.cuda.synchronize()
+    assert info2["candidates"] == 0 and info2["waves_per_cu"] == info["waves_per_cu"]
+    assert rel(complex(got2.item()), oracle.perm_ryser(B)) <= 1e-8
+    # a shape with repeated rows and columns gets a decision of its own
+    V = workloads.haar(8, 13)
+    S = [2, 0, 3, 1, 0, 2, 1, 1]
+    T = [1, 2, 1, 1, 2, 0, 2, 1]
+    got3, _ = tuned.perm(dev(V), S, T)
+    info3 = tuned.autotune_last()
+    torch.cuda.synchronize()
+    assert info3["candidates"] == 3
+    assert rel(complex(got3.item()), oracle.perm_mult(V, S, T)) <= 1e-10
+
+
+def test_noalloc_follows_the_recorded_launch_shape(engines):
+    # after tuning, pq_perm and pq_perm_noalloc on that ctx run the same
+    # launch shape, so they give the same bits
+    import ctypes
+    tuned, _ = engines
+    n = 22
+    ones = (ctypes.c_int32 * n)(*([1] * n))
+    U = dev(workloads.collision_free_block(n, 14))
+    a, _ = tuned.perm(U, [1] * n, [1] * n)
+    lib = tuned._lib
+    out = torch.empty(2, dtype=torch.complex128, device="cuda")
+    torch.cuda.synchronize()
+    st = lib.pq_perm_noalloc(tuned._ctx, U.data_ptr(), U.stride(0), n, ones, ones, out.data_ptr(), None,
+                             torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert st == 0
+    assert complex(out[0].item()) == complex(a.item())
