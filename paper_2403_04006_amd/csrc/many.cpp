@@ -29,6 +29,8 @@ namespace {
 // shortest walk of the reverse sweep (a multiple of its 8-state blocks): a
 // walk's set-up and closing reductions cost a few steps
 constexpr uint64_t kWalkMinChunk = 32;
+// shortest walk once a class is cut into more than one round of walks
+constexpr uint64_t kWalkSplitStates = 4096;
 // chunk policies the autotuner times (the first is the default)
 constexpr ChunkPolicy kTuneCandidates[] = {
     {64, 8, 256}, {16, 4, 64}, {4, 2, 64}, {8, 1, 64}, {8, 2, 64}, {8, 4, 64}, {16, 2, 64},
@@ -304,9 +306,16 @@ int build_many(pq_ctx* ctx, int mode, int32_t m, const std::vector<PatternSpec>&
             chunk = (total + target - 1) / target;
             if (chunk < (uint64_t)pol.min_chunk) chunk = (uint64_t)pol.min_chunk;
         } else if (C.mode == kModeAdjWalk) {
-            // one round of the resident wavefronts (every walk costs the
-            // same), in whole 8-state blocks
-            const uint64_t waves = (uint64_t)ctx->num_cu * (uint64_t)kWalkWaves * (uint64_t)walk_occupancy(ctx, C);
+            // whole rounds of the resident wavefronts (every walk costs the
+            // same), in whole 8-state blocks: one round, or up to four while
+            // every walk keeps at least kWalkSplitStates states.  Later
+            // rounds go to the CUs that finish first, which evens out unequal
+            // CU speeds; shorter walks would spend more on their set-up and
+            // closing reductions than that gains.
+            const uint64_t round = (uint64_t)ctx->num_cu * (uint64_t)kWalkWaves * (uint64_t)walk_occupancy(ctx, C);
+            uint64_t waves = total / kWalkSplitStates;
+            if (waves > 4 * round) waves = 4 * round;
+            if (waves < round) waves = round;
             chunk = (total + waves - 1) / waves;
             if (chunk < kWalkMinChunk) chunk = kWalkMinChunk;
             chunk = (chunk + 7) / 8 * 8;
