@@ -286,7 +286,7 @@ int pq_lhaf(pq_ctx* ctx, const pq_c128* A, int64_t lda, int32_t d, const pq_c128
     }
     const int occ = pack ? occupancy_haf_pack(loops, p.nl, p.rr) : occupancy_haf(loops, p.nl, p.rr);
     if (occ <= 0) return ctx->fail(PQ_EDEVICE, "pq_lhaf: occupancy query failed");
-    const uint64_t max_waves = (uint64_t)ctx->num_cu * (uint64_t)occ * kWavesPerBlock;
+    const uint64_t max_waves = (uint64_t)ctx->num_cu * (uint64_t)occ * kWavesPerBlock * kHafRounds;
     uint64_t waves = (work + kHafMinChunk - 1) / kHafMinChunk;
     if (waves > max_waves) waves = max_waves;
     if (waves < 1) waves = 1;

@@ -48,6 +48,12 @@ constexpr int kHafMaxLane = 7;     // lane digits (six of radix >= 2 and a radix
 constexpr int kHafMaxN = 64;       // vertices (photons)
 constexpr int kHafInner = 2048;    // inner (table-driven) Gray block
 constexpr uint64_t kHafMinChunk = 256;   // time states per wavefront, at least
+// A hafnian sweep splits its steps evenly over this many rounds of the
+// resident wavefronts (each at least kHafMinChunk states): later rounds go to
+// the CUs that finish first.  On 2 x 20 modes 1, 2, 4, 8 and 16 rounds took
+// 2.87, 2.78, 2.72, 2.77 and 2.82 ms (the loop hafnian 10.5, 9.7, 9.2, 9.1
+// and 9.1 ms).
+constexpr int kHafRounds = 4;
 
 // One step of the inner Gray block: entry p (p >= 1) moves time digit t by
 // dx (-2 when its digit value rises, +2 when it falls) from position p - 1 to
